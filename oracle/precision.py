@@ -1,0 +1,71 @@
+"""Rounding to reduced-precision leaf formats, for emulating reduced-precision leaves.
+
+These set tolerances for the reduced-precision paths; they are never the
+parity reference.  Each is the plain definition of round-to-nearest-even onto
+the format's grid:
+
+  bf16:  1 sign, 8 exponent, 7 fraction bits (float32 with the low 16 bits
+         cleared after rounding to nearest even on bit 16);
+  f16:   IEEE binary16 (numpy's float16 conversion is correctly rounded);
+  e4m3:  OCP FP8 E4M3FN: bias 7, 3 fraction bits, largest finite 448, no
+         infinities, subnormal spacing 2^-9; values beyond 448 saturate here.
+
+split_hi_lo(x, fmt) returns hi = rn(x), lo = rn(x - hi) (the residual computed
+in float64, which is exact for float32 x and these formats).
+
+Pins: tests compare bf16 / f16 / e4m3 rounding with torch's CPU casts
+(an independent implementation) on random and edge values.
+"""
+
+import numpy as np
+
+
+def round_bf16(x):
+    x = np.asarray(x, dtype=np.float32)
+    bits = x.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1
+    bits = (bits + 0x7FFF + lsb) & 0xFFFF0000
+    return bits.astype(np.uint32).view(np.float32)
+
+
+def round_f16(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float32)
+
+
+def round_e4m3(x, saturate=True):
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    out = np.zeros_like(a)
+    nz = a > 0
+    e = np.floor(np.log2(np.where(nz, a, 1.0)))
+    e = np.maximum(e, -6.0)              # below 2^-6 the grid is the subnormal one
+    step = 2.0 ** (e - 3)
+    q = a / step
+    r = np.floor(q)
+    frac = q - r
+    r = r + ((frac > 0.5) | ((frac == 0.5) & (np.mod(r, 2) == 1)))
+    out = np.where(nz, r * step, 0.0)
+    if saturate:
+        out = np.minimum(out, 448.0)
+    return (np.sign(x) * out).astype(np.float32)
+
+
+ROUND = {"bf16": round_bf16, "f16": round_f16, "e4m3": round_e4m3}
+
+
+def split_hi_lo(x, fmt="bf16"):
+    rn = ROUND[fmt]
+    x = np.asarray(x, dtype=np.float32)
+    hi = rn(x)
+    lo = rn((x.astype(np.float64) - hi.astype(np.float64)).astype(np.float32))
+    return hi, lo
+
+
+def pow2_scale(maxabs, target):
+    """Power of two 2^e with maxabs * 2^e <= target (e chosen as large as possible)."""
+    if maxabs == 0 or not np.isfinite(maxabs):
+        return 1.0
+    e = int(np.floor(np.log2(target / maxabs)))
+    while maxabs * 2.0 ** e > target:
+        e -= 1
+    return 2.0 ** e

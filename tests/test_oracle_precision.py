@@ -1,0 +1,41 @@
+"""Reduced-precision rounding helpers against torch's CPU casts (an independent implementation)."""
+
+import numpy as np
+import torch
+
+from oracle import precision
+
+
+def _values():
+    g = np.random.default_rng(0)
+    x = np.concatenate([g.standard_normal(20000) * 10.0 ** g.uniform(-6, 3, 20000),
+                        [0.0, 1.0, -1.0, 1.00390625, 1.0078125 + 2 ** -9, 3.1e-5, 448.0, -300.0]])
+    return x.astype(np.float32)
+
+
+def test_bf16_matches_torch():
+    x = _values()
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(precision.round_bf16(x), ref)
+
+
+def test_f16_matches_torch():
+    x = _values()
+    x = x[np.abs(x) < 60000]
+    ref = torch.from_numpy(x).to(torch.float16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(precision.round_f16(x), ref)
+
+
+def test_e4m3_matches_torch():
+    x = _values()
+    x = x[np.abs(x) <= 448]
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float32).numpy()
+    np.testing.assert_array_equal(precision.round_e4m3(x), ref)
+
+
+def test_split_hi_lo_bf16_recovers_16_bits():
+    x = _values()
+    x = x[(np.abs(x) > 1e-30) & (np.abs(x) < 1e30)]
+    hi, lo = precision.split_hi_lo(x, "bf16")
+    rel = np.abs((hi.astype(np.float64) + lo) - x) / np.abs(x)
+    assert rel.max() <= 2.0 ** -16
