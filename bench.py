@@ -1,0 +1,155 @@
+"""Benchmark: randomized Strassen F-hat^(3) on one MI355X.
+
+Workload: C = A B with N = 4096, three Strassen levels (343 leaves of
+512 x 512 x 512 on f32 MFMA, f32 accumulation), A, B i.i.d. U[-1, 1] (data
+seeds 2001/2002), algorithm seed = step index mod 16, mode "full".  One step
+is one full pass of the hot path: draws + fold for every level, gather of A
+and B, the batched leaf GEMM, and the scatter into C, with A and B resident
+in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 4096
+LEVELS = 3
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("gemm.hip",):
+        with open(os.path.join(ROOT, "paper_1905_07439_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(launch_flops_unused=None):
+    """HBM bytes per leaf-GEMM launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "leaf_gemm_f32_n4096_counters.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("kernel_source_sha256_16") != _kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A, B):
+    """The oracle (float64 NumPy recursion) on the same workload, one seed, timed on the host."""
+    import numpy as np
+    from oracle import recursion, schemes
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    S = schemes.strassen()
+    t0 = time.perf_counter()
+    recursion.rbc_seeded(A, B, [S] * LEVELS, 0)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * N ** 3 / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": "one full F-hat^(3) product, N=4096, float64 NumPy (OpenBLAS dgemm leaves), seed 0; "
+                      "%.2f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this library has no multi-GPU path (requested --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1905_07439_amd as rbc
+    import workloads
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    S = rbc.Scheme.builtin("strassen")
+    plan = rbc.Plan(N, N, N, [S] * LEVELS, prec="f32")
+    info = plan.info
+    A64 = workloads.uniform((N, N), 2001, -1, 1)
+    B64 = workloads.uniform((N, N), 2002, -1, 1)
+    A = torch.from_numpy(A64.astype(np.float32)).to(dev)
+    B = torch.from_numpy(B64.astype(np.float32)).to(dev)
+    C = torch.empty((N, N), dtype=torch.float32, device=dev)
+    ws = plan.workspace(dev)
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        plan.matmul(A, B, C=C, seed=i % 16, workspace=ws)
+    torch.cuda.synchronize()
+
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plan.matmul(A, B, C=C, seed=i % 16, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, calls = plan.timing_collect()
+    plan.set_timing(False)
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = 2.0 * N ** 3 / (ms_per_step * 1e-3) / 1e12
+
+    # accuracy of the last step's seed against the float64 standard product
+    seed = (args.steps - 1) % 16
+    plan.matmul(A, B, C=C, seed=seed, workspace=ws)
+    ref = A.double() @ B.double()
+    rel_err = float(torch.linalg.norm(C.double() - ref) / torch.linalg.norm(ref))
+
+    leaf_ms = stage_ms[2] / calls
+    leaf_flops = info["n_leaves"] * 2.0 * info["mM"] * info["mN"] * info["mK"]
+    achieved = leaf_flops / (leaf_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+                "traffic": _traffic()}
+    comb_bytes = 4.0 * (2 * (N * N + info["n_leaves"] * info["mM"] * info["mK"])
+                        + info["n_leaves"] * info["mM"] * info["mN"] + N * N)
+    comb_ms = stage_ms[0] / calls + stage_ms[1] / calls + stage_ms[3] / calls
+
+    out = {
+        "metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "randomized Strassen F-hat^(3), N=4096, 343 leaves of 512^3 on f32 MFMA, "
+                               "A,B ~ U[-1,1] (seeds 2001/2002), algorithm seeds 0..15, mode full",
+                   "n": N, "levels": LEVELS, "scheme": "strassen", "leaf": info["mM"], "prec": "f32",
+                   "parallelism": "single GPU"},
+        "rel_err_vs_fp64": rel_err,
+        "stage_ms": {"gather_A": round(stage_ms[0] / calls, 4), "gather_B": round(stage_ms[1] / calls, 4),
+                     "leaf": round(leaf_ms, 4), "scatter": round(stage_ms[3] / calls, 4)},
+        "combination_hbm_GBs": round(comb_bytes / (comb_ms * 1e-3) / 1e9, 1),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A64, B64)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * rbc.h -- C ABI of librbc: matrix multiplication by randomized (approximate)
+ * bilinear computation on AMD MI355X (gfx950).
+ *
+ * Method: Malik & Becker, "Randomization of Approximate Bilinear Computation
+ * for Matrix Multiplication".  A bilinear computation (BC) with tensors
+ * (U, V, W) computes C = A B blockwise (Section 1, eqs. bilinear-computation
+ * and bilinear-computation-block); it is randomized by signed block
+ * permutations (Definition 2, eq. f-hat-def) and applied recursively, one
+ * draw per level, with a standard product at the leaves
+ * (Section 2.1.1, eq. recursive-random-formula).  The library evaluates the
+ * folded form of eq. randomized-algorithm (proof of Proposition 10): the
+ * signs and permutations are folded into the coefficients, so randomization
+ * moves no data.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns rbc_status; no C++ exception crosses the ABI.
+ *     On error, rbc_last_error() returns a thread-local message.
+ *   - Scheme tensors are row-major doubles: U[b1][b2][R] (U[k][l][r] weights
+ *     block A_kl in product r), V[b2][b3][R], W[b1][b3][R].
+ *   - Matrices are row-major.  A is M x K with leading dimension lda >= K,
+ *     B is K x N (ldb >= N), C is M x N (ldc >= N).  A, B, C and the
+ *     workspace are DEVICE pointers owned by the caller; they must not alias.
+ *   - Element type: double for RBC_PREC_F64, float for every other precision.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued asynchronously on it; argument and plan errors
+ *     are reported synchronously; device faults surface at the next
+ *     synchronizing call as RBC_EHIP.
+ *   - Draw arrays: for a plan with Q levels, `signs` and `perms` hold, per
+ *     level from the top, b1 + b2 + b3 entries: s1[0..b1) s2[0..b2) s3[0..b3)
+ *     (+1/-1) and pi1 pi2 pi3 (0-based permutations).
+ *   - Determinism: the same (plan, inputs, draws) give bitwise identical C.
+ */
+#ifndef RBC_H
+#define RBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBC_ABI_VERSION 1
+#define RBC_MAX_LEVELS 8
+
+typedef enum {
+  RBC_OK = 0,
+  RBC_EINVAL = 1,       /* bad argument, shape or pointer */
+  RBC_ESCHEME = 2,      /* scheme residual above tolerance, or |1 - kappa| too small */
+  RBC_ENOMEM = 3,       /* workspace too small, or host allocation failed */
+  RBC_EHIP = 4,         /* a HIP runtime call failed (message in rbc_last_error) */
+  RBC_EUNSUPPORTED = 5  /* valid request this build does not implement */
+} rbc_status;
+
+/* Randomization modes (Section 3.2: fully randomized, random sign, random
+ * permutation; "none" is the deterministic F^(Q) of Section 3). */
+typedef enum {
+  RBC_MODE_FULL = 0,
+  RBC_MODE_SIGNS = 1,
+  RBC_MODE_PERMS = 2,
+  RBC_MODE_NONE = 3
+} rbc_mode;
+
+/* Leaf precision.  The block combinations (S_r, T_r, and the W-recombination)
+ * run in the element type's precision, except where noted. */
+typedef enum {
+  RBC_PREC_F64 = 0,    /* f64 everywhere; leaves on v_mfma_f64 */
+  RBC_PREC_F32 = 1,    /* f32 everywhere; leaves on v_mfma_f32 */
+  RBC_PREC_BF16X3 = 2  /* f32 combinations; leaf operands split hi+lo in bf16,
+                          3 bf16 MFMA products with f32 accumulation; the
+                          W-recombination in f64, C rounded to f32 */
+} rbc_prec;
+
+typedef struct rbc_scheme_s* rbc_scheme;
+typedef struct rbc_plan_s* rbc_plan;
+
+/* Plan geometry, see rbc_plan_get_info. */
+typedef struct {
+  int64_t M, K, N;          /* problem size */
+  int64_t Mp, Kp, Np;       /* zero-padded size (end of Section 2.1.1) */
+  int64_t mM, mK, mN;       /* leaf block: S is mM x mK, T is mK x mN */
+  int64_t n_leaves;         /* prod_d R_d */
+  int32_t levels;           /* Q */
+  int32_t n_groups;         /* fused level groups */
+  int32_t prec;             /* rbc_prec */
+  int32_t tile_m, tile_n, tile_k;  /* leaf GEMM tile */
+  size_t workspace_bytes;   /* minimum workspace for rbc_matmul */
+  size_t off_S, off_T, off_P;      /* byte offsets of the leaf operands and products */
+  size_t bytes_S, bytes_T, bytes_P;
+} rbc_plan_info;
+
+const char* rbc_status_str(rbc_status s);
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* rbc_last_error(void);
+int rbc_abi_version(void);
+
+/* ---- schemes (Section 1; Definition 1; eq. epsilon-def) ---------------- */
+
+/* Copy (U, V, W) into a new immutable scheme and validate it: the Brent
+ * residual tau = ||Y - X||_F is computed by brute force over every index
+ * 6-tuple (eq. requirement; exactly, in 64-bit integers, when every entry is
+ * an integer).  Fails with RBC_ESCHEME when tau > residual_tol or when
+ * |1 - kappa| < 1e-12 (Definition 2 needs kappa != 1).  Pass
+ * residual_tol = INFINITY to accept approximate schemes (ABCs).
+ * Limits: 1 <= b1, b2, b3 <= 4, 1 <= R <= 64. */
+rbc_status rbc_scheme_create(int b1, int b2, int b3, int R, const double* U, const double* V,
+                             const double* W, double residual_tol, rbc_scheme* out);
+/* Builtin exact schemes: "strassen" (rank 7, 2x2; Strassen 1969 in the form of
+ * Golub & Van Loan), "laderman" (rank 23, 3x3; Laderman 1976), and
+ * "naive:b1,b2,b3" (the standard algorithm as a BC, R = b1 b2 b3). */
+rbc_status rbc_scheme_builtin(const char* name, rbc_scheme* out);
+/* dims = {b1, b2, b3, R}; tau (Definition 1), kappa (eq. epsilon-def),
+ * ||Y||_F (eq. def-y), q = sqrt(sum_r ||U_r||^2 ||V_r||^2 ||W_r||^2)
+ * (eq. square-root-of-sum).  Any output pointer may be NULL. */
+rbc_status rbc_scheme_info(rbc_scheme s, int dims[4], double* tau, double* kappa, double* ynorm,
+                           double* q);
+/* Copy the tensors out (buffers sized b1*b2*R, b2*b3*R, b1*b3*R). */
+rbc_status rbc_scheme_tensors(rbc_scheme s, double* U, double* V, double* W);
+void rbc_scheme_destroy(rbc_scheme s);
+
+/* ---- draws and fold (Section 2.1; Definition 2; Prop. 10) --------------- */
+
+/* The draw of level `depth` (0 = outermost) for `seed`: Philox4x64-10 (Salmon
+ * et al. 2011) with key (seed, 0) and counters (j+1, depth, 0, 0), j = 0, 1,
+ * ...; one 64-bit word per sign (s = +1 iff the top bit is 0) for
+ * s1, s2, s3, then Fisher-Yates from the identity for pi1, pi2, pi3
+ * (i = b-1..1: j = floor(word (i+1) / 2^64), swap p[i], p[j]).  Mode SIGNS
+ * sets pi = id, PERMS sets s = 1, NONE both; all words are consumed in every
+ * mode.  signs and perms receive b1 + b2 + b3 entries each. */
+rbc_status rbc_draw(uint64_t seed, int depth, int b1, int b2, int b3, rbc_mode mode, int32_t* signs,
+                    int32_t* perms);
+/* Folded tensors of eq. randomized-algorithm for one draw:
+ *   Uh[k][l][r] = U[pi1(k)][pi2(l)][r] s1(k) s2(l)
+ *   Vh[k][l][r] = V[pi2(k)][pi3(l)][r] s2(k) s3(l)
+ *   Wh[i][j][r] = c s1(i) s3(j) W[pi1(i)][pi3(j)][r],  c = (1 - kappa)^-1 if
+ *   kappa_scale, else 1. */
+rbc_status rbc_fold(rbc_scheme s, const int32_t* signs, const int32_t* perms, int kappa_scale,
+                    double* Uh, double* Vh, double* Wh);
+
+/* ---- plans (Section 2.1.1) ----------------------------------------------- */
+
+/* Plan C = F-hat^(Q)(A, B) for an M x K by K x N product with `levels`
+ * schemes, top level first (the scheme objects may be destroyed after the
+ * call).  The leaf block sizes are the padded sizes divided by
+ * prod b1, prod b2, prod b3, rounded up to the leaf GEMM tile; A and B are
+ * zero padded virtually (never copied).  leaf_tile = 0 picks the tile
+ * automatically; otherwise it is the square tile edge (f32/bf16x3: 64 or
+ * 128; f64: 32 or 64).  levels may be 0 (plain product by the leaf kernel). */
+rbc_status rbc_plan_create(int64_t M, int64_t K, int64_t N, int levels, const rbc_scheme* schemes,
+                           rbc_prec prec, int leaf_tile, rbc_plan* out);
+rbc_status rbc_plan_get_info(rbc_plan p, rbc_plan_info* info);
+void rbc_plan_destroy(rbc_plan p);
+
+/* ---- products ------------------------------------------------------------ */
+
+/* C = F-hat^(Q)(A, B) with the draws of (seed, mode) for every level.
+ * kappa_scale: multiply by (1 - kappa)^-1 at every level (eq.
+ * recursive-random-formula); exact schemes have kappa = 0.
+ * workspace: device buffer of at least info.workspace_bytes, 256-byte
+ * aligned, used for the leaf operands and products; it must not be used by
+ * another call until this one has completed on the stream. */
+rbc_status rbc_matmul(rbc_plan p, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                      int64_t ldc, uint64_t seed, rbc_mode mode, int kappa_scale, void* workspace,
+                      size_t ws_bytes, void* stream);
+/* Same, with explicit draws (host arrays, layout above). */
+rbc_status rbc_matmul_draws(rbc_plan p, const void* A, int64_t lda, const void* B, int64_t ldb,
+                            void* C, int64_t ldc, const int32_t* signs, const int32_t* perms,
+                            int kappa_scale, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- stages of rbc_matmul, for composition and testing --------------------
+ * gather:  which = 0 forms every leaf S (from A), which = 1 every leaf T
+ *          (from B), into the workspace at info.off_S / info.off_T, as
+ *          n_leaves row-major blocks in leaf order (r_0 slowest).  For
+ *          RBC_PREC_BF16X3 the region holds the hi plane then the lo plane.
+ * leaf:    P_l = S_l T_l for every leaf l into info.off_P.
+ * scatter: C from the P blocks through the folded W of every level.
+ * The block combinations sum in a fixed order: S_r over (k, l) row-major and
+ * C_ij over ascending r, skipping zero coefficients, one rounding per
+ * multiply and per add (no fused multiply-add). */
+rbc_status rbc_stage_gather(rbc_plan p, int which, const void* X, int64_t ldx,
+                            const int32_t* signs, const int32_t* perms, void* workspace,
+                            size_t ws_bytes, void* stream);
+rbc_status rbc_stage_leaf(rbc_plan p, void* workspace, size_t ws_bytes, void* stream);
+rbc_status rbc_stage_scatter(rbc_plan p, const int32_t* signs, const int32_t* perms, int kappa_scale,
+                             void* C, int64_t ldc, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- timing ---------------------------------------------------------------
+ * With timing on, every rbc_matmul / rbc_matmul_draws records HIP events on
+ * its stream around each stage.  rbc_plan_timing_collect waits for the
+ * recorded events and returns, per stage (0 gather A, 1 gather B, 2 leaf,
+ * 3 scatter), the summed milliseconds and the number of calls, then clears
+ * them.  At most 4096 calls may be recorded between collects (RBC_ENOMEM). */
+rbc_status rbc_plan_set_timing(rbc_plan p, int on);
+rbc_status rbc_plan_timing_collect(rbc_plan p, double ms[4], int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBC_H */

@@ -1,0 +1,250 @@
+"""Randomized (approximate) bilinear matrix multiplication on AMD MI355X.
+
+C = F-hat^(Q)(A, B): recursive bilinear computation with seeded random signed
+block permutations folded into the scheme coefficients (Malik & Becker,
+Definition 2 and eq. recursive-random-formula).  Every step runs in the HIP
+library librbc.so (include/rbc.h); this module only marshals arguments and
+uses torch for device memory and streams.  There is no CPU fallback: if the
+library is not built, import of the compute entry points raises.
+
+    import paper_1905_07439_amd as rbc
+    S = rbc.Scheme.builtin("strassen")
+    plan = rbc.Plan(4096, 4096, 4096, [S, S, S], prec="f32")
+    C = plan.matmul(A, B, seed=0)           # A, B: torch tensors on the GPU
+"""
+
+import ctypes
+
+import numpy as np
+
+from ._lib import MODES, PRECS, PlanInfo, RbcError, check, lib  # noqa: F401
+
+__all__ = ["Scheme", "Plan", "draw", "fold", "RbcError", "lib"]
+
+
+def _dbl(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Scheme:
+    """An immutable, validated bilinear-computation scheme (U, V, W)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def builtin(cls, name):
+        h = ctypes.c_void_p()
+        check(lib().rbc_scheme_builtin(name.encode(), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_tensors(cls, U, V, W, residual_tol=0.0):
+        U = np.asarray(U, np.float64)
+        V = np.asarray(V, np.float64)
+        W = np.asarray(W, np.float64)
+        b1, b2, R = U.shape
+        b3 = V.shape[1]
+        if V.shape != (b2, b3, R) or W.shape != (b1, b3, R):
+            raise ValueError("tensor shapes must be (b1,b2,R), (b2,b3,R), (b1,b3,R)")
+        (u, up), (v, vp), (w, wp) = _dbl(U), _dbl(V), _dbl(W)
+        h = ctypes.c_void_p()
+        check(lib().rbc_scheme_create(b1, b2, b3, R, up, vp, wp, float(residual_tol), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def perturbed(cls, base, sigma, seed, n_zero=5):
+        """Approximate scheme of Section 3.1 built from an exact ``base``.
+
+        Independently for U, V, W: i.i.d. N(0, sigma^2) noise on every entry
+        equal to 1 and on ``n_zero`` entries equal to 0 picked without
+        replacement (numpy PCG64 stream of ``seed``; ones in row-major order
+        first, then the picked zeros).  The result is accepted whatever its
+        Brent residual.
+        """
+        g = np.random.Generator(np.random.PCG64(seed))
+        out = []
+        for T in base.tensors():
+            T = T.copy()
+            flat = T.reshape(-1)
+            ones = np.flatnonzero(flat == 1.0)
+            zeros = np.flatnonzero(flat == 0.0)
+            flat[ones] += g.normal(0.0, sigma, size=ones.size)
+            pick = g.choice(zeros.size, size=min(n_zero, zeros.size), replace=False)
+            flat[zeros[pick]] += g.normal(0.0, sigma, size=pick.size)
+            out.append(T)
+        return cls.from_tensors(*out, residual_tol=float("inf"))
+
+    def info(self):
+        dims = (ctypes.c_int * 4)()
+        vals = [ctypes.c_double() for _ in range(4)]
+        check(lib().rbc_scheme_info(self._h, dims, *[ctypes.byref(v) for v in vals]))
+        b1, b2, b3, R = list(dims)
+        tau, kappa, ynorm, q = [v.value for v in vals]
+        return {"b1": b1, "b2": b2, "b3": b3, "R": R, "tau": tau, "kappa": kappa, "ynorm": ynorm, "q": q}
+
+    def tensors(self):
+        i = self.info()
+        U = np.zeros((i["b1"], i["b2"], i["R"]))
+        V = np.zeros((i["b2"], i["b3"], i["R"]))
+        W = np.zeros((i["b1"], i["b3"], i["R"]))
+        check(lib().rbc_scheme_tensors(self._h, _dbl(U)[1], _dbl(V)[1], _dbl(W)[1]))
+        return U, V, W
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().rbc_scheme_destroy(h)
+            except Exception:
+                pass
+            self._h = ctypes.c_void_p()
+
+
+def draw(seed, depth, b1, b2, b3, mode="full"):
+    """(signs, perms) of one level: int32 arrays of b1 + b2 + b3 entries (include/rbc.h)."""
+    n = b1 + b2 + b3
+    s = np.zeros(n, np.int32)
+    p = np.zeros(n, np.int32)
+    check(lib().rbc_draw(seed & 0xFFFFFFFFFFFFFFFF, depth, b1, b2, b3, MODES[mode], _i32(s)[1], _i32(p)[1]))
+    return s, p
+
+
+def fold(scheme, signs, perms, kappa_scale=True):
+    i = scheme.info()
+    Uh = np.zeros((i["b1"], i["b2"], i["R"]))
+    Vh = np.zeros((i["b2"], i["b3"], i["R"]))
+    Wh = np.zeros((i["b1"], i["b3"], i["R"]))
+    s, sp = _i32(signs)
+    p, pp = _i32(perms)
+    check(lib().rbc_fold(scheme._h, sp, pp, int(bool(kappa_scale)), _dbl(Uh)[1], _dbl(Vh)[1], _dbl(Wh)[1]))
+    return Uh, Vh, Wh
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan for C = F-hat^(Q)(A, B) with A of size M x K and B of size K x N."""
+
+    def __init__(self, M, K, N, schemes, prec="f32", leaf_tile=0):
+        self.schemes = list(schemes)
+        arr = (ctypes.c_void_p * max(1, len(self.schemes)))(*[s._h.value for s in self.schemes])
+        h = ctypes.c_void_p()
+        check(lib().rbc_plan_create(M, K, N, len(self.schemes), arr, PRECS[prec], leaf_tile, ctypes.byref(h)))
+        self._h = h
+        self.prec = prec
+        inf = PlanInfo()
+        check(lib().rbc_plan_get_info(self._h, ctypes.byref(inf)))
+        self.info = inf.as_dict()
+        self._ws = None
+
+    @property
+    def workspace_bytes(self):
+        return self.info["workspace_bytes"]
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.prec == "f64" else torch.float32
+
+    def workspace(self, device=None):
+        import torch
+        if self._ws is None or (device is not None and self._ws.device != torch.device(device)):
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+    def _common(self, A, B, C, workspace, stream):
+        import torch
+        M, K, N = self.info["M"], self.info["K"], self.info["N"]
+        for name, X, shape in (("A", A, (M, K)), ("B", B, (K, N))):
+            if tuple(X.shape) != shape or X.dtype != self.dtype or not X.is_cuda:
+                raise ValueError("%s must be a %s CUDA tensor of shape %s" % (name, self.dtype, shape))
+            if X.stride(1) != 1:
+                raise ValueError("%s must be row-major (unit column stride)" % name)
+        if C is None:
+            C = torch.empty((M, N), dtype=self.dtype, device=A.device)
+        if tuple(C.shape) != (M, N) or C.dtype != self.dtype or C.stride(1) != 1:
+            raise ValueError("C must be a row-major %s tensor of shape %s" % (self.dtype, (M, N)))
+        ws = workspace if workspace is not None else self.workspace(A.device)
+        st = stream if stream is not None else torch.cuda.current_stream(A.device)
+        return C, ws, ctypes.c_void_p(st.cuda_stream)
+
+    def matmul(self, A, B, C=None, seed=0, mode="full", kappa_scale=None, workspace=None, stream=None):
+        """C = F-hat^(Q)(A, B) with the draws of (seed, mode), asynchronously on ``stream``."""
+        if kappa_scale is None:
+            kappa_scale = mode != "none"
+        C, ws, st = self._common(A, B, C, workspace, stream)
+        check(lib().rbc_matmul(self._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                               seed & 0xFFFFFFFFFFFFFFFF, MODES[mode], int(bool(kappa_scale)), _ptr(ws),
+                               ws.numel(), st))
+        return C
+
+    def matmul_draws(self, A, B, signs, perms, C=None, kappa_scale=True, workspace=None, stream=None):
+        C, ws, st = self._common(A, B, C, workspace, stream)
+        s, sp = _i32(signs)
+        p, pp = _i32(perms)
+        check(lib().rbc_matmul_draws(self._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C),
+                                     C.stride(0), sp, pp, int(bool(kappa_scale)), _ptr(ws), ws.numel(), st))
+        return C
+
+    def draws(self, seed, mode="full"):
+        """Concatenated per-level draws of (seed, mode), as rbc_matmul computes them."""
+        ss, ps = [], []
+        for d, sch in enumerate(self.schemes):
+            i = sch.info()
+            s, p = draw(seed, d, i["b1"], i["b2"], i["b3"], mode)
+            ss.append(s)
+            ps.append(p)
+        if not ss:
+            return np.zeros(0, np.int32), np.zeros(0, np.int32)
+        return np.concatenate(ss), np.concatenate(ps)
+
+    # ---- stages -------------------------------------------------------------
+    def stage_gather(self, which, X, signs, perms, workspace, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(X.device)
+        s, sp = _i32(signs)
+        p, pp = _i32(perms)
+        check(lib().rbc_stage_gather(self._h, which, _ptr(X), X.stride(0), sp, pp, _ptr(workspace),
+                                     workspace.numel(), ctypes.c_void_p(st.cuda_stream)))
+
+    def stage_leaf(self, workspace, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(workspace.device)
+        check(lib().rbc_stage_leaf(self._h, _ptr(workspace), workspace.numel(), ctypes.c_void_p(st.cuda_stream)))
+
+    def stage_scatter(self, signs, perms, C, workspace, kappa_scale=True, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(C.device)
+        s, sp = _i32(signs)
+        p, pp = _i32(perms)
+        check(lib().rbc_stage_scatter(self._h, sp, pp, int(bool(kappa_scale)), _ptr(C), C.stride(0),
+                                      _ptr(workspace), workspace.numel(), ctypes.c_void_p(st.cuda_stream)))
+
+    # ---- timing -------------------------------------------------------------
+    def set_timing(self, on=True):
+        check(lib().rbc_plan_set_timing(self._h, int(bool(on))))
+
+    def timing_collect(self):
+        """(ms per stage [gather A, gather B, leaf, scatter] summed, number of calls)."""
+        ms = (ctypes.c_double * 4)()
+        calls = ctypes.c_int64()
+        check(lib().rbc_plan_timing_collect(self._h, ms, ctypes.byref(calls)))
+        return list(ms), calls.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().rbc_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = ctypes.c_void_p()

@@ -1,0 +1,289 @@
+// Fused block-combination kernels: the gather (forming S_r = sum u-hat A_kl and
+// T_r = sum v-hat B_k'l') and the scatter (C_ij = sum_r w-hat P_r) of
+// eq. recursive-random-formula, several levels per pass.
+//
+// One thread owns one element position (y, x) of the bottom block and walks
+// the group's levels depth first in registers: it loads the prod(b_row b_col)
+// values of the top block that map onto (y, x), forms every level's sums in
+// the fixed order of the folded formula (eq. randomized-algorithm), and
+// writes the prod R bottom values (gather), or loads the prod R products and
+// accumulates upwards (scatter).  Every load and store of a wavefront is
+// contiguous along x, each top element is read once and each bottom element
+// written once, so the kernels move the algorithmic minimum of bytes.
+//
+// Summation order (the fl model of Section 2.2, sequential sums): S_r over
+// (k, l) in row-major order and C_ij over ascending r, skipping zero
+// coefficients; the first term is fl(c * x), then acc = fl(acc + fl(c * x)).
+// Contraction into fused multiply-adds is disabled (pragma below, and
+// -ffp-contract=off for every translation unit that instantiates these).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace rbc {
+namespace comb {
+
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Folded coefficient of block (k, l) in product r: table entry at the permuted
+// block times the two signs (eq. randomized-algorithm).
+template <typename T, int BC>
+__device__ __forceinline__ T coef(const SideLevel& L, int k, int l, int r, int R) {
+  const T* tab = static_cast<const T*>(L.tab);
+  const T c = tab[(L.pr[k] * BC + L.pc[l]) * R + r];
+  return (L.sr[k] * L.sc[l] < 0) ? -c : c;
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <typename T, int OUTF>
+struct GatherEmit {
+  void* dst;
+  int64_t dst_batch, plane, off;
+  __device__ __forceinline__ void operator()(int64_t idx, T v) const {
+    if constexpr (OUTF == OUT_SAME) {
+      static_cast<T*>(dst)[idx * dst_batch + off] = v;
+    } else {
+      // leaf operand split: hi = rn_bf16(v), lo = rn_bf16(v - hi) (v - hi is exact in f32)
+      const float f = (float)v;
+      const uint16_t hi = bf16_rne(f);
+      const uint16_t lo = bf16_rne(f - bf16_to_float(hi));
+      uint16_t* d = static_cast<uint16_t*>(dst) + idx * dst_batch + off;
+      d[0] = hi;
+      d[plane] = lo;
+    }
+  }
+};
+
+// Level T of a gather group: v holds BB^(NL-T) values of the current block,
+// block (k, l) of this level occupying the SUB consecutive values at
+// (k * BC + l) * SUB.  R > 0 is the compiled product count, R == 0 reads it
+// from the level descriptor.
+template <typename T, int NL, int BR, int BC, int R, int LT, typename Emit>
+__device__ __forceinline__ void gather_level(const T* v, const SideLevel* lev, int64_t idx,
+                                             const Emit& emit) {
+  if constexpr (LT == NL) {
+    emit(idx, v[0]);
+  } else {
+    constexpr int BB = BR * BC;
+    constexpr int SUB = ipow(BB, NL - LT - 1);
+    const SideLevel& L = lev[LT];
+    const int RR = R ? R : L.R;
+    // Unroll the product loops of the inner levels; the outermost level of a
+    // multi-level group stays a loop (code size), as does a runtime R.
+    constexpr int UNR = (R == 0 || (LT == 0 && NL >= 2)) ? 1 : R;
+#pragma unroll UNR
+    for (int r = 0; r < RR; ++r) {
+      T acc[SUB];
+#pragma unroll
+      for (int j = 0; j < SUB; ++j) acc[j] = T(0);
+      bool first = true;
+#pragma unroll
+      for (int kl = 0; kl < BB; ++kl) {
+        const T c = coef<T, BC>(L, kl / BC, kl % BC, r, RR);
+        if (c != T(0)) {
+#pragma unroll
+          for (int j = 0; j < SUB; ++j) {
+            const T t = c * v[kl * SUB + j];
+            acc[j] = first ? t : acc[j] + t;
+          }
+          first = false;
+        }
+      }
+      gather_level<T, NL, BR, BC, R, LT + 1>(acc, lev, idx * RR + r, emit);
+    }
+  }
+}
+
+template <typename T, int OUTF, int NL, int BR, int BC, int R>
+__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
+  constexpr int BB = BR * BC;
+  constexpr int NSRC = ipow(BB, NL);
+  const int64_t npos = p.rows_bot * p.cols_bot;
+  const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (pos >= npos) return;
+  const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
+  for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
+    const T* src = static_cast<const T*>(p.src) + in * p.src_batch;
+    T v[NSRC];
+#pragma unroll
+    for (int s = 0; s < NSRC; ++s) {
+      int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
+      int rem = s;
+#pragma unroll
+      for (int t = 0; t < NL; ++t) {  // least significant digit = deepest level
+        const int d = rem % BB;
+        rem /= BB;
+        row += (d / BC) * hs;
+        col += (d % BC) * ws;
+        hs *= BR;
+        ws *= BC;
+      }
+      v[s] = (row < p.src_rows && col < p.src_cols) ? src[row * p.ld_src + col] : T(0);
+    }
+    GatherEmit<T, OUTF> e{p.dst, p.dst_batch, p.plane, pos};
+    gather_level<T, NL, BR, BC, R, 0>(v, p.lev, in, e);
+  }
+}
+
+// Level LT of a scatter group: returns in `out` the BB^(NL-LT) values of the
+// block at this level for subproblem prefix idx.
+template <typename TP, typename TA, int NL, int BR, int BC, int R, int LT>
+__device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, int64_t off,
+                                              const SideLevel* lev, int64_t idx, TA* out) {
+  if constexpr (LT == NL) {
+    out[0] = (TA)src[idx * src_batch + off];
+  } else {
+    constexpr int BB = BR * BC;
+    constexpr int SUB = ipow(BB, NL - LT - 1);
+    const SideLevel& L = lev[LT];
+    const int RR = R ? R : L.R;
+    bool first[BB];
+#pragma unroll
+    for (int ij = 0; ij < BB; ++ij) first[ij] = true;
+#pragma unroll
+    for (int j = 0; j < BB * SUB; ++j) out[j] = TA(0);
+    constexpr int UNR = (R == 0 || (LT == 0 && NL >= 2)) ? 1 : R;
+#pragma unroll UNR
+    for (int r = 0; r < RR; ++r) {
+      TA sub[SUB];
+      scatter_level<TP, TA, NL, BR, BC, R, LT + 1>(src, src_batch, off, lev, idx * RR + r, sub);
+#pragma unroll
+      for (int ij = 0; ij < BB; ++ij) {
+        const TA c = coef<TA, BC>(L, ij / BC, ij % BC, r, RR);
+        if (c != TA(0)) {
+#pragma unroll
+          for (int j = 0; j < SUB; ++j) {
+            const TA t = c * sub[j];
+            out[ij * SUB + j] = first[ij] ? t : out[ij * SUB + j] + t;
+          }
+          first[ij] = false;
+        }
+      }
+    }
+  }
+}
+
+template <typename TP, typename TA, typename TO, int NL, int BR, int BC, int R>
+__global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
+  constexpr int BB = BR * BC;
+  constexpr int NOUT = ipow(BB, NL);
+  const int64_t npos = p.rows_bot * p.cols_bot;
+  const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (pos >= npos) return;
+  const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
+  const TP* src = static_cast<const TP*>(p.src);
+  for (int64_t o = blockIdx.y; o < p.n_out; o += gridDim.y) {
+    TA out[NOUT];
+    scatter_level<TP, TA, NL, BR, BC, R, 0>(src, p.src_batch, pos, p.lev, o, out);
+    TO* dst = static_cast<TO*>(p.dst) + o * p.dst_batch;
+#pragma unroll
+    for (int s = 0; s < NOUT; ++s) {
+      int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
+      int rem = s;
+#pragma unroll
+      for (int t = 0; t < NL; ++t) {
+        const int d = rem % BB;
+        rem /= BB;
+        row += (d / BC) * hs;
+        col += (d % BC) * ws;
+        hs *= BR;
+        ws *= BC;
+      }
+      if (row < p.dst_rows && col < p.dst_cols) dst[row * p.ld_dst + col] = (TO)out[s];
+    }
+  }
+}
+
+inline dim3 grid_for(int64_t npos, int64_t nbatch) {
+  const int64_t gx = (npos + 255) / 256;
+  const int64_t gy = nbatch < 65535 ? nbatch : 65535;
+  return dim3((unsigned)gx, (unsigned)gy, 1);
+}
+
+template <typename T, int OUTF, int NL, int BR, int BC, int R>
+hipError_t run_gather(const GatherParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((k_gather<T, OUTF, NL, BR, BC, R>), grid_for(p.rows_bot * p.cols_bot, p.n_in),
+                     dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <typename TP, typename TA, typename TO, int NL, int BR, int BC, int R>
+hipError_t run_scatter(const ScatterParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((k_scatter<TP, TA, TO, NL, BR, BC, R>),
+                     grid_for(p.rows_bot * p.cols_bot, p.n_out), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+// Shape dispatch.  F is a functor template taking <NL, BR, BC, R>.
+template <template <int, int, int, int> class F, typename P>
+hipError_t dispatch_shape(int nl, int br, int bc, int R, const P& p, hipStream_t s) {
+  if (nl == 0) return F<0, 1, 1, 1>::run(p, s);
+  if (nl == 3 && br == 2 && bc == 2 && R == 7) return F<3, 2, 2, 7>::run(p, s);
+  if (nl == 2 && br == 2 && bc == 2 && R == 7) return F<2, 2, 2, 7>::run(p, s);
+  if (nl == 1 && br == 2 && bc == 2 && R == 7) return F<1, 2, 2, 7>::run(p, s);
+  if (nl == 1 && br == 3 && bc == 3 && R == 23) return F<1, 3, 3, 23>::run(p, s);
+  if (nl != 1) return hipErrorInvalidValue;
+#define RBC_SHAPE(a, b) \
+  if (br == a && bc == b) return F<1, a, b, 0>::run(p, s);
+  RBC_SHAPE(1, 1) RBC_SHAPE(1, 2) RBC_SHAPE(1, 3) RBC_SHAPE(1, 4)
+  RBC_SHAPE(2, 1) RBC_SHAPE(2, 2) RBC_SHAPE(2, 3) RBC_SHAPE(2, 4)
+  RBC_SHAPE(3, 1) RBC_SHAPE(3, 2) RBC_SHAPE(3, 3) RBC_SHAPE(3, 4)
+  RBC_SHAPE(4, 1) RBC_SHAPE(4, 2) RBC_SHAPE(4, 3) RBC_SHAPE(4, 4)
+#undef RBC_SHAPE
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int OUTF>
+struct GatherOf {
+  template <int NL, int BR, int BC, int R>
+  struct F {
+    static hipError_t run(const GatherParams& p, hipStream_t s) {
+      return run_gather<T, OUTF, NL, BR, BC, R>(p, s);
+    }
+  };
+};
+
+template <typename TP, typename TA, typename TO>
+struct ScatterOf {
+  template <int NL, int BR, int BC, int R>
+  struct F {
+    static hipError_t run(const ScatterParams& p, hipStream_t s) {
+      return run_scatter<TP, TA, TO, NL, BR, BC, R>(p, s);
+    }
+  };
+};
+
+
+template <typename T, int OUTF>
+hipError_t gather_dispatch(int nl, int br, int bc, int R, const GatherParams& p, hipStream_t s) {
+  return dispatch_shape<GatherOf<T, OUTF>::template F>(nl, br, bc, R, p, s);
+}
+
+template <typename TP, typename TA, typename TO>
+hipError_t scatter_dispatch(int nl, int br, int bc, int R, const ScatterParams& p, hipStream_t s) {
+  return dispatch_shape<ScatterOf<TP, TA, TO>::template F>(nl, br, bc, R, p, s);
+}
+
+#define RBC_GATHER_COMBOS(X) \
+  X(double, OUT_SAME) X(float, OUT_SAME) X(float, OUT_BF16X2)
+#define RBC_SCATTER_COMBOS(X)                                                          \
+  X(double, double, double) X(float, float, float) X(float, double, double)            \
+  X(float, double, float) X(double, double, float)
+
+#define RBC_DECL_G(T, O) \
+  extern template hipError_t gather_dispatch<T, O>(int, int, int, int, const GatherParams&, hipStream_t);
+#define RBC_DECL_S(A, B, C)                                                                     \
+  extern template hipError_t scatter_dispatch<A, B, C>(int, int, int, int, const ScatterParams&, \
+                                                        hipStream_t);
+
+}  // namespace comb
+}  // namespace rbc

@@ -1,0 +1,8 @@
+// Instantiation of the fused gather for element type float, output OUT_SAME.
+#include "combine.hpp"
+
+namespace rbc {
+namespace comb {
+template hipError_t gather_dispatch<float, OUT_SAME>(int, int, int, int, const GatherParams&, hipStream_t);
+}  // namespace comb
+}  // namespace rbc

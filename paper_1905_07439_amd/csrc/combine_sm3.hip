@@ -1,0 +1,8 @@
+// Instantiation of the fused scatter: products double, accumulation double, output float.
+#include "combine.hpp"
+
+namespace rbc {
+namespace comb {
+template hipError_t scatter_dispatch<double, double, float>(int, int, int, int, const ScatterParams&, hipStream_t);
+}  // namespace comb
+}  // namespace rbc

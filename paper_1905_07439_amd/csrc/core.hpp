@@ -1,0 +1,117 @@
+// Host core of librbc: schemes, draws, fold and plans.  Plain C++17: no HIP
+// types appear here, so the planner and the validator build and run on any
+// host.  The device side (kernels.hpp) consumes the descriptors defined here.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rbc.h"
+
+namespace rbc {
+
+constexpr int kMaxB = 4;     // block partition per level and dimension
+constexpr int kMaxR = 64;    // products per level
+constexpr int kMaxLevels = RBC_MAX_LEVELS;
+
+// ---- errors ---------------------------------------------------------------
+rbc_status fail(rbc_status st, const char* fmt, ...);
+void clear_error();
+
+// ---- schemes (Section 1, Definition 1, eq. epsilon-def) -------------------
+struct Scheme {
+  int b1 = 0, b2 = 0, b3 = 0, R = 0;
+  std::vector<double> U, V, W;  // [b1][b2][R], [b2][b3][R], [b1][b3][R]
+  bool integral = false;        // every entry an integer (exact validation)
+  double tau = 0, kappa = 0, ynorm = 0, q = 0;
+  double kappa_total = 0;       // sum_{i,l,j} (1 - sum_r u v w); kappa = total / (b1 b2 b3)
+};
+
+// Fill tau, kappa, ynorm, q by brute force over the index 6-tuples.
+void analyse(Scheme& s);
+rbc_status make_scheme(int b1, int b2, int b3, int R, const double* U, const double* V,
+                       const double* W, double residual_tol, Scheme& out);
+rbc_status builtin_scheme(const char* name, Scheme& out);
+
+// ---- draws (Section 2.1) ----------------------------------------------------
+void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+// signs and perms receive b1 + b2 + b3 entries each.
+void draw_level(uint64_t seed, int depth, int b1, int b2, int b3, rbc_mode mode, int32_t* signs,
+                int32_t* perms);
+bool valid_draw(int b1, int b2, int b3, const int32_t* signs, const int32_t* perms);
+
+// (1 - kappa)^-1 exactly as 1.0 / (1.0 - kappa) in double.
+double kappa_factor(const Scheme& s);
+void fold(const Scheme& s, const int32_t* signs, const int32_t* perms, bool kappa_scale,
+          double* Uh, double* Vh, double* Wh);
+
+// ---- plans (Section 2.1.1) --------------------------------------------------
+// One side (A, B or C) of one level as the kernels see it: block-row and
+// block-column signs and permutations and the product count.  The folded
+// coefficient of block (k, l), product r, is
+//   tab[(pr[k] * BC + pc[l]) * R + r] * sr[k] * sc[l].
+struct SideLevel {
+  int8_t pr[kMaxB], pc[kMaxB];
+  int8_t sr[kMaxB], sc[kMaxB];
+  int32_t R;
+  int32_t pad_;
+  const void* tab;  // device table of this side (f64 or f32, see Plan)
+};
+
+// Consecutive levels that one kernel pass fuses.  All levels of a group share
+// the block shape <b1, b2, b3>.  "top" blocks enter the group from above (the
+// user's A/B/C for group 0), "bot" blocks are the group's leaves (the leaf
+// operands and products for the last group).
+struct Group {
+  int d0 = 0, d1 = 0;             // levels [d0, d1)
+  int b1 = 0, b2 = 0, b3 = 0;
+  int64_t n_in = 1;               // subproblems entering the group = prod_{d < d0} R_d
+  int64_t Rg = 1;                 // prod_{d0 <= d < d1} R_d
+  int64_t a_rows_top = 0, a_cols_top = 0, a_rows_bot = 0, a_cols_bot = 0;
+  int64_t b_rows_top = 0, b_cols_top = 0, b_rows_bot = 0, b_cols_bot = 0;
+  int64_t c_rows_top = 0, c_cols_top = 0, c_rows_bot = 0, c_cols_bot = 0;
+  // Workspace byte offsets of the bottom-side buffers: gathered A side,
+  // gathered B side, and the products the scatter of this group reads.
+  size_t off_a_bot = 0, off_b_bot = 0, off_c_bot = 0;
+};
+
+struct LevelTables {  // host copies, uploaded once per device
+  std::vector<double> U, V, W, Wk;  // Wk = (1 - kappa)^-1 * W (double product)
+  std::vector<float> Uf, Vf, Wf, Wkf;
+};
+
+struct Plan {
+  int64_t M = 0, K = 0, N = 0, Mp = 0, Kp = 0, Np = 0, mM = 0, mK = 0, mN = 0;
+  int64_t n_leaves = 1;
+  int Q = 0;
+  rbc_prec prec = RBC_PREC_F32;
+  int tile_m = 0, tile_n = 0, tile_k = 0;
+  std::vector<Scheme> levels;
+  std::vector<LevelTables> tables;
+  std::vector<Group> groups;
+  size_t ws_bytes = 0, off_S = 0, off_T = 0, off_P = 0, bytes_S = 0, bytes_T = 0, bytes_P = 0;
+  // element sizes: combination precision (gather side), recombination (scatter side)
+  int comb_bytes = 4, recomb_bytes = 4;
+
+  // device state, created on first use (see device.cpp)
+  int device = -1;
+  void* dev_tables = nullptr;  // one allocation holding every level's tables
+  std::vector<size_t> tab_off;   // per level: offsets of U, V, W, Wk (double) then Uf, Vf, Wf, Wkf
+  // timing
+  bool timing = false;
+  std::vector<void*> events;     // hipEvent_t, 5 per recorded call
+  int64_t recorded = 0;
+};
+
+// Is a fused group of `nl` levels of shape <b1,b2,b3> with R products compiled?
+bool fused_supported(int b1, int b2, int b3, int R, int nl);
+
+rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>& levels,
+                     rbc_prec prec, int leaf_tile, Plan& out);
+
+// Table index helpers into Plan::tab_off (per level, 8 entries).
+enum TabKind { TAB_U = 0, TAB_V = 1, TAB_W = 2, TAB_WK = 3 };
+
+}  // namespace rbc

@@ -1,0 +1,65 @@
+// Kernel parameter blocks and launchers shared by the HIP translation units
+// and the C ABI.  Parameters travel by value as kernel arguments, so a launch
+// copies nothing to the device besides them.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "core.hpp"
+
+namespace rbc {
+
+constexpr int kMaxGroupLevels = 3;
+
+// Output formats of a gather.
+enum GatherOut { OUT_SAME = 0, OUT_BF16X2 = 1 };
+
+// Gather of one group: every top block (n_in of them) becomes Rg bottom blocks,
+// S = sum over (k, l) of the folded coefficient times block (k, l), level by
+// level inside the group.  Element types: double (f64) or float.
+struct GatherParams {
+  const void* src;
+  int64_t ld_src;      // row stride of a top block
+  int64_t src_batch;   // elements between consecutive top blocks (0: a single user matrix)
+  int64_t src_rows, src_cols;  // readable part of a top block; zero beyond (virtual padding)
+  void* dst;
+  int64_t rows_bot, cols_bot;  // bottom block size
+  int64_t dst_batch;   // elements between consecutive bottom blocks
+  int64_t plane;       // bf16x2 output: elements between the hi and lo planes
+  int64_t n_in;
+  SideLevel lev[kMaxGroupLevels];
+};
+
+// Scatter of one group: Rg bottom blocks per top block are combined through W.
+struct ScatterParams {
+  const void* src;
+  int64_t src_batch;   // elements between consecutive bottom blocks (= rows_bot * cols_bot)
+  void* dst;
+  int64_t ld_dst;
+  int64_t dst_batch;   // elements between consecutive top blocks (0: the user's C)
+  int64_t dst_rows, dst_cols;  // writable part of a top block (crop)
+  int64_t rows_bot, cols_bot;
+  int64_t n_out;
+  SideLevel lev[kMaxGroupLevels];
+};
+
+// Element-type codes for launchers.
+enum Elt { ELT_F32 = 0, ELT_F64 = 1 };
+
+hipError_t launch_gather(Elt elt, GatherOut out, int nl, int br, int bc, int R,
+                         const GatherParams& p, hipStream_t stream);
+// tp: product element type, ta: accumulation type, to: output element type
+hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int nl, int br, int bc, int R,
+                          const ScatterParams& p, hipStream_t stream);
+
+// Batched leaf products P_l = S_l T_l, l < batch; S: m x k, T: k x n, P: m x n,
+// each row-major and contiguous, consecutive leaves back to back.
+hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, int64_t n, int64_t k,
+                           int64_t batch, int tile, hipStream_t stream);
+hipError_t launch_gemm_f64(const double* S, const double* T, double* P, int64_t m, int64_t n,
+                           int64_t k, int64_t batch, hipStream_t stream);
+// bf16x3: S and T hold hi planes followed (plane elements later) by lo planes.
+hipError_t launch_gemm_bf16x3(const uint16_t* S, const uint16_t* T, float* P, int64_t m, int64_t n,
+                              int64_t k, int64_t batch, int tile, hipStream_t stream);
+
+}  // namespace rbc

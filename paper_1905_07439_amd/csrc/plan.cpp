@@ -1,0 +1,159 @@
+// Planner: leaf sizes, zero padding, fused level groups and the workspace
+// layout of F-hat^(Q) (Section 2.1.1, eq. recursive-random-formula).
+//
+// The recursion is evaluated breadth-first over fused groups of levels: the
+// gather of a group turns every block entering it into the prod R_d blocks of
+// its deepest level in one kernel pass, the leaf kernel multiplies all
+// prod_d R_d leaf pairs in one batched launch, and the scatter of a group
+// folds its products back through W.  Padding (end of Section 2.1.1) is
+// virtual: reads outside A or B return zero, writes outside C are dropped.
+#include <algorithm>
+#include <cstring>
+
+#include "core.hpp"
+
+namespace rbc {
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Fused group shapes the block-combination kernels are compiled for: one
+// level of any shape, or two or three Strassen-shaped levels (2x2x2, R = 7).
+// A thread holds prod (b_row b_col) source values of the group, at most 64.
+bool fused_supported(int b1, int b2, int b3, int R, int nl) {
+  if (nl <= 1) return true;
+  const bool strassen_shape = b1 == 2 && b2 == 2 && b3 == 2 && R == 7;
+  return (nl == 2 || nl == 3) && strassen_shape;
+}
+
+static bool can_extend(const Group& g, const Scheme& s, int R0) {
+  if (s.b1 != g.b1 || s.b2 != g.b2 || s.b3 != g.b3 || s.R != R0) return false;
+  return fused_supported(s.b1, s.b2, s.b3, s.R, g.d1 - g.d0 + 1);
+}
+
+rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>& levels,
+                     rbc_prec prec, int leaf_tile, Plan& out) {
+  if (M < 1 || K < 1 || N < 1) return fail(RBC_EINVAL, "empty product %lldx%lldx%lld", (long long)M,
+                                          (long long)K, (long long)N);
+  if ((int)levels.size() > kMaxLevels) return fail(RBC_EINVAL, "at most %d levels", kMaxLevels);
+  if (prec != RBC_PREC_F64 && prec != RBC_PREC_F32 && prec != RBC_PREC_BF16X3)
+    return fail(RBC_EUNSUPPORTED, "precision %d not implemented", (int)prec);
+  Plan p;
+  p.M = M, p.K = K, p.N = N;
+  p.Q = (int)levels.size();
+  p.prec = prec;
+  p.levels = levels;
+
+  int64_t P1 = 1, P2 = 1, P3 = 1;
+  p.n_leaves = 1;
+  for (const Scheme& s : levels) {
+    P1 *= s.b1, P2 *= s.b2, P3 *= s.b3;
+    p.n_leaves *= s.R;
+  }
+  const int64_t lm = ceil_div(M, P1), lk = ceil_div(K, P2), ln = ceil_div(N, P3);
+
+  // Leaf GEMM tile.
+  if (prec == RBC_PREC_F64) {
+    if (leaf_tile == 0) leaf_tile = 16;
+    if (leaf_tile != 16) return fail(RBC_EUNSUPPORTED, "f64 leaf tile must be 16");
+    p.tile_m = p.tile_n = 16, p.tile_k = 4;
+  } else {
+    if (leaf_tile == 0) {
+      // 128 unless it pads the leaf by more than 1/8
+      const bool big = round_up(lm, 128) * 8 <= lm * 9 && round_up(ln, 128) * 8 <= ln * 9;
+      leaf_tile = big ? 128 : 64;
+    }
+    if (leaf_tile != 64 && leaf_tile != 128)
+      return fail(RBC_EUNSUPPORTED, "f32/bf16x3 leaf tile must be 64 or 128");
+    p.tile_m = p.tile_n = leaf_tile;
+    p.tile_k = prec == RBC_PREC_BF16X3 ? 32 : 16;
+  }
+  p.mM = round_up(lm, p.tile_m);
+  p.mK = round_up(lk, p.tile_k);
+  p.mN = round_up(ln, p.tile_n);
+  p.Mp = p.mM * P1, p.Kp = p.mK * P2, p.Np = p.mN * P3;
+
+  p.comb_bytes = prec == RBC_PREC_F64 ? 8 : 4;
+  p.recomb_bytes = prec == RBC_PREC_F32 ? 4 : 8;
+  const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : 4;  // bf16x3: hi + lo planes of 2 bytes
+  const int prod_bytes = prec == RBC_PREC_F64 ? 8 : 4;
+
+  // Fused groups.
+  for (int d = 0; d < p.Q; ++d) {
+    const Scheme& s = levels[d];
+    if (!p.groups.empty() && can_extend(p.groups.back(), s, levels[p.groups.back().d0].R)) {
+      p.groups.back().d1 = d + 1;
+      continue;
+    }
+    Group g;
+    g.d0 = d, g.d1 = d + 1;
+    g.b1 = s.b1, g.b2 = s.b2, g.b3 = s.b3;
+    p.groups.push_back(g);
+  }
+  if (p.Q == 0) {  // plain product: one empty group copies A, B in and C out
+    Group g;
+    g.b1 = g.b2 = g.b3 = 1;
+    p.groups.push_back(g);
+  }
+
+  // Dimensions per group.
+  int64_t n_in = 1;
+  for (Group& g : p.groups) {
+    int64_t q1 = 1, q2 = 1, q3 = 1, below1 = 1, below2 = 1, below3 = 1;
+    for (int d = g.d0; d < g.d1; ++d) q1 *= levels[d].b1, q2 *= levels[d].b2, q3 *= levels[d].b3;
+    for (int d = g.d1; d < p.Q; ++d)
+      below1 *= levels[d].b1, below2 *= levels[d].b2, below3 *= levels[d].b3;
+    g.n_in = n_in;
+    g.Rg = 1;
+    for (int d = g.d0; d < g.d1; ++d) g.Rg *= levels[d].R;
+    g.a_rows_bot = p.mM * below1, g.a_cols_bot = p.mK * below2;
+    g.b_rows_bot = p.mK * below2, g.b_cols_bot = p.mN * below3;
+    g.c_rows_bot = p.mM * below1, g.c_cols_bot = p.mN * below3;
+    g.a_rows_top = g.a_rows_bot * q1, g.a_cols_top = g.a_cols_bot * q2;
+    g.b_rows_top = g.b_rows_bot * q2, g.b_cols_top = g.b_cols_bot * q3;
+    g.c_rows_top = g.c_rows_bot * q1, g.c_cols_top = g.c_cols_bot * q3;
+    n_in *= g.Rg;
+  }
+
+  // Workspace: leaf operands, products, then the group-boundary buffers.
+  size_t off = 0;
+  p.bytes_S = (size_t)p.n_leaves * p.mM * p.mK * leaf_op_bytes;
+  p.bytes_T = (size_t)p.n_leaves * p.mK * p.mN * leaf_op_bytes;
+  p.bytes_P = (size_t)p.n_leaves * p.mM * p.mN * prod_bytes;
+  p.off_S = off, off = align256(off + p.bytes_S);
+  p.off_T = off, off = align256(off + p.bytes_T);
+  p.off_P = off, off = align256(off + p.bytes_P);
+  for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+    Group& g = p.groups[gi];
+    if (gi + 1 == p.groups.size()) {
+      g.off_a_bot = p.off_S, g.off_b_bot = p.off_T, g.off_c_bot = p.off_P;
+      continue;
+    }
+    const size_t nb = (size_t)g.n_in * g.Rg;
+    g.off_a_bot = off, off = align256(off + nb * g.a_rows_bot * g.a_cols_bot * p.comb_bytes);
+    g.off_b_bot = off, off = align256(off + nb * g.b_rows_bot * g.b_cols_bot * p.comb_bytes);
+    g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * p.recomb_bytes);
+  }
+  p.ws_bytes = std::max<size_t>(off, 256);
+
+  // Host tables per level: U, V, W and (1 - kappa)^-1 W, in f64 and f32.
+  for (const Scheme& s : levels) {
+    LevelTables t;
+    t.U = s.U, t.V = s.V, t.W = s.W;
+    const double c = kappa_factor(s);
+    t.Wk.resize(s.W.size());
+    for (size_t i = 0; i < s.W.size(); ++i) t.Wk[i] = c * s.W[i];
+    auto to_f = [](const std::vector<double>& v) {
+      std::vector<float> f(v.size());
+      for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+      return f;
+    };
+    t.Uf = to_f(t.U), t.Vf = to_f(t.V), t.Wf = to_f(t.W), t.Wkf = to_f(t.Wk);
+    p.tables.push_back(std::move(t));
+  }
+  out = std::move(p);
+  return RBC_OK;
+}
+
+}  // namespace rbc

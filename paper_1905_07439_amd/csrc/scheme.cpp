@@ -1,0 +1,209 @@
+// Schemes: storage, validation by the Brent equations, builtin exact schemes.
+//
+// Brent equations (Section 1, eq. requirement): sum_r u_klr v_k'l'r w_ijr =
+// delta(k,i) delta(l',j) delta(l,k') for every index 6-tuple.  tau is the
+// Frobenius norm of the residual Y - X (Definition 1, eqs. def-x, def-y),
+// kappa the mean defect on the n^3 entries where X = 1 (eq. epsilon-def;
+// divided by b1 b2 b3 for rectangular blocks).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "core.hpp"
+
+namespace rbc {
+
+static thread_local std::string g_last_error;
+
+rbc_status fail(rbc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+const char* last_error_text() { return g_last_error.c_str(); }
+
+static bool is_integer(double x) { return std::isfinite(x) && std::floor(x) == x && std::fabs(x) < 1e15; }
+
+void analyse(Scheme& s) {
+  const int b1 = s.b1, b2 = s.b2, b3 = s.b3, R = s.R;
+  auto U = [&](int k, int l, int r) { return s.U[(k * b2 + l) * R + r]; };
+  auto V = [&](int k, int l, int r) { return s.V[(k * b3 + l) * R + r]; };
+  auto W = [&](int i, int j, int r) { return s.W[(i * b3 + j) * R + r]; };
+  s.integral = true;
+  for (double x : s.U) s.integral &= is_integer(x);
+  for (double x : s.V) s.integral &= is_integer(x);
+  for (double x : s.W) s.integral &= is_integer(x);
+
+  // Brute force over [b1] x [b2] x [b2] x [b3] x [b1] x [b3].
+  long double res2 = 0, y2 = 0;
+  int64_t ires2 = 0, iy2 = 0;
+  for (int k = 0; k < b1; ++k)
+    for (int l = 0; l < b2; ++l)
+      for (int kp = 0; kp < b2; ++kp)
+        for (int lp = 0; lp < b3; ++lp)
+          for (int i = 0; i < b1; ++i)
+            for (int j = 0; j < b3; ++j) {
+              const int x = (k == i && lp == j && l == kp) ? 1 : 0;
+              if (s.integral) {
+                int64_t y = 0;
+                for (int r = 0; r < R; ++r)
+                  y += (int64_t)U(k, l, r) * (int64_t)V(kp, lp, r) * (int64_t)W(i, j, r);
+                ires2 += (y - x) * (y - x);
+                iy2 += y * y;
+              } else {
+                long double y = 0;
+                for (int r = 0; r < R; ++r) y += (long double)U(k, l, r) * V(kp, lp, r) * W(i, j, r);
+                res2 += (y - x) * (y - x);
+                y2 += y * y;
+              }
+            }
+  if (s.integral) {
+    s.tau = std::sqrt((double)ires2);
+    s.ynorm = std::sqrt((double)iy2);
+  } else {
+    s.tau = (double)std::sqrt(res2);
+    s.ynorm = (double)std::sqrt(y2);
+  }
+
+  // kappa: defect summed over the (i, l, j) triples where X = 1.
+  double total = 0;
+  for (int i = 0; i < b1; ++i)
+    for (int l = 0; l < b2; ++l)
+      for (int j = 0; j < b3; ++j) {
+        double y = 0;
+        for (int r = 0; r < R; ++r) y += U(i, l, r) * V(l, j, r) * W(i, j, r);
+        total += 1.0 - y;
+      }
+  s.kappa_total = total;
+  s.kappa = total / (double)(b1 * b2 * b3);
+
+  // q = sqrt(sum_r ||U_r||^2 ||V_r||^2 ||W_r||^2) (eq. square-root-of-sum)
+  double q2 = 0;
+  for (int r = 0; r < R; ++r) {
+    double nu = 0, nv = 0, nw = 0;
+    for (int k = 0; k < b1; ++k)
+      for (int l = 0; l < b2; ++l) nu += U(k, l, r) * U(k, l, r);
+    for (int k = 0; k < b2; ++k)
+      for (int l = 0; l < b3; ++l) nv += V(k, l, r) * V(k, l, r);
+    for (int i = 0; i < b1; ++i)
+      for (int j = 0; j < b3; ++j) nw += W(i, j, r) * W(i, j, r);
+    q2 += nu * nv * nw;
+  }
+  s.q = std::sqrt(q2);
+}
+
+rbc_status make_scheme(int b1, int b2, int b3, int R, const double* U, const double* V,
+                       const double* W, double residual_tol, Scheme& out) {
+  if (b1 < 1 || b2 < 1 || b3 < 1 || b1 > kMaxB || b2 > kMaxB || b3 > kMaxB)
+    return fail(RBC_EINVAL, "block partition <%d,%d,%d> outside 1..%d", b1, b2, b3, kMaxB);
+  if (R < 1 || R > kMaxR) return fail(RBC_EINVAL, "R = %d outside 1..%d", R, kMaxR);
+  if (!U || !V || !W) return fail(RBC_EINVAL, "null tensor pointer");
+  Scheme s;
+  s.b1 = b1, s.b2 = b2, s.b3 = b3, s.R = R;
+  s.U.assign(U, U + b1 * b2 * R);
+  s.V.assign(V, V + b2 * b3 * R);
+  s.W.assign(W, W + b1 * b3 * R);
+  for (double x : s.U) if (!std::isfinite(x)) return fail(RBC_EINVAL, "non-finite entry in U");
+  for (double x : s.V) if (!std::isfinite(x)) return fail(RBC_EINVAL, "non-finite entry in V");
+  for (double x : s.W) if (!std::isfinite(x)) return fail(RBC_EINVAL, "non-finite entry in W");
+  analyse(s);
+  if (!(s.tau <= residual_tol))
+    return fail(RBC_ESCHEME, "Brent residual tau = %.6g exceeds tolerance %.6g", s.tau, residual_tol);
+  if (std::fabs(1.0 - s.kappa) < 1e-12)
+    return fail(RBC_ESCHEME, "kappa = %.17g: (1 - kappa)^-1 undefined", s.kappa);
+  out = std::move(s);
+  return RBC_OK;
+}
+
+// Strassen (1969), in the form of Golub & Van Loan:
+//   P1 = (A11+A22)(B11+B22), P2 = (A21+A22)B11, P3 = A11(B12-B22), P4 = A22(B21-B11),
+//   P5 = (A11+A12)B22, P6 = (A21-A11)(B11+B12), P7 = (A12-A22)(B21+B22);
+//   C11 = P1+P4-P5+P7, C12 = P3+P5, C21 = P2+P4, C22 = P1-P2+P3+P6.
+// Each row lists, per product, the coefficients of blocks 11, 12, 21, 22.
+static const int kStrassenA[7][4] = {{1, 0, 0, 1}, {0, 0, 1, 1}, {1, 0, 0, 0}, {0, 0, 0, 1},
+                                     {1, 1, 0, 0}, {-1, 0, 1, 0}, {0, 1, 0, -1}};
+static const int kStrassenB[7][4] = {{1, 0, 0, 1}, {1, 0, 0, 0}, {0, 1, 0, -1}, {-1, 0, 1, 0},
+                                     {0, 0, 0, 1}, {1, 1, 0, 0}, {0, 0, 1, 1}};
+static const int kStrassenC[7][4] = {{1, 0, 0, 1}, {0, 0, 1, -1}, {0, 1, 0, 1}, {1, 0, 1, 0},
+                                     {-1, 1, 0, 0}, {0, 0, 0, 1}, {1, 0, 0, 0}};
+
+// Laderman (1976), rank 23 for 3x3 blocks.  Per product, the coefficients of
+// blocks 11 12 13 21 22 23 31 32 33 of A and of B; then, per output block,
+// the products summed with coefficient +1.
+static const int kLadermanA[23][9] = {
+    {1, 1, 1, -1, -1, 0, 0, -1, -1}, {1, 0, 0, -1, 0, 0, 0, 0, 0},  {0, 0, 0, 0, 1, 0, 0, 0, 0},
+    {-1, 0, 0, 1, 1, 0, 0, 0, 0},    {0, 0, 0, 1, 1, 0, 0, 0, 0},   {1, 0, 0, 0, 0, 0, 0, 0, 0},
+    {-1, 0, 0, 0, 0, 0, 1, 1, 0},    {-1, 0, 0, 0, 0, 0, 1, 0, 0},  {0, 0, 0, 0, 0, 0, 1, 1, 0},
+    {1, 1, 1, 0, -1, -1, -1, -1, 0}, {0, 0, 0, 0, 0, 0, 0, 1, 0},   {0, 0, -1, 0, 0, 0, 0, 1, 1},
+    {0, 0, 1, 0, 0, 0, 0, 0, -1},    {0, 0, 1, 0, 0, 0, 0, 0, 0},   {0, 0, 0, 0, 0, 0, 0, 1, 1},
+    {0, 0, -1, 0, 1, 1, 0, 0, 0},    {0, 0, 1, 0, 0, -1, 0, 0, 0},  {0, 0, 0, 0, 1, 1, 0, 0, 0},
+    {0, 1, 0, 0, 0, 0, 0, 0, 0},     {0, 0, 0, 0, 0, 1, 0, 0, 0},   {0, 0, 0, 1, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 1, 0, 0},     {0, 0, 0, 0, 0, 0, 0, 0, 1}};
+static const int kLadermanB[23][9] = {
+    {0, 0, 0, 0, 1, 0, 0, 0, 0},      {0, -1, 0, 0, 1, 0, 0, 0, 0}, {-1, 1, 0, 1, -1, -1, -1, 0, 1},
+    {1, -1, 0, 0, 1, 0, 0, 0, 0},     {-1, 1, 0, 0, 0, 0, 0, 0, 0}, {1, 0, 0, 0, 0, 0, 0, 0, 0},
+    {1, 0, -1, 0, 0, 1, 0, 0, 0},     {0, 0, 1, 0, 0, -1, 0, 0, 0}, {-1, 0, 1, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, 0, 0, 0},      {-1, 0, 1, 1, -1, -1, -1, 1, 0}, {0, 0, 0, 0, 1, 0, 1, -1, 0},
+    {0, 0, 0, 0, 1, 0, 0, -1, 0},     {0, 0, 0, 0, 0, 0, 1, 0, 0},  {0, 0, 0, 0, 0, 0, -1, 1, 0},
+    {0, 0, 0, 0, 0, 1, 1, 0, -1},     {0, 0, 0, 0, 0, 1, 0, 0, -1}, {0, 0, 0, 0, 0, 0, -1, 0, 1},
+    {0, 0, 0, 1, 0, 0, 0, 0, 0},      {0, 0, 0, 0, 0, 0, 0, 1, 0},  {0, 0, 1, 0, 0, 0, 0, 0, 0},
+    {0, 1, 0, 0, 0, 0, 0, 0, 0},      {0, 0, 0, 0, 0, 0, 0, 0, 1}};
+static const int kLadermanC[9][8] = {  // product numbers (1-based), 0 terminates
+    {6, 14, 19, 0},          {1, 4, 5, 6, 12, 14, 15, 0}, {6, 7, 9, 10, 14, 16, 18, 0},
+    {2, 3, 4, 6, 14, 16, 17, 0}, {2, 4, 5, 6, 20, 0},     {14, 16, 17, 18, 21, 0},
+    {6, 7, 8, 11, 12, 13, 14, 0}, {12, 13, 14, 15, 22, 0}, {6, 7, 8, 9, 23, 0}};
+
+rbc_status builtin_scheme(const char* name, Scheme& out) {
+  if (!name) return fail(RBC_EINVAL, "null scheme name");
+  std::vector<double> U, V, W;
+  int b1, b2, b3, R;
+  if (!std::strcmp(name, "strassen")) {
+    b1 = b2 = b3 = 2, R = 7;
+    U.assign(4 * R, 0), V.assign(4 * R, 0), W.assign(4 * R, 0);
+    for (int r = 0; r < R; ++r)
+      for (int e = 0; e < 4; ++e) {
+        U[e * R + r] = kStrassenA[r][e];
+        V[e * R + r] = kStrassenB[r][e];
+        W[e * R + r] = kStrassenC[r][e];
+      }
+  } else if (!std::strcmp(name, "laderman")) {
+    b1 = b2 = b3 = 3, R = 23;
+    U.assign(9 * R, 0), V.assign(9 * R, 0), W.assign(9 * R, 0);
+    for (int r = 0; r < R; ++r)
+      for (int e = 0; e < 9; ++e) {
+        U[e * R + r] = kLadermanA[r][e];
+        V[e * R + r] = kLadermanB[r][e];
+      }
+    for (int e = 0; e < 9; ++e)
+      for (int t = 0; kLadermanC[e][t]; ++t) W[e * R + kLadermanC[e][t] - 1] = 1;
+  } else if (!std::strncmp(name, "naive:", 6)) {
+    if (std::sscanf(name + 6, "%d,%d,%d", &b1, &b2, &b3) != 3)
+      return fail(RBC_EINVAL, "expected naive:b1,b2,b3, got '%s'", name);
+    if (b1 < 1 || b2 < 1 || b3 < 1 || b1 > kMaxB || b2 > kMaxB || b3 > kMaxB || b1 * b2 * b3 > kMaxR)
+      return fail(RBC_EINVAL, "naive scheme <%d,%d,%d> out of range", b1, b2, b3);
+    R = b1 * b2 * b3;
+    U.assign(b1 * b2 * R, 0), V.assign(b2 * b3 * R, 0), W.assign(b1 * b3 * R, 0);
+    for (int i = 0; i < b1; ++i)
+      for (int l = 0; l < b2; ++l)
+        for (int j = 0; j < b3; ++j) {
+          const int r = (i * b2 + l) * b3 + j;
+          U[(i * b2 + l) * R + r] = 1;
+          V[(l * b3 + j) * R + r] = 1;
+          W[(i * b3 + j) * R + r] = 1;
+        }
+  } else {
+    return fail(RBC_EINVAL, "unknown builtin scheme '%s'", name);
+  }
+  return make_scheme(b1, b2, b3, R, U.data(), V.data(), W.data(), 0.0, out);
+}
+
+}  // namespace rbc

@@ -1,0 +1,308 @@
+"""GPU parity of the HIP path against the oracle (run on an MI355X).
+
+Stages: the gathers and the scatter are compared with the oracle's recursion
+element by element and must be bit-identical (same folded coefficients, same
+summation order, one rounding per operation).  The leaf products are compared
+with a float64 matmul within the format's rounding.  End to end: exact schemes
+on small integers are exact (every intermediate stays below 2^24 here), and
+real inputs are held to the tolerances written in each test.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1905_07439_amd as rbc
+import workloads
+from oracle import precision, recursion, schemes as osch, tensors as oten
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+BASE = {"strassen": osch.strassen, "laderman": osch.laderman}
+
+
+def _schemes(names):
+    """(library schemes, oracle tensors) for a list of names ("strassen", "laderman",
+    "naive:b1,b2,b3", "pert:<sigma>:<seed>")."""
+    lib, ref = [], []
+    for n in names:
+        if n.startswith("naive:"):
+            b = tuple(int(x) for x in n[6:].split(","))
+            lib.append(rbc.Scheme.builtin(n))
+            ref.append(osch.naive(*b))
+        elif n.startswith("pert:"):
+            _, sigma, seed = n.split(":")
+            base = osch.strassen()
+            lib.append(rbc.Scheme.perturbed(rbc.Scheme.builtin("strassen"), float(sigma), int(seed)))
+            ref.append(osch.perturbed(*base, float(sigma), np.random.default_rng(int(seed))))
+        else:
+            lib.append(rbc.Scheme.builtin(n))
+            ref.append(BASE[n]())
+    return lib, ref
+
+
+def _level_draws(plan, ref, seed, mode):
+    s, p = plan.draws(seed, mode)
+    out, o = [], 0
+    for U, V, W in ref:
+        b1, b2, b3, _ = oten.dims(U, V, W)
+        n = b1 + b2 + b3
+        ss, pp = s[o:o + n], p[o:o + n]
+        out.append((ss[:b1], ss[b1:b1 + b2], ss[b1 + b2:], pp[:b1], pp[b1:b1 + b2], pp[b1 + b2:]))
+        o += n
+    return s, p, out
+
+
+def _region(ws, off, nbytes, dtype, shape):
+    return ws[off:off + nbytes].view(dtype).reshape(shape).cpu().numpy()
+
+
+GATHER_CASES = [
+    # (schemes, M, K, N, prec, tile)
+    (["strassen"], 64, 64, 64, "f32", 64),
+    (["strassen", "strassen"], 130, 70, 90, "f32", 64),
+    (["strassen"] * 3, 512, 256, 512, "f32", 64),
+    (["laderman"], 200, 150, 100, "f32", 64),
+    (["laderman", "strassen"], 300, 200, 260, "f32", 64),
+    (["naive:2,3,2", "strassen"], 100, 130, 70, "f32", 64),
+    (["strassen"] * 4, 512, 512, 512, "f32", 64),
+    (["pert:1e-2:5", "pert:1e-3:6"], 150, 150, 150, "f32", 64),
+    (["strassen", "strassen"], 64, 64, 64, "f64", 16),
+    (["laderman", "pert:1e-2:1"], 90, 60, 120, "f64", 16),
+    ([], 100, 60, 50, "f32", 64),
+]
+
+
+@pytest.mark.parametrize("case", range(len(GATHER_CASES)))
+@pytest.mark.parametrize("mode", ["full", "none"])
+def test_gather_and_scatter_bit_exact(case, mode):
+    names, M, K, N, prec, tile = GATHER_CASES[case]
+    _say("gather/scatter case", names, M, K, N, prec, mode)
+    lib_s, ref_s = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec=prec, leaf_tile=tile)
+    info = plan.info
+    arith = "f64" if prec == "f64" else "f32"
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    ndt = np.float64 if prec == "f64" else np.float32
+    A = workloads.gaussian((M, K), 10 + case).astype(ndt)
+    B = workloads.gaussian((K, N), 20 + case).astype(ndt)
+    seed = 1000 + case
+    s, p, dr = _level_draws(plan, ref_s, seed, mode)
+    ws = torch.zeros(info["workspace_bytes"], dtype=torch.uint8, device=DEV)
+    Ad = torch.from_numpy(A).to(DEV)
+    Bd = torch.from_numpy(B).to(DEV)
+    plan.stage_gather(0, Ad, s, p, ws)
+    plan.stage_gather(1, Bd, s, p, ws)
+    torch.cuda.synchronize()
+    L, mM, mK, mN = info["n_leaves"], info["mM"], info["mK"], info["mN"]
+    Sg = _region(ws, info["off_S"], info["bytes_S"], tdt, (L, mM, mK))
+    Tg = _region(ws, info["off_T"], info["bytes_T"], tdt, (L, mK, mN))
+    ops = recursion.leaf_operands(A, B, ref_s, dr, kappa_scale=(mode != "none"), arith=arith,
+                                  leaf_dims=(mM, mK, mN))
+    assert len(ops) == L
+    for l, (S, T) in enumerate(ops):
+        np.testing.assert_array_equal(Sg[l], S, err_msg="S leaf %d" % l)
+        np.testing.assert_array_equal(Tg[l], T, err_msg="T leaf %d" % l)
+    # scatter of random products
+    g = np.random.default_rng(case)
+    P = g.standard_normal((L, mM, mN)).astype(ndt)
+    ws[info["off_P"]:info["off_P"] + info["bytes_P"]].copy_(torch.from_numpy(P.view(np.uint8).reshape(-1)))
+    for ks in (True, False):
+        C = torch.full((M, N), float("nan"), dtype=tdt, device=DEV)
+        plan.stage_scatter(s, p, C, ws, kappa_scale=ks)
+        ref = recursion.combine(list(P), M, N, K, ref_s, dr, kappa_scale=ks, arith=arith,
+                                leaf_dims=(mM, mK, mN))
+        np.testing.assert_array_equal(C.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("names,M,K,N", [(["strassen", "strassen"], 256, 192, 320),
+                                         (["laderman"], 192, 96, 288)])
+def test_bf16x3_gather_split_and_f64_scatter_bit_exact(names, M, K, N):
+    _say("bf16x3 stages", names, M, K, N)
+    lib_s, ref_s = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec="bf16x3", leaf_tile=64)
+    info = plan.info
+    A = workloads.gaussian((M, K), 1).astype(np.float32)
+    B = workloads.gaussian((K, N), 2).astype(np.float32)
+    s, p, dr = _level_draws(plan, ref_s, 3, "full")
+    ws = torch.zeros(info["workspace_bytes"], dtype=torch.uint8, device=DEV)
+    plan.stage_gather(0, torch.from_numpy(A).to(DEV), s, p, ws)
+    plan.stage_gather(1, torch.from_numpy(B).to(DEV), s, p, ws)
+    torch.cuda.synchronize()
+    L, mM, mK, mN = info["n_leaves"], info["mM"], info["mK"], info["mN"]
+    Sg = _region(ws, info["off_S"], info["bytes_S"], torch.int16, (2, L, mM, mK)).view(np.uint16)
+    Tg = _region(ws, info["off_T"], info["bytes_T"], torch.int16, (2, L, mK, mN)).view(np.uint16)
+    ops = recursion.leaf_operands(A, B, ref_s, dr, arith="f32", leaf_dims=(mM, mK, mN))
+    for l, (S, T) in enumerate(ops):
+        for X, G in ((S, Sg), (T, Tg)):
+            hi, lo = precision.split_hi_lo(X, "bf16")
+            np.testing.assert_array_equal(G[0, l], (hi.view(np.uint32) >> 16).astype(np.uint16))
+            np.testing.assert_array_equal(G[1, l], (lo.view(np.uint32) >> 16).astype(np.uint16))
+    P = np.random.default_rng(0).standard_normal((L, mM, mN)).astype(np.float32)
+    ws[info["off_P"]:info["off_P"] + info["bytes_P"]].copy_(torch.from_numpy(P.view(np.uint8).reshape(-1)))
+    C = torch.empty((M, N), dtype=torch.float32, device=DEV)
+    plan.stage_scatter(s, p, C, ws)
+    ref = recursion.combine(list(P.astype(np.float64)), M, N, K, ref_s, dr, arith="f64",
+                            leaf_dims=(mM, mK, mN)).astype(np.float32)
+    np.testing.assert_array_equal(C.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("prec,m,n,k,tile,batch", [("f32", 128, 256, 64, 128, 3), ("f32", 64, 128, 48, 64, 4),
+                                                   ("f64", 16, 48, 20, 16, 3), ("f32", 512, 512, 512, 128, 2)])
+def test_leaf_products(prec, m, n, k, tile, batch):
+    # A zero-level plan is one leaf; use the stage API on a plan with the given leaf count.
+    _say("leaf", prec, m, n, k, tile, batch)
+    S = rbc.Scheme.builtin("naive:1,1,%d" % batch) if batch > 1 else None
+    plan = rbc.Plan(m, k, n * batch, [S] if S else [], prec=prec, leaf_tile=tile)
+    info = plan.info
+    assert info["n_leaves"] == batch and (info["mM"], info["mK"], info["mN"]) == (m, k, n)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    g = torch.Generator(device="cpu").manual_seed(0)
+    ws = torch.zeros(info["workspace_bytes"], dtype=torch.uint8, device=DEV)
+    Sx = torch.randn(batch, m, k, generator=g, dtype=tdt)
+    Tx = torch.randn(batch, k, n, generator=g, dtype=tdt)
+    ws[info["off_S"]:info["off_S"] + info["bytes_S"]].copy_(Sx.view(torch.uint8).reshape(-1))
+    ws[info["off_T"]:info["off_T"] + info["bytes_T"]].copy_(Tx.view(torch.uint8).reshape(-1))
+    plan.stage_leaf(ws)
+    torch.cuda.synchronize()
+    P = _region(ws, info["off_P"], info["bytes_P"], tdt, (batch, m, n))
+    ref = np.matmul(Sx.double().numpy(), Tx.double().numpy())
+    eps = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+    bound = 2 * k * eps * np.matmul(np.abs(Sx.double().numpy()), np.abs(Tx.double().numpy()))
+    assert np.all(np.abs(P - ref) <= bound + 1e-300)
+
+
+def test_cfg1_fp64_n64_strassen_two_levels():
+    # Strassen, Q = 2, N = 64 -> 49 leaves of 16x16, f64; seed 0; data seeds 1001..1003.
+    _say("cfg1 f64 n=64")
+    lib_s, ref_s = _schemes(["strassen", "strassen"])
+    plan = rbc.Plan(64, 64, 64, lib_s, prec="f64")
+    Ai = workloads.integers((64, 64), 1003)
+    Bi = workloads.integers((64, 64), 1004)
+    for mode in ("full", "signs", "perms", "none"):
+        C = plan.matmul(torch.from_numpy(Ai.astype(np.float64)).to(DEV),
+                        torch.from_numpy(Bi.astype(np.float64)).to(DEV), seed=0, mode=mode)
+        np.testing.assert_array_equal(C.cpu().numpy(), (Ai @ Bi).astype(np.float64))
+    A = workloads.gaussian((64, 64), 1001)
+    B = workloads.gaussian((64, 64), 1002)
+    C = plan.matmul(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV), seed=0).cpu().numpy()
+    ref = recursion.rbc_seeded(A, B, ref_s, 0)
+    assert recursion.rel_err(C, ref) <= 1e-13
+    assert recursion.rel_err(C, A @ B) <= 1e-13
+
+
+@pytest.mark.parametrize("names,M,K,N,tile", [
+    (["strassen"] * 3, 4096, 4096, 4096, 0),
+    (["strassen"] * 3, 1000, 600, 777, 64),
+    (["laderman", "strassen"], 700, 500, 900, 64),
+    (["strassen"] * 5, 2048, 2048, 2048, 64),
+    (["naive:2,3,2"], 130, 90, 200, 64),
+    ([], 300, 200, 100, 64),
+])
+def test_f32_integers_exact(names, M, K, N, tile):
+    _say("f32 integers exact", names, M, K, N)
+    lib_s, _ = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec="f32", leaf_tile=tile)
+    A = workloads.integers((M, K), 7)
+    B = workloads.integers((K, N), 8)
+    ref = (A @ B).astype(np.float32)
+    Ad = torch.from_numpy(A.astype(np.float32)).to(DEV)
+    Bd = torch.from_numpy(B.astype(np.float32)).to(DEV)
+    for seed, mode in [(0, "full"), (1, "signs"), (2, "perms"), (3, "none")]:
+        C = plan.matmul(Ad, Bd, seed=seed, mode=mode)
+        np.testing.assert_array_equal(C.cpu().numpy(), ref, err_msg="seed %d %s" % (seed, mode))
+
+
+def test_cfg2_f32_n4096_uniform_matches_oracle():
+    # Strassen Q = 3, N = 4096, 512^3 leaves on f32 MFMA; U[-1,1], data seeds 2001/2002.
+    _say("cfg2 f32 n=4096 vs oracle")
+    lib_s, ref_s = _schemes(["strassen"] * 3)
+    plan = rbc.Plan(4096, 4096, 4096, lib_s, prec="f32")
+    A = workloads.uniform((4096, 4096), 2001, -1, 1)
+    B = workloads.uniform((4096, 4096), 2002, -1, 1)
+    AB = A @ B
+    Ad = torch.from_numpy(A.astype(np.float32)).to(DEV)
+    Bd = torch.from_numpy(B.astype(np.float32)).to(DEV)
+    emu = recursion.rbc_seeded(A.astype(np.float32), B.astype(np.float32), ref_s, 0, arith="f32")
+    e_emu = recursion.rel_err(emu, AB)
+    errs = []
+    for seed in range(16):
+        C = plan.matmul(Ad, Bd, seed=seed).cpu().numpy()
+        e = recursion.rel_err(C, AB)
+        errs.append(e)
+        assert e <= 1e-4, (seed, e)
+        if seed == 0:
+            assert e <= 4 * e_emu, (e, e_emu)
+            assert recursion.rel_err(C, emu) <= 4 * e_emu
+    _say("cfg2 rel err per seed", ["%.3g" % e for e in errs], "oracle f32 emulation %.3g" % e_emu)
+
+
+def test_perturbed_f64_matches_oracle_and_expectation_direction():
+    _say("perturbed f64")
+    lib_s, ref_s = _schemes(["pert:1e-2:3", "pert:1e-2:4"])
+    plan = rbc.Plan(96, 96, 96, lib_s, prec="f64")
+    A = workloads.gaussian((96, 96), 5)
+    B = workloads.gaussian((96, 96), 6)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    for seed in range(4):
+        for mode in ("full", "none"):
+            C = plan.matmul(Ad, Bd, seed=seed, mode=mode).cpu().numpy()
+            ref = recursion.rbc_seeded(A, B, ref_s, seed, mode)
+            assert recursion.rel_err(C, ref) <= 1e-13
+
+
+def test_bf16x3_end_to_end():
+    _say("bf16x3 end to end")
+    lib_s, ref_s = _schemes(["strassen"] * 3)
+    plan = rbc.Plan(768, 768, 768, lib_s, prec="bf16x3", leaf_tile=0)
+    A = workloads.gaussian((768, 768), 3001)
+    B = workloads.gaussian((768, 768), 3002)
+    AB = A @ B
+    C = plan.matmul(torch.from_numpy(A.astype(np.float32)).to(DEV),
+                    torch.from_numpy(B.astype(np.float32)).to(DEV), seed=0).cpu().numpy()
+
+    def leaf(S, T):
+        sh, sl = precision.split_hi_lo(S.astype(np.float32), "bf16")
+        th, tl = precision.split_hi_lo(T.astype(np.float32), "bf16")
+        sh, sl, th, tl = [x.astype(np.float64) for x in (sh, sl, th, tl)]
+        return (sh @ th + sh @ tl + sl @ th).astype(np.float32).astype(np.float64)
+
+    # emulation: f32 combinations, split leaves, f64 recombination
+    ops = recursion.leaf_operands(A.astype(np.float32), B.astype(np.float32), ref_s,
+                                  recursion.seeded_draws(ref_s, 0), arith="f32")
+    prods = [leaf(S, T) for S, T in ops]
+    emu = recursion.combine(prods, 768, 768, 768, ref_s, recursion.seeded_draws(ref_s, 0), arith="f64")
+    e_emu = recursion.rel_err(emu, AB)
+    e = recursion.rel_err(C, AB)
+    _say("bf16x3 rel err %.3g, emulation %.3g" % (e, e_emu))
+    assert e <= 1.5 * e_emu + 2e-7 and e <= 1e-4
+
+
+def test_results_are_deterministic_and_stream_ordered():
+    _say("determinism")
+    lib_s, _ = _schemes(["strassen"] * 3)
+    plan = rbc.Plan(1024, 1024, 1024, lib_s, prec="f32")
+    A = torch.randn(1024, 1024, device=DEV)
+    B = torch.randn(1024, 1024, device=DEV)
+    C1 = plan.matmul(A, B, seed=5).clone()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        C2 = plan.matmul(A, B, seed=5, workspace=torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=DEV))
+    s.synchronize()
+    assert torch.equal(C1, C2)
+    C3 = plan.matmul(A, B, seed=6)
+    assert not torch.equal(C1, C3)

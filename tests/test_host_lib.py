@@ -1,0 +1,175 @@
+"""Host-side checks of librbc on the CPU: symbols, schemes, draws, fold, plans, errors.
+
+No device compute is issued here.  The oracle is the reference for every value.
+"""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1905_07439_amd as rbc
+from paper_1905_07439_amd import _lib
+from oracle import draws as odraws
+from oracle import schemes as oschemes
+from oracle import tensors as otensors
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "rbc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = rbc.lib()
+    names = _header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.SIGNATURES, n
+    assert L.rbc_abi_version() == 1
+
+
+@pytest.mark.parametrize("name,builder", [("strassen", oschemes.strassen), ("laderman", oschemes.laderman)])
+def test_builtin_schemes_match_oracle(name, builder):
+    s = rbc.Scheme.builtin(name)
+    U, V, W = builder()
+    Ul, Vl, Wl = s.tensors()
+    np.testing.assert_array_equal(Ul, U)
+    np.testing.assert_array_equal(Vl, V)
+    np.testing.assert_array_equal(Wl, W)
+    i = s.info()
+    assert i["tau"] == 0.0 and i["kappa"] == 0.0
+    assert i["q"] == pytest.approx(otensors.q_uvw(U, V, W), rel=1e-14)
+    assert i["ynorm"] == pytest.approx(otensors.ynorm(U, V, W), rel=1e-14)
+
+
+def test_naive_builtin_and_rank_one_scheme():
+    s = rbc.Scheme.builtin("naive:2,3,2")
+    U, V, W = oschemes.naive(2, 3, 2)
+    np.testing.assert_array_equal(s.tensors()[0], U)
+    one = rbc.Scheme.from_tensors(*oschemes.rank_one_all_ones(2), residual_tol=math.inf)
+    assert one.info()["kappa"] == 0.0
+    assert one.info()["tau"] == pytest.approx(math.sqrt(56.0), rel=1e-15)
+
+
+def test_perturbed_scheme_matches_oracle_recipe_and_kappa():
+    for sigma, seed in [(1e-3, 0), (1e-1, 7)]:
+        s = rbc.Scheme.perturbed(rbc.Scheme.builtin("strassen"), sigma, seed)
+        ref = oschemes.perturbed(*oschemes.strassen(), sigma, np.random.default_rng(seed))
+        for a, b in zip(s.tensors(), ref):
+            np.testing.assert_array_equal(a, b)
+        i = s.info()
+        assert i["tau"] == pytest.approx(otensors.tau(*ref), rel=1e-12)
+        assert i["kappa"] == pytest.approx(otensors.kappa(*ref), rel=1e-12, abs=1e-18)
+
+
+def test_scheme_validation_errors():
+    U, V, W = oschemes.strassen()
+    W2 = W.copy()
+    W2[0, 0, 0] = 0
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.Scheme.from_tensors(U, V, W2)
+    assert e.value.status == _lib.RBC_ESCHEME
+    # kappa = 1 is rejected (Definition 2 needs kappa != 1)
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.Scheme.from_tensors(U * 0.0, V, W, residual_tol=math.inf)
+    assert e.value.status == _lib.RBC_ESCHEME
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.Scheme.from_tensors(np.zeros((5, 2, 1)), np.zeros((2, 2, 1)), np.zeros((5, 2, 1)))
+    assert e.value.status == _lib.RBC_EINVAL
+    with pytest.raises(rbc.RbcError):
+        rbc.Scheme.builtin("winograd")
+
+
+@pytest.mark.parametrize("b", [(2, 2, 2), (3, 3, 3), (3, 2, 2), (1, 4, 2)])
+@pytest.mark.parametrize("mode", ["full", "signs", "perms", "none"])
+def test_draws_match_oracle(b, mode):
+    for seed in list(range(40)) + [2 ** 63 + 5, 2 ** 64 - 1]:
+        for depth in range(4):
+            s, p = rbc.draw(seed, depth, *b, mode=mode)
+            ref = odraws.draw(seed, depth, *b, mode=mode)
+            np.testing.assert_array_equal(s, np.concatenate(ref[:3]))
+            np.testing.assert_array_equal(p, np.concatenate(ref[3:]))
+
+
+def test_fold_matches_oracle_bitwise():
+    base = oschemes.perturbed(*oschemes.laderman(), 1e-2, np.random.default_rng(3))
+    s = rbc.Scheme.from_tensors(*base, residual_tol=math.inf)
+    for seed in range(10):
+        sg, pm = rbc.draw(seed, 1, 3, 3, 3)
+        ref_draw = odraws.draw(seed, 1, 3, 3, 3)
+        for ks in (True, False):
+            c = 1.0 / (1.0 - float(otensors.kappa(*base))) if ks else 1.0
+            ref = odraws.fold(*base, ref_draw, c)
+            got = rbc.fold(s, sg, pm, kappa_scale=ks)
+            for a, r in zip(got, ref):
+                np.testing.assert_array_equal(a, r)
+
+
+def test_plan_geometry():
+    S = rbc.Scheme.builtin("strassen")
+    p = rbc.Plan(4096, 4096, 4096, [S, S, S], prec="f32")
+    i = p.info
+    assert (i["mM"], i["mK"], i["mN"]) == (512, 512, 512)
+    assert i["n_leaves"] == 343 and i["n_groups"] == 1 and i["tile_m"] == 128
+    assert i["bytes_S"] == 343 * 512 * 512 * 4
+    assert i["workspace_bytes"] >= 3 * 343 * 512 * 512 * 4
+    q = rbc.Plan(64, 64, 64, [S, S], prec="f64")
+    assert (q.info["mM"], q.info["n_leaves"], q.info["tile_m"]) == (16, 49, 16)
+    # ragged sizes pad up to the leaf tile; Laderman then Strassen is two groups
+    L = rbc.Scheme.builtin("laderman")
+    r = rbc.Plan(1000, 777, 333, [L, S], prec="f32", leaf_tile=64)
+    i = r.info
+    assert i["n_groups"] == 2 and i["n_leaves"] == 23 * 7
+    assert i["mM"] == 192 and i["Mp"] == 192 * 6 >= 1000
+    assert i["mK"] % 16 == 0 and i["mK"] * 6 >= 777
+    assert i["mN"] == 64 and i["Np"] >= 333
+    # five Strassen levels: groups of 3 and 2
+    f = rbc.Plan(2048, 2048, 2048, [S] * 5, prec="f32", leaf_tile=64)
+    assert f.info["n_groups"] == 2 and f.info["n_leaves"] == 7 ** 5
+    z = rbc.Plan(100, 50, 30, [], prec="f32")
+    assert z.info["n_leaves"] == 1 and z.info["mM"] == 128
+
+
+def test_plan_errors():
+    S = rbc.Scheme.builtin("strassen")
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.Plan(0, 4, 4, [S])
+    assert e.value.status == _lib.RBC_EINVAL
+    with pytest.raises(rbc.RbcError) as e:
+        rbc.Plan(64, 64, 64, [S], prec="f32", leaf_tile=96)
+    assert e.value.status == _lib.RBC_EUNSUPPORTED
+    with pytest.raises(rbc.RbcError):
+        rbc.Plan(64, 64, 64, [S] * 9)
+
+
+def test_matmul_argument_errors_are_synchronous():
+    # Argument checks fire before any device call, so they run without a GPU.
+    S = rbc.Scheme.builtin("strassen")
+    p = rbc.Plan(64, 64, 64, [S], prec="f32")
+    L = rbc.lib()
+    null = ctypes.c_void_p()
+    st = L.rbc_matmul(p._h, null, 64, null, 64, null, 64, 0, 0, 1, null, 0, null)
+    assert st == _lib.RBC_EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    st = L.rbc_matmul(p._h, fake, 64, fake, 64, fake, 64, 0, 0, 1, ctypes.c_void_p(0x1010), 10, null)
+    assert st == _lib.RBC_EINVAL  # workspace not 256-byte aligned
+    st = L.rbc_matmul(p._h, fake, 64, fake, 64, fake, 64, 0, 0, 1, ctypes.c_void_p(0x100000), 10, null)
+    assert st == _lib.RBC_ENOMEM
+    st = L.rbc_matmul(p._h, fake, 32, fake, 64, fake, 64, 0, 0, 1, ctypes.c_void_p(0x100000), 1 << 30, null)
+    assert st == _lib.RBC_EINVAL
+    st = L.rbc_matmul(p._h, fake, 64, fake, 64, fake, 64, 0, 7, 1, ctypes.c_void_p(0x100000), 1 << 30, null)
+    assert st == _lib.RBC_EINVAL
+    bad_s = (ctypes.c_int32 * 6)(1, 1, 2, 1, 1, 1)
+    ok_p = (ctypes.c_int32 * 6)(0, 1, 0, 1, 0, 1)
+    st = L.rbc_matmul_draws(p._h, fake, 64, fake, 64, fake, 64, bad_s, ok_p, 1, ctypes.c_void_p(0x100000),
+                            1 << 30, null)
+    assert st == _lib.RBC_EINVAL
+    assert b"draw" in L.rbc_last_error()
