@@ -149,9 +149,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ S,
     const double b = Tl[(int64_t)k0 * n];
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
+  // D layout of the f64 16x16 MFMA: lane holds column (lane & 15), rows (lane >> 4) + 4 v.
   double* Pl = P + leaf * (int64_t)m * n + (int64_t)(tm * 16) * n + tn * 16;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) Pl[(int64_t)((lane >> 4) * 4 + v) * n + (lane & 15)] = acc[v];
+  for (int v = 0; v < 4; ++v) Pl[(int64_t)((lane >> 4) + 4 * v) * n + (lane & 15)] = acc[v];
 }
 
 }  // namespace
