@@ -115,6 +115,16 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = 2.0 * N ** 3 / (ms_per_step * 1e-3) / 1e12
 
+    # the standard O(n^3) product on the same GPU (torch -> hipBLASLt/rocBLAS f32), for context
+    for _ in range(3):
+        torch.matmul(A, B, out=C)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.matmul(A, B, out=C)
+    torch.cuda.synchronize()
+    std_ms = (time.perf_counter() - g0) * 1e3 / args.steps
+
     # accuracy of the last step's seed against the float64 standard product
     seed = (args.steps - 1) % 16
     plan.matmul(A, B, C=C, seed=seed, workspace=ws)
@@ -144,6 +154,8 @@ def main():
         "stage_ms": {"gather_A": round(stage_ms[0] / calls, 4), "gather_B": round(stage_ms[1] / calls, 4),
                      "leaf": round(leaf_ms, 4), "scatter": round(stage_ms[3] / calls, 4)},
         "combination_hbm_GBs": round(comb_bytes / (comb_ms * 1e-3) / 1e9, 1),
+        "standard_f32_gemm_same_gpu": {"ms": round(std_ms, 4), "tflops": round(2.0 * N ** 3 / std_ms / 1e9, 2),
+                                       "lib": "torch.matmul (hipBLASLt/rocBLAS)"},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

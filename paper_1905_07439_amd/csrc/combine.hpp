@@ -23,6 +23,7 @@
 
 #pragma clang fp contract(off)
 
+
 namespace rbc {
 namespace comb {
 
@@ -50,15 +51,16 @@ struct GatherEmit {
   int64_t dst_batch, plane, off;
   __device__ __forceinline__ void operator()(int64_t idx, T v) const {
     if constexpr (OUTF == OUT_SAME) {
-      static_cast<T*>(dst)[idx * dst_batch + off] = v;
+      // streaming store: the leaf operands are read once, by the next kernel
+      __builtin_nontemporal_store(v, static_cast<T*>(dst) + idx * dst_batch + off);
     } else {
       // leaf operand split: hi = rn_bf16(v), lo = rn_bf16(v - hi) (v - hi is exact in f32)
       const float f = (float)v;
       const uint16_t hi = bf16_rne(f);
       const uint16_t lo = bf16_rne(f - bf16_to_float(hi));
       uint16_t* d = static_cast<uint16_t*>(dst) + idx * dst_batch + off;
-      d[0] = hi;
-      d[plane] = lo;
+      __builtin_nontemporal_store(hi, d);
+      __builtin_nontemporal_store(lo, d + plane);
     }
   }
 };
@@ -77,11 +79,13 @@ __device__ __forceinline__ void gather_level(const T* v, const SideLevel* lev, i
     constexpr int SUB = ipow(BB, NL - LT - 1);
     const SideLevel& L = lev[LT];
     const int RR = R ? R : L.R;
-    // Unroll the product loops of the inner levels; the outermost level of a
-    // multi-level group stays a loop (code size), as does a runtime R.
-    constexpr int UNR = (R == 0 || (LT == 0 && NL >= 2)) ? 1 : R;
+    // Unroll only the innermost level's product loop (R compiled in): outer
+    // levels stay loops, which bounds the values in flight per thread.
+    constexpr int UNR = (R == 0 || LT + 1 < NL) ? 1 : R;
 #pragma unroll UNR
     for (int r = 0; r < RR; ++r) {
+      // Keep each outer iteration's loads inside it (no hoisting across levels).
+      if constexpr (UNR == 1) __asm__ volatile("" ::: "memory");
       T acc[SUB];
 #pragma unroll
       for (int j = 0; j < SUB; ++j) acc[j] = T(0);
@@ -140,7 +144,7 @@ template <typename TP, typename TA, int NL, int BR, int BC, int R, int LT>
 __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, int64_t off,
                                               const SideLevel* lev, int64_t idx, TA* out) {
   if constexpr (LT == NL) {
-    out[0] = (TA)src[idx * src_batch + off];
+    out[0] = (TA)__builtin_nontemporal_load(src + idx * src_batch + off);
   } else {
     constexpr int BB = BR * BC;
     constexpr int SUB = ipow(BB, NL - LT - 1);
@@ -151,9 +155,10 @@ __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, 
     for (int ij = 0; ij < BB; ++ij) first[ij] = true;
 #pragma unroll
     for (int j = 0; j < BB * SUB; ++j) out[j] = TA(0);
-    constexpr int UNR = (R == 0 || (LT == 0 && NL >= 2)) ? 1 : R;
+    constexpr int UNR = (R == 0 || LT + 1 < NL) ? 1 : R;
 #pragma unroll UNR
     for (int r = 0; r < RR; ++r) {
+      if constexpr (UNR == 1) __asm__ volatile("" ::: "memory");
       TA sub[SUB];
       scatter_level<TP, TA, NL, BR, BC, R, LT + 1>(src, src_batch, off, lev, idx * RR + r, sub);
 #pragma unroll

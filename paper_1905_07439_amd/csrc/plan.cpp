@@ -8,6 +8,7 @@
 // folds its products back through W.  Padding (end of Section 2.1.1) is
 // virtual: reads outside A or B return zero, writes outside C are dropped.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "core.hpp"
@@ -27,9 +28,20 @@ bool fused_supported(int b1, int b2, int b3, int R, int nl) {
   return (nl == 2 || nl == 3) && strassen_shape;
 }
 
-static bool can_extend(const Group& g, const Scheme& s, int R0) {
-  if (s.b1 != g.b1 || s.b2 != g.b2 || s.b3 != g.b3 || s.R != R0) return false;
-  return fused_supported(s.b1, s.b2, s.b3, s.R, g.d1 - g.d0 + 1);
+// Most levels one pass fuses.  Three fused levels need about 100 values in
+// registers per thread, which costs occupancy; two keep every kernel under
+// 80 VGPRs.  Override with the environment variable RBC_MAX_FUSED_LEVELS.
+static int max_fused_levels() {
+  const char* e = std::getenv("RBC_MAX_FUSED_LEVELS");
+  if (e && *e) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 3) return v;
+  }
+  return 2;
+}
+
+static bool same_shape(const Scheme& a, const Scheme& b) {
+  return a.b1 == b.b1 && a.b2 == b.b2 && a.b3 == b.b3 && a.R == b.R;
 }
 
 rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>& levels,
@@ -79,18 +91,25 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : 4;  // bf16x3: hi + lo planes of 2 bytes
   const int prod_bytes = prec == RBC_PREC_F64 ? 8 : 4;
 
-  // Fused groups.
-  for (int d = 0; d < p.Q; ++d) {
+  // Fused groups, formed from the deepest level upwards so that the
+  // boundaries between passes sit where the intermediate blocks are fewest.
+  const int max_nl = max_fused_levels();
+  for (int d = p.Q - 1; d >= 0; --d) {
     const Scheme& s = levels[d];
-    if (!p.groups.empty() && can_extend(p.groups.back(), s, levels[p.groups.back().d0].R)) {
-      p.groups.back().d1 = d + 1;
-      continue;
+    if (!p.groups.empty()) {
+      Group& g = p.groups.back();  // the group just below, levels [g.d0, g.d1)
+      const int nl = g.d1 - g.d0 + 1;
+      if (nl <= max_nl && same_shape(s, levels[g.d0]) && fused_supported(s.b1, s.b2, s.b3, s.R, nl)) {
+        g.d0 = d;
+        continue;
+      }
     }
     Group g;
     g.d0 = d, g.d1 = d + 1;
     g.b1 = s.b1, g.b2 = s.b2, g.b3 = s.b3;
     p.groups.push_back(g);
   }
+  std::reverse(p.groups.begin(), p.groups.end());
   if (p.Q == 0) {  // plain product: one empty group copies A, B in and C out
     Group g;
     g.b1 = g.b2 = g.b3 = 1;

@@ -118,7 +118,9 @@ def test_plan_geometry():
     p = rbc.Plan(4096, 4096, 4096, [S, S, S], prec="f32")
     i = p.info
     assert (i["mM"], i["mK"], i["mN"]) == (512, 512, 512)
-    assert i["n_leaves"] == 343 and i["n_groups"] == 1 and i["tile_m"] == 128
+    assert i["n_leaves"] == 343 and i["tile_m"] == 128
+    # fused groups of at most two levels by default, formed from the bottom: [0] [1, 2]
+    assert i["n_groups"] == (1 if os.environ.get("RBC_MAX_FUSED_LEVELS") == "3" else 2)
     assert i["bytes_S"] == 343 * 512 * 512 * 4
     assert i["workspace_bytes"] >= 3 * 343 * 512 * 512 * 4
     q = rbc.Plan(64, 64, 64, [S, S], prec="f64")
@@ -131,11 +133,12 @@ def test_plan_geometry():
     assert i["mM"] == 192 and i["Mp"] == 192 * 6 >= 1000
     assert i["mK"] % 16 == 0 and i["mK"] * 6 >= 777
     assert i["mN"] == 64 and i["Np"] >= 333
-    # five Strassen levels: groups of 3 and 2
+    # five Strassen levels: [0] [1, 2] [3, 4]
     f = rbc.Plan(2048, 2048, 2048, [S] * 5, prec="f32", leaf_tile=64)
-    assert f.info["n_groups"] == 2 and f.info["n_leaves"] == 7 ** 5
+    assert f.info["n_leaves"] == 7 ** 5
+    assert f.info["n_groups"] == (2 if os.environ.get("RBC_MAX_FUSED_LEVELS") == "3" else 3)
     z = rbc.Plan(100, 50, 30, [], prec="f32")
-    assert z.info["n_leaves"] == 1 and z.info["mM"] == 128
+    assert z.info["n_leaves"] == 1 and z.info["mM"] == 128 and z.info["n_groups"] == 1
 
 
 def test_plan_errors():
