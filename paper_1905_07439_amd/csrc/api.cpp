@@ -3,8 +3,11 @@
 // them into status codes.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <vector>
 
@@ -250,6 +253,31 @@ rbc_status check_draws(const Plan& p, const int32_t* signs, const int32_t* perms
 
 enum Side { SIDE_A, SIDE_B, SIDE_C };
 
+// Positions per thread for a combination launch: the widest of 4, 2, 1 that
+// divides the block width, every leading dimension and block stride, and the
+// element alignment of every pointer.  8-byte accumulators use at most 2.
+// RBC_COMBINE_VEC (1, 2 or 4) lowers the cap for tuning.
+int max_vec_override() {
+  static const int v = [] {
+    const char* e = std::getenv("RBC_COMBINE_VEC");
+    const int x = e ? std::atoi(e) : 4;
+    return (x == 1 || x == 2 || x == 4) ? x : 4;
+  }();
+  return v;
+}
+
+int pick_vec(int elt_bytes, int64_t cols, std::initializer_list<int64_t> strides,
+             std::initializer_list<const void*> ptrs, bool wide_acc) {
+  const int cap = std::min(wide_acc ? 2 : 4, max_vec_override());
+  for (int v = cap; v > 1; v /= 2) {
+    bool ok = cols % v == 0;
+    for (int64_t s : strides) ok = ok && s % v == 0;
+    for (const void* q : ptrs) ok = ok && reinterpret_cast<uintptr_t>(q) % (size_t)(v * elt_bytes) == 0;
+    if (ok) return v;
+  }
+  return 1;
+}
+
 void fill_side(const Plan& p, const Draws& dr, int level, Side side, bool f64, bool kappa_scale,
                SideLevel& L) {
   const Scheme& s = p.levels[level];
@@ -316,8 +344,10 @@ rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx) {
       fill_side(p, c.dr, d, which == 0 ? SIDE_A : SIDE_B, f64, false, gp.lev[d - g.d0]);
     const int br = which == 0 ? g.b1 : g.b2, bc = which == 0 ? g.b2 : g.b3;
     const int R = p.Q ? p.levels[g.d0].R : 1;
-    hipError_t e = launch_gather(f64 ? ELT_F64 : ELT_F32, bf16_out ? OUT_BF16X2 : OUT_SAME, g.d1 - g.d0,
-                                 br, bc, R, gp, c.stream);
+    const int vec = pick_vec(f64 ? 8 : 4, gp.cols_bot, {gp.ld_src, gp.src_batch, gp.dst_batch, gp.plane},
+                             {gp.src, gp.dst}, f64);
+    hipError_t e = launch_gather(f64 ? ELT_F64 : ELT_F32, bf16_out ? OUT_BF16X2 : OUT_SAME, vec,
+                                 g.d1 - g.d0, br, bc, R, gp, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "gather launch: %s", hipGetErrorString(e));
   }
   return RBC_OK;
@@ -371,7 +401,9 @@ rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc) {
     else if (p.prec == RBC_PREC_F32) tp = ta = to = ELT_F32;
     else tp = last ? ELT_F32 : ELT_F64, ta = ELT_F64, to = gi == 0 ? ELT_F32 : ELT_F64;
     const int R = p.Q ? p.levels[g.d0].R : 1;
-    hipError_t e = launch_scatter(tp, ta, to, g.d1 - g.d0, g.b1, g.b3, R, sp, c.stream);
+    const int vec = pick_vec(to == ELT_F64 ? 8 : 4, sp.cols_bot, {sp.ld_dst, sp.dst_batch, sp.src_batch},
+                             {sp.src, sp.dst}, ta == ELT_F64);
+    hipError_t e = launch_scatter(tp, ta, to, vec, g.d1 - g.d0, g.b1, g.b3, R, sp, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "scatter launch: %s", hipGetErrorString(e));
   }
   return RBC_OK;

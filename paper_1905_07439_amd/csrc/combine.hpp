@@ -23,6 +23,16 @@
 
 #pragma clang fp contract(off)
 
+#ifndef RBC_NT_LOADS
+#define RBC_NT_LOADS 1
+#endif
+#ifndef RBC_NT_STORES
+#define RBC_NT_STORES 1
+#endif
+#ifndef RBC_LEVEL_BARRIER
+#define RBC_LEVEL_BARRIER 0
+#endif
+
 
 namespace rbc {
 namespace comb {
@@ -45,22 +55,49 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-template <typename T, int OUTF>
+// V consecutive element positions per thread: the loads and stores of a
+// wavefront cover 64 V contiguous elements of every block it touches.
+template <typename T, int V>
+using VecT = T __attribute__((ext_vector_type(V)));
+
+template <typename T, int V>
+__device__ __forceinline__ VecT<T, V> vload(const T* p) {
+#if RBC_NT_LOADS
+  return __builtin_nontemporal_load(reinterpret_cast<const VecT<T, V>*>(p));
+#else
+  return *reinterpret_cast<const VecT<T, V>*>(p);
+#endif
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vstore(T* p, VecT<T, V> v) {
+#if RBC_NT_STORES
+  __builtin_nontemporal_store(v, reinterpret_cast<VecT<T, V>*>(p));
+#else
+  *reinterpret_cast<VecT<T, V>*>(p) = v;
+#endif
+}
+
+template <typename T, int OUTF, int V>
 struct GatherEmit {
   void* dst;
   int64_t dst_batch, plane, off;
-  __device__ __forceinline__ void operator()(int64_t idx, T v) const {
+  __device__ __forceinline__ void operator()(int64_t idx, VecT<T, V> v) const {
     if constexpr (OUTF == OUT_SAME) {
       // streaming store: the leaf operands are read once, by the next kernel
-      __builtin_nontemporal_store(v, static_cast<T*>(dst) + idx * dst_batch + off);
+      vstore<T, V>(static_cast<T*>(dst) + idx * dst_batch + off, v);
     } else {
       // leaf operand split: hi = rn_bf16(v), lo = rn_bf16(v - hi) (v - hi is exact in f32)
-      const float f = (float)v;
-      const uint16_t hi = bf16_rne(f);
-      const uint16_t lo = bf16_rne(f - bf16_to_float(hi));
+      VecT<uint16_t, V> hi, lo;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const float f = (float)v[e];
+        hi[e] = bf16_rne(f);
+        lo[e] = bf16_rne(f - bf16_to_float(hi[e]));
+      }
       uint16_t* d = static_cast<uint16_t*>(dst) + idx * dst_batch + off;
-      __builtin_nontemporal_store(hi, d);
-      __builtin_nontemporal_store(lo, d + plane);
+      vstore<uint16_t, V>(d, hi);
+      vstore<uint16_t, V>(d + plane, lo);
     }
   }
 };
@@ -69,8 +106,8 @@ struct GatherEmit {
 // block (k, l) of this level occupying the SUB consecutive values at
 // (k * BC + l) * SUB.  R > 0 is the compiled product count, R == 0 reads it
 // from the level descriptor.
-template <typename T, int NL, int BR, int BC, int R, int LT, typename Emit>
-__device__ __forceinline__ void gather_level(const T* v, const SideLevel* lev, int64_t idx,
+template <typename T, int V, int NL, int BR, int BC, int R, int LT, typename Emit>
+__device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLevel* lev, int64_t idx,
                                              const Emit& emit) {
   if constexpr (LT == NL) {
     emit(idx, v[0]);
@@ -79,16 +116,14 @@ __device__ __forceinline__ void gather_level(const T* v, const SideLevel* lev, i
     constexpr int SUB = ipow(BB, NL - LT - 1);
     const SideLevel& L = lev[LT];
     const int RR = R ? R : L.R;
-    // Unroll only the innermost level's product loop (R compiled in): outer
-    // levels stay loops, which bounds the values in flight per thread.
+    // Unroll only the innermost level's product loop (R compiled in).
     constexpr int UNR = (R == 0 || LT + 1 < NL) ? 1 : R;
 #pragma unroll UNR
     for (int r = 0; r < RR; ++r) {
-      // Keep each outer iteration's loads inside it (no hoisting across levels).
-      if constexpr (UNR == 1) __asm__ volatile("" ::: "memory");
-      T acc[SUB];
+      if constexpr (UNR == 1 && RBC_LEVEL_BARRIER) __asm__ volatile("" ::: "memory");
+      VecT<T, V> acc[SUB];
 #pragma unroll
-      for (int j = 0; j < SUB; ++j) acc[j] = T(0);
+      for (int j = 0; j < SUB; ++j) acc[j] = VecT<T, V>(T(0));
       bool first = true;
 #pragma unroll
       for (int kl = 0; kl < BB; ++kl) {
@@ -96,28 +131,28 @@ __device__ __forceinline__ void gather_level(const T* v, const SideLevel* lev, i
         if (c != T(0)) {
 #pragma unroll
           for (int j = 0; j < SUB; ++j) {
-            const T t = c * v[kl * SUB + j];
+            const VecT<T, V> t = c * v[kl * SUB + j];
             acc[j] = first ? t : acc[j] + t;
           }
           first = false;
         }
       }
-      gather_level<T, NL, BR, BC, R, LT + 1>(acc, lev, idx * RR + r, emit);
+      gather_level<T, V, NL, BR, BC, R, LT + 1>(acc, lev, idx * RR + r, emit);
     }
   }
 }
 
-template <typename T, int OUTF, int NL, int BR, int BC, int R>
+template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
 __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
   constexpr int BB = BR * BC;
   constexpr int NSRC = ipow(BB, NL);
   const int64_t npos = p.rows_bot * p.cols_bot;
-  const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t pos = ((int64_t)blockIdx.x * 256 + threadIdx.x) * V;
   if (pos >= npos) return;
-  const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
+  const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;  // cols_bot % V == 0
   for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
     const T* src = static_cast<const T*>(p.src) + in * p.src_batch;
-    T v[NSRC];
+    VecT<T, V> v[NSRC];
 #pragma unroll
     for (int s = 0; s < NSRC; ++s) {
       int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
@@ -131,20 +166,28 @@ __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
         hs *= BR;
         ws *= BC;
       }
-      v[s] = (row < p.src_rows && col < p.src_cols) ? src[row * p.ld_src + col] : T(0);
+      if (row < p.src_rows && col + V <= p.src_cols) {
+        v[s] = vload<T, V>(src + row * p.ld_src + col);  // aligned: checked by the host
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          v[s][e] = (row < p.src_rows && col + e < p.src_cols) ? src[row * p.ld_src + col + e] : T(0);
+      }
     }
-    GatherEmit<T, OUTF> e{p.dst, p.dst_batch, p.plane, pos};
-    gather_level<T, NL, BR, BC, R, 0>(v, p.lev, in, e);
+    GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos};
+    gather_level<T, V, NL, BR, BC, R, 0>(v, p.lev, in, e);
   }
 }
 
 // Level LT of a scatter group: returns in `out` the BB^(NL-LT) values of the
 // block at this level for subproblem prefix idx.
-template <typename TP, typename TA, int NL, int BR, int BC, int R, int LT>
+template <typename TP, typename TA, int V, int NL, int BR, int BC, int R, int LT>
 __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, int64_t off,
-                                              const SideLevel* lev, int64_t idx, TA* out) {
+                                              const SideLevel* lev, int64_t idx, VecT<TA, V>* out) {
   if constexpr (LT == NL) {
-    out[0] = (TA)__builtin_nontemporal_load(src + idx * src_batch + off);
+    const VecT<TP, V> x = vload<TP, V>(src + idx * src_batch + off);
+#pragma unroll
+    for (int e = 0; e < V; ++e) out[0][e] = (TA)x[e];
   } else {
     constexpr int BB = BR * BC;
     constexpr int SUB = ipow(BB, NL - LT - 1);
@@ -154,20 +197,20 @@ __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, 
 #pragma unroll
     for (int ij = 0; ij < BB; ++ij) first[ij] = true;
 #pragma unroll
-    for (int j = 0; j < BB * SUB; ++j) out[j] = TA(0);
+    for (int j = 0; j < BB * SUB; ++j) out[j] = VecT<TA, V>(TA(0));
     constexpr int UNR = (R == 0 || LT + 1 < NL) ? 1 : R;
 #pragma unroll UNR
     for (int r = 0; r < RR; ++r) {
-      if constexpr (UNR == 1) __asm__ volatile("" ::: "memory");
-      TA sub[SUB];
-      scatter_level<TP, TA, NL, BR, BC, R, LT + 1>(src, src_batch, off, lev, idx * RR + r, sub);
+      if constexpr (UNR == 1 && RBC_LEVEL_BARRIER) __asm__ volatile("" ::: "memory");
+      VecT<TA, V> sub[SUB];
+      scatter_level<TP, TA, V, NL, BR, BC, R, LT + 1>(src, src_batch, off, lev, idx * RR + r, sub);
 #pragma unroll
       for (int ij = 0; ij < BB; ++ij) {
         const TA c = coef<TA, BC>(L, ij / BC, ij % BC, r, RR);
         if (c != TA(0)) {
 #pragma unroll
           for (int j = 0; j < SUB; ++j) {
-            const TA t = c * sub[j];
+            const VecT<TA, V> t = c * sub[j];
             out[ij * SUB + j] = first[ij] ? t : out[ij * SUB + j] + t;
           }
           first[ij] = false;
@@ -177,18 +220,18 @@ __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, 
   }
 }
 
-template <typename TP, typename TA, typename TO, int NL, int BR, int BC, int R>
+template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
 __global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
   constexpr int BB = BR * BC;
   constexpr int NOUT = ipow(BB, NL);
   const int64_t npos = p.rows_bot * p.cols_bot;
-  const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t pos = ((int64_t)blockIdx.x * 256 + threadIdx.x) * V;
   if (pos >= npos) return;
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
   const TP* src = static_cast<const TP*>(p.src);
   for (int64_t o = blockIdx.y; o < p.n_out; o += gridDim.y) {
-    TA out[NOUT];
-    scatter_level<TP, TA, NL, BR, BC, R, 0>(src, p.src_batch, pos, p.lev, o, out);
+    VecT<TA, V> out[NOUT];
+    scatter_level<TP, TA, V, NL, BR, BC, R, 0>(src, p.src_batch, pos, p.lev, o, out);
     TO* dst = static_cast<TO*>(p.dst) + o * p.dst_batch;
 #pragma unroll
     for (int s = 0; s < NOUT; ++s) {
@@ -203,7 +246,16 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
         hs *= BR;
         ws *= BC;
       }
-      if (row < p.dst_rows && col < p.dst_cols) dst[row * p.ld_dst + col] = (TO)out[s];
+      VecT<TO, V> w;
+#pragma unroll
+      for (int e = 0; e < V; ++e) w[e] = (TO)out[s][e];
+      if (row < p.dst_rows && col + V <= p.dst_cols) {
+        *reinterpret_cast<VecT<TO, V>*>(dst + row * p.ld_dst + col) = w;  // aligned: checked by the host
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (row < p.dst_rows && col + e < p.dst_cols) dst[row * p.ld_dst + col + e] = w[e];
+      }
     }
   }
 }
@@ -214,17 +266,17 @@ inline dim3 grid_for(int64_t npos, int64_t nbatch) {
   return dim3((unsigned)gx, (unsigned)gy, 1);
 }
 
-template <typename T, int OUTF, int NL, int BR, int BC, int R>
+template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
 hipError_t run_gather(const GatherParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((k_gather<T, OUTF, NL, BR, BC, R>), grid_for(p.rows_bot * p.cols_bot, p.n_in),
-                     dim3(256), 0, s, p);
+  hipLaunchKernelGGL((k_gather<T, OUTF, V, NL, BR, BC, R>),
+                     grid_for(p.rows_bot * p.cols_bot / V, p.n_in), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
-template <typename TP, typename TA, typename TO, int NL, int BR, int BC, int R>
+template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
 hipError_t run_scatter(const ScatterParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((k_scatter<TP, TA, TO, NL, BR, BC, R>),
-                     grid_for(p.rows_bot * p.cols_bot, p.n_out), dim3(256), 0, s, p);
+  hipLaunchKernelGGL((k_scatter<TP, TA, TO, V, NL, BR, BC, R>),
+                     grid_for(p.rows_bot * p.cols_bot / V, p.n_out), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
@@ -247,35 +299,41 @@ hipError_t dispatch_shape(int nl, int br, int bc, int R, const P& p, hipStream_t
   return hipErrorInvalidValue;
 }
 
-template <typename T, int OUTF>
+template <typename T, int OUTF, int V>
 struct GatherOf {
   template <int NL, int BR, int BC, int R>
   struct F {
     static hipError_t run(const GatherParams& p, hipStream_t s) {
-      return run_gather<T, OUTF, NL, BR, BC, R>(p, s);
+      return run_gather<T, OUTF, V, NL, BR, BC, R>(p, s);
     }
   };
 };
 
-template <typename TP, typename TA, typename TO>
+template <typename TP, typename TA, typename TO, int V>
 struct ScatterOf {
   template <int NL, int BR, int BC, int R>
   struct F {
     static hipError_t run(const ScatterParams& p, hipStream_t s) {
-      return run_scatter<TP, TA, TO, NL, BR, BC, R>(p, s);
+      return run_scatter<TP, TA, TO, V, NL, BR, BC, R>(p, s);
     }
   };
 };
 
-
+// vec: positions per thread (1, 2 or 4), chosen by the host from the
+// alignment of every pointer, leading dimension and block stride involved.
 template <typename T, int OUTF>
-hipError_t gather_dispatch(int nl, int br, int bc, int R, const GatherParams& p, hipStream_t s) {
-  return dispatch_shape<GatherOf<T, OUTF>::template F>(nl, br, bc, R, p, s);
+hipError_t gather_dispatch(int vec, int nl, int br, int bc, int R, const GatherParams& p, hipStream_t s) {
+  if (vec == 4) return dispatch_shape<GatherOf<T, OUTF, 4>::template F>(nl, br, bc, R, p, s);
+  if (vec == 2) return dispatch_shape<GatherOf<T, OUTF, 2>::template F>(nl, br, bc, R, p, s);
+  return dispatch_shape<GatherOf<T, OUTF, 1>::template F>(nl, br, bc, R, p, s);
 }
 
 template <typename TP, typename TA, typename TO>
-hipError_t scatter_dispatch(int nl, int br, int bc, int R, const ScatterParams& p, hipStream_t s) {
-  return dispatch_shape<ScatterOf<TP, TA, TO>::template F>(nl, br, bc, R, p, s);
+hipError_t scatter_dispatch(int vec, int nl, int br, int bc, int R, const ScatterParams& p,
+                            hipStream_t s) {
+  if (vec == 4) return dispatch_shape<ScatterOf<TP, TA, TO, 4>::template F>(nl, br, bc, R, p, s);
+  if (vec == 2) return dispatch_shape<ScatterOf<TP, TA, TO, 2>::template F>(nl, br, bc, R, p, s);
+  return dispatch_shape<ScatterOf<TP, TA, TO, 1>::template F>(nl, br, bc, R, p, s);
 }
 
 #define RBC_GATHER_COMBOS(X) \
@@ -284,10 +342,11 @@ hipError_t scatter_dispatch(int nl, int br, int bc, int R, const ScatterParams& 
   X(double, double, double) X(float, float, float) X(float, double, double)            \
   X(float, double, float) X(double, double, float)
 
-#define RBC_DECL_G(T, O) \
-  extern template hipError_t gather_dispatch<T, O>(int, int, int, int, const GatherParams&, hipStream_t);
-#define RBC_DECL_S(A, B, C)                                                                     \
-  extern template hipError_t scatter_dispatch<A, B, C>(int, int, int, int, const ScatterParams&, \
+#define RBC_DECL_G(T, O)                                                                   \
+  extern template hipError_t gather_dispatch<T, O>(int, int, int, int, int, const GatherParams&, \
+                                                   hipStream_t);
+#define RBC_DECL_S(A, B, C)                                                                          \
+  extern template hipError_t scatter_dispatch<A, B, C>(int, int, int, int, int, const ScatterParams&, \
                                                         hipStream_t);
 
 }  // namespace comb

@@ -8,29 +8,29 @@ RBC_GATHER_COMBOS(RBC_DECL_G)
 RBC_SCATTER_COMBOS(RBC_DECL_S)
 }  // namespace comb
 
-hipError_t launch_gather(Elt elt, GatherOut out, int nl, int br, int bc, int R,
+hipError_t launch_gather(Elt elt, GatherOut out, int vec, int nl, int br, int bc, int R,
                          const GatherParams& p, hipStream_t s) {
   if (p.rows_bot * p.cols_bot == 0 || p.n_in == 0) return hipSuccess;
-  if (elt == ELT_F64 && out == OUT_SAME) return comb::gather_dispatch<double, OUT_SAME>(nl, br, bc, R, p, s);
-  if (elt == ELT_F32 && out == OUT_SAME) return comb::gather_dispatch<float, OUT_SAME>(nl, br, bc, R, p, s);
+  if (elt == ELT_F64 && out == OUT_SAME) return comb::gather_dispatch<double, OUT_SAME>(vec, nl, br, bc, R, p, s);
+  if (elt == ELT_F32 && out == OUT_SAME) return comb::gather_dispatch<float, OUT_SAME>(vec, nl, br, bc, R, p, s);
   if (elt == ELT_F32 && out == OUT_BF16X2)
-    return comb::gather_dispatch<float, OUT_BF16X2>(nl, br, bc, R, p, s);
+    return comb::gather_dispatch<float, OUT_BF16X2>(vec, nl, br, bc, R, p, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int nl, int br, int bc, int R,
+hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int vec, int nl, int br, int bc, int R,
                           const ScatterParams& p, hipStream_t s) {
   if (p.rows_bot * p.cols_bot == 0 || p.n_out == 0) return hipSuccess;
   if (tp == ELT_F64 && ta == ELT_F64 && to == ELT_F64)
-    return comb::scatter_dispatch<double, double, double>(nl, br, bc, R, p, s);
+    return comb::scatter_dispatch<double, double, double>(vec, nl, br, bc, R, p, s);
   if (tp == ELT_F32 && ta == ELT_F32 && to == ELT_F32)
-    return comb::scatter_dispatch<float, float, float>(nl, br, bc, R, p, s);
+    return comb::scatter_dispatch<float, float, float>(vec, nl, br, bc, R, p, s);
   if (tp == ELT_F32 && ta == ELT_F64 && to == ELT_F64)
-    return comb::scatter_dispatch<float, double, double>(nl, br, bc, R, p, s);
+    return comb::scatter_dispatch<float, double, double>(vec, nl, br, bc, R, p, s);
   if (tp == ELT_F32 && ta == ELT_F64 && to == ELT_F32)
-    return comb::scatter_dispatch<float, double, float>(nl, br, bc, R, p, s);
+    return comb::scatter_dispatch<float, double, float>(vec, nl, br, bc, R, p, s);
   if (tp == ELT_F64 && ta == ELT_F64 && to == ELT_F32)
-    return comb::scatter_dispatch<double, double, float>(nl, br, bc, R, p, s);
+    return comb::scatter_dispatch<double, double, float>(vec, nl, br, bc, R, p, s);
   return hipErrorInvalidValue;
 }
 

@@ -3,6 +3,6 @@
 
 namespace rbc {
 namespace comb {
-template hipError_t scatter_dispatch<double, double, double>(int, int, int, int, const ScatterParams&, hipStream_t);
+template hipError_t scatter_dispatch<double, double, double>(int, int, int, int, int, const ScatterParams&, hipStream_t);
 }  // namespace comb
 }  // namespace rbc

@@ -46,10 +46,12 @@ struct ScatterParams {
 // Element-type codes for launchers.
 enum Elt { ELT_F32 = 0, ELT_F64 = 1 };
 
-hipError_t launch_gather(Elt elt, GatherOut out, int nl, int br, int bc, int R,
+// vec: element positions per thread (1, 2 or 4); every pointer, leading
+// dimension and block stride of the launch must be a multiple of it.
+hipError_t launch_gather(Elt elt, GatherOut out, int vec, int nl, int br, int bc, int R,
                          const GatherParams& p, hipStream_t stream);
 // tp: product element type, ta: accumulation type, to: output element type
-hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int nl, int br, int bc, int R,
+hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int vec, int nl, int br, int bc, int R,
                           const ScatterParams& p, hipStream_t stream);
 
 // Batched leaf products P_l = S_l T_l, l < batch; S: m x k, T: k x n, P: m x n,
