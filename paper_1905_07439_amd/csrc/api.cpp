@@ -255,7 +255,8 @@ enum Side { SIDE_A, SIDE_B, SIDE_C };
 
 // Positions per thread for a combination launch: the widest of 4, 2, 1 that
 // divides the block width, every leading dimension and block stride, and the
-// element alignment of every pointer.  8-byte accumulators use at most 2.
+// element alignment of every pointer.  8-byte accumulators use at most 2, and
+// 1 in two-level groups (register budget).
 // RBC_COMBINE_VEC (1, 2 or 4) lowers the cap for tuning.
 int max_vec_override() {
   static const int v = [] {
@@ -267,8 +268,8 @@ int max_vec_override() {
 }
 
 int pick_vec(int elt_bytes, int64_t cols, std::initializer_list<int64_t> strides,
-             std::initializer_list<const void*> ptrs, bool wide_acc) {
-  const int cap = std::min(wide_acc ? 2 : 4, max_vec_override());
+             std::initializer_list<const void*> ptrs, bool wide_acc, int nl) {
+  const int cap = std::min(wide_acc ? (nl >= 2 ? 1 : 2) : 4, max_vec_override());
   for (int v = cap; v > 1; v /= 2) {
     bool ok = cols % v == 0;
     for (int64_t s : strides) ok = ok && s % v == 0;
@@ -345,7 +346,7 @@ rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx) {
     const int br = which == 0 ? g.b1 : g.b2, bc = which == 0 ? g.b2 : g.b3;
     const int R = p.Q ? p.levels[g.d0].R : 1;
     const int vec = pick_vec(f64 ? 8 : 4, gp.cols_bot, {gp.ld_src, gp.src_batch, gp.dst_batch, gp.plane},
-                             {gp.src, gp.dst}, f64);
+                             {gp.src, gp.dst}, f64, g.d1 - g.d0);
     hipError_t e = launch_gather(f64 ? ELT_F64 : ELT_F32, bf16_out ? OUT_BF16X2 : OUT_SAME, vec,
                                  g.d1 - g.d0, br, bc, R, gp, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "gather launch: %s", hipGetErrorString(e));
@@ -402,7 +403,7 @@ rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc) {
     else tp = last ? ELT_F32 : ELT_F64, ta = ELT_F64, to = gi == 0 ? ELT_F32 : ELT_F64;
     const int R = p.Q ? p.levels[g.d0].R : 1;
     const int vec = pick_vec(to == ELT_F64 ? 8 : 4, sp.cols_bot, {sp.ld_dst, sp.dst_batch, sp.src_batch},
-                             {sp.src, sp.dst}, ta == ELT_F64);
+                             {sp.src, sp.dst}, ta == ELT_F64, g.d1 - g.d0);
     hipError_t e = launch_scatter(tp, ta, to, vec, g.d1 - g.d0, g.b1, g.b3, R, sp, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "scatter launch: %s", hipGetErrorString(e));
   }

@@ -116,26 +116,28 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
     constexpr int SUB = ipow(BB, NL - LT - 1);
     const SideLevel& L = lev[LT];
     const int RR = R ? R : L.R;
-    // Unroll only the innermost level's product loop (R compiled in).
-    constexpr int UNR = (R == 0 || LT + 1 < NL) ? 1 : R;
+    // Unroll only the innermost level's product loop, when R is compiled in and small.
+    constexpr int UNR = (R == 0 || R > 8 || LT + 1 < NL) ? 1 : R;
 #pragma unroll UNR
     for (int r = 0; r < RR; ++r) {
       if constexpr (UNR == 1 && RBC_LEVEL_BARRIER) __asm__ volatile("" ::: "memory");
       VecT<T, V> acc[SUB];
 #pragma unroll
       for (int j = 0; j < SUB; ++j) acc[j] = VecT<T, V>(T(0));
+      // Branch-free sequential sum: a zero coefficient leaves acc untouched (selects on
+      // uniform conditions instead of branches keep the scalar registers free).
       bool first = true;
 #pragma unroll
       for (int kl = 0; kl < BB; ++kl) {
         const T c = coef<T, BC>(L, kl / BC, kl % BC, r, RR);
-        if (c != T(0)) {
+        const bool nz = c != T(0);
 #pragma unroll
-          for (int j = 0; j < SUB; ++j) {
-            const VecT<T, V> t = c * v[kl * SUB + j];
-            acc[j] = first ? t : acc[j] + t;
-          }
-          first = false;
+        for (int j = 0; j < SUB; ++j) {
+          const VecT<T, V> t = c * v[kl * SUB + j];
+          const VecT<T, V> sum = first ? t : acc[j] + t;
+          acc[j] = nz ? sum : acc[j];
         }
+        first = first && !nz;
       }
       gather_level<T, V, NL, BR, BC, R, LT + 1>(acc, lev, idx * RR + r, emit);
     }
@@ -198,7 +200,7 @@ __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, 
     for (int ij = 0; ij < BB; ++ij) first[ij] = true;
 #pragma unroll
     for (int j = 0; j < BB * SUB; ++j) out[j] = VecT<TA, V>(TA(0));
-    constexpr int UNR = (R == 0 || LT + 1 < NL) ? 1 : R;
+    constexpr int UNR = (R == 0 || R > 8 || LT + 1 < NL) ? 1 : R;
 #pragma unroll UNR
     for (int r = 0; r < RR; ++r) {
       if constexpr (UNR == 1 && RBC_LEVEL_BARRIER) __asm__ volatile("" ::: "memory");
@@ -207,14 +209,14 @@ __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, 
 #pragma unroll
       for (int ij = 0; ij < BB; ++ij) {
         const TA c = coef<TA, BC>(L, ij / BC, ij % BC, r, RR);
-        if (c != TA(0)) {
+        const bool nz = c != TA(0);
 #pragma unroll
-          for (int j = 0; j < SUB; ++j) {
-            const VecT<TA, V> t = c * sub[j];
-            out[ij * SUB + j] = first[ij] ? t : out[ij * SUB + j] + t;
-          }
-          first[ij] = false;
+        for (int j = 0; j < SUB; ++j) {
+          const VecT<TA, V> t = c * sub[j];
+          const VecT<TA, V> sum = first[ij] ? t : out[ij * SUB + j] + t;
+          out[ij * SUB + j] = nz ? sum : out[ij * SUB + j];
         }
+        first[ij] = first[ij] && !nz;
       }
     }
   }

@@ -4,13 +4,14 @@
 //
 // f32: v_mfma_f32_16x16x4_f32.  A workgroup of 4 wavefronts computes a BM x BN
 // tile (BM = BN = 64 or 128), each wavefront a (BM/2) x (BN/2) quarter as a
-// grid of 16x16 MFMA tiles.  K advances in steps of 16 through a double
-// buffered LDS stage: the next K slab is fetched from global memory into
-// registers while the current slab feeds the MFMAs, then stored to the other
-// LDS buffer.  S slabs are stored transposed (k-major) so that one MFMA
-// operand is 16 consecutive LDS words per k row; rows are padded by 16 words,
-// which puts the four k rows a wavefront reads in one instruction on
-// disjoint banks.
+// grid of 16x16 MFMA tiles.  K advances in slabs of 32 (16 when K is not a
+// multiple of 32) through two LDS buffers: a slab held in registers is
+// written to one buffer, one barrier, then the next slab's global loads are
+// issued and stay in flight while the MFMAs consume the buffer.  Both slabs
+// keep their memory layout in LDS (16-byte stores): the k order inside each
+// group of 16 is permuted identically for both operands so that an S operand
+// is one 16-byte LDS read per four MFMA steps; S rows are padded to 36 words
+// and T rows to BN + 4, which spreads each read over all banks.
 //
 // Workgroups are dispatched round robin over the 8 XCDs; block ids are
 // remapped so that the tiles of one leaf run on the same XCD and share its L2.
@@ -34,19 +35,27 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ S,
                                                   const float* __restrict__ T, float* __restrict__ P,
                                                   int m, int n, int k, int tiles_n,
                                                   int tiles_per_leaf, int64_t nblocks) {
-  constexpr int BK = 16;
-  constexpr int PAD = 16;
+  constexpr int LDA = BK + 4;                 // S slab row: k-contiguous, padded
+  constexpr int LDB = BN + 4;                 // T slab row: n-contiguous, padded
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int A_VEC = BM * BK / 4 / 256;  // float4 loads per thread per slab
-  constexpr int B_VEC = BN * BK / 4 / 256;
-  __shared__ float As[2][BK][BM + PAD];
-  __shared__ float Bs[2][BK][BN + PAD];
+  constexpr int KQ = BK / 4;                  // float4 chunks per S row of a slab
+  constexpr int A_VEC = BM * KQ / 256;        // float4 loads per thread per slab
+  constexpr int B_VEC = BK * (BN / 4) / 256;
+  constexpr int LDE = WN + 4;                 // epilogue row of a wavefront's quarter
+  static_assert(A_VEC >= 1 && B_VEC >= 1, "tile too small for 256 threads");
+  // One LDS block: two S and two T slab buffers during the K loop, the four
+  // wavefronts' output quarters in the epilogue.
+  constexpr int A_FLOATS = 2 * BM * LDA, B_FLOATS = 2 * BK * LDB, E_FLOATS = 4 * WM * LDE;
+  constexpr int SMEM = A_FLOATS + B_FLOATS > E_FLOATS ? A_FLOATS + B_FLOATS : E_FLOATS;
+  __shared__ __attribute__((aligned(16))) float smem[SMEM];
+  float(*As)[BM][LDA] = reinterpret_cast<float(*)[BM][LDA]>(smem);
+  float(*Bs)[BK][LDB] = reinterpret_cast<float(*)[BK][LDB]>(smem + A_FLOATS);
 
   const int64_t bid = xcd_remap(blockIdx.x, nblocks);
   const int64_t leaf = bid / tiles_per_leaf;
@@ -59,34 +68,27 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ S,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  float4 ra[A_VEC], rb[B_VEC];
-  auto gload = [&](int k0) {
+  // Per-thread slab sources: S row (tid + 256 i) / KQ, chunk % KQ; T row (tid + 256 i) / (BN/4).
+  const float* a_src[A_VEC];
+  const float* b_src[B_VEC];
 #pragma unroll
-    for (int i = 0; i < A_VEC; ++i) {
-      const int idx = tid + 256 * i, row = idx / (BK / 4), kq = idx % (BK / 4);
-      ra[i] = *reinterpret_cast<const float4*>(Sl + (int64_t)row * k + k0 + kq * 4);
-    }
+  for (int i = 0; i < A_VEC; ++i) {
+    const int idx = tid + 256 * i;
+    a_src[i] = Sl + (int64_t)(idx / KQ) * k + (idx % KQ) * 4;
+  }
 #pragma unroll
-    for (int i = 0; i < B_VEC; ++i) {
-      const int idx = tid + 256 * i, kr = idx / (BN / 4), cq = idx % (BN / 4);
-      rb[i] = *reinterpret_cast<const float4*>(Tl + (int64_t)(k0 + kr) * n + cq * 4);
-    }
-  };
-  auto sstore = [&](int buf) {
+  for (int i = 0; i < B_VEC; ++i) {
+    const int idx = tid + 256 * i;
+    b_src[i] = Tl + (int64_t)(idx / (BN / 4)) * n + (idx % (BN / 4)) * 4;
+  }
+  const int64_t b_step = (int64_t)BK * n;
+
+  // clang vector types (not HIP's float4 struct) so the staging stays in registers
+  floatx4 ra[A_VEC], rb[B_VEC];
 #pragma unroll
-    for (int i = 0; i < A_VEC; ++i) {
-      const int idx = tid + 256 * i, row = idx / (BK / 4), kq = idx % (BK / 4);
-      As[buf][kq * 4 + 0][row] = ra[i].x;
-      As[buf][kq * 4 + 1][row] = ra[i].y;
-      As[buf][kq * 4 + 2][row] = ra[i].z;
-      As[buf][kq * 4 + 3][row] = ra[i].w;
-    }
+  for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i]);
 #pragma unroll
-    for (int i = 0; i < B_VEC; ++i) {
-      const int idx = tid + 256 * i, kr = idx / (BN / 4), cq = idx % (BN / 4);
-      *reinterpret_cast<float4*>(&Bs[buf][kr][cq * 4]) = rb[i];
-    }
-  };
+  for (int i = 0; i < B_VEC; ++i) rb[i] = *reinterpret_cast<const floatx4*>(b_src[i]);
 
   floatx4 acc[FM][FN];
 #pragma unroll
@@ -94,41 +96,72 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ S,
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int nk = k / BK;
-  const int lr = lane & 15, lk = lane >> 4;
+  const int lr = lane & 15, lg = lane >> 4;
+  int cur = 0;
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      float a[FM], b[FN];
+    for (int i = 0; i < A_VEC; ++i) {
+      const int idx = tid + 256 * i;
+      *reinterpret_cast<floatx4*>(&As[cur][idx / KQ][(idx % KQ) * 4]) = ra[i];
+    }
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[cur][kk + lk][wm * WM + i * 16 + lr];
+    for (int i = 0; i < B_VEC; ++i) {
+      const int idx = tid + 256 * i;
+      *reinterpret_cast<floatx4*>(&Bs[cur][idx / (BN / 4)][(idx % (BN / 4)) * 4]) = rb[i];
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
 #pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = Bs[cur][kk + lk][wn * WN + j * 16 + lr];
+      for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i] + (kt + 1) * BK);
+#pragma unroll
+      for (int i = 0; i < B_VEC; ++i)
+        rb[i] = *reinterpret_cast<const floatx4*>(b_src[i] + (kt + 1) * b_step);
+    }
+    // 16 k per chunk: in MFMA step j, lane group lg carries k = 16 c + 4 lg + j for both
+    // operands, so one 16-byte read of S gives a lane its operands for four steps.
+#pragma unroll
+    for (int c = 0; c < BK / 16; ++c) {
+      floatx4 a[FM];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
+        a[i] = *reinterpret_cast<const floatx4*>(&As[cur][wm * WM + i * 16 + lr][c * 16 + lg * 4]);
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 4; ++j) {
+        float b[FN];
+#pragma unroll
+        for (int q = 0; q < FN; ++q) b[q] = Bs[cur][c * 16 + lg * 4 + j][wn * WN + q * 16 + lr];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int q = 0; q < FN; ++q)
+            acc[i][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[q], acc[i][q], 0, 0, 0);
+      }
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
+    cur ^= 1;
   }
 
-  // D layout of the 16x16 MFMA: lane holds column (lane & 15), rows 4*(lane >> 4) + v.
+  // Epilogue through LDS: each wavefront parks its (BM/2) x (BN/2) quarter (D layout of the
+  // 16x16 MFMA: lane holds column lane & 15, rows 4 (lane >> 4) + v), then writes it back
+  // row by row with 16-byte stores, 16 lanes per row.
+  __syncthreads();  // every wavefront is done reading the operand buffers
+  float* Es = smem + wave * WM * LDE;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wm * WM + i * 16 + lk * 4 + v, col = wn * WN + j * 16 + lr;
-        Pl[(int64_t)row * n + col] = acc[i][j][v];
-      }
+      for (int v = 0; v < 4; ++v) Es[(i * 16 + lg * 4 + v) * LDE + j * 16 + lr] = acc[i][j][v];
+  __syncthreads();
+  constexpr int LPR = WN / 4;            // lanes per row (16-byte chunks)
+  constexpr int RPI = 64 / LPR;          // rows per store instruction
+  float* Pw = Pl + (int64_t)(wm * WM) * n + wn * WN;
+  const int er = lane / LPR, ec = (lane % LPR) * 4;
+#pragma unroll
+  for (int r0 = 0; r0 < WM; r0 += RPI) {
+    const floatx4 v = *reinterpret_cast<const floatx4*>(&Es[(r0 + er) * LDE + ec]);
+    *reinterpret_cast<floatx4*>(Pw + (int64_t)(r0 + er) * n + ec) = v;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ S,
@@ -161,15 +194,23 @@ hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, 
                            int64_t batch, int tile, hipStream_t stream) {
   if (batch == 0 || m == 0 || n == 0) return hipSuccess;
   if (m % tile || n % tile || k % 16 || (tile != 64 && tile != 128)) return hipErrorInvalidValue;
+  const bool deep = k % 32 == 0;  // K slabs of 32 when K allows, else 16
   const int tiles_n = (int)(n / tile), tiles_per_leaf = (int)((m / tile) * tiles_n);
   const int64_t nblocks = batch * tiles_per_leaf;
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (tile == 128)
-    hipLaunchKernelGGL((k_gemm_f32<128, 128>), dim3((unsigned)nblocks), dim3(256), 0, stream, S, T, P,
-                       (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
+  const dim3 grid((unsigned)nblocks), block(256);
+  if (tile == 128 && deep)
+    hipLaunchKernelGGL((k_gemm_f32<128, 128, 32>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+                       (int)k, tiles_n, tiles_per_leaf, nblocks);
+  else if (tile == 128)
+    hipLaunchKernelGGL((k_gemm_f32<128, 128, 16>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+                       (int)k, tiles_n, tiles_per_leaf, nblocks);
+  else if (deep)
+    hipLaunchKernelGGL((k_gemm_f32<64, 64, 32>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+                       (int)k, tiles_n, tiles_per_leaf, nblocks);
   else
-    hipLaunchKernelGGL((k_gemm_f32<64, 64>), dim3((unsigned)nblocks), dim3(256), 0, stream, S, T, P,
-                       (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
+    hipLaunchKernelGGL((k_gemm_f32<64, 64, 16>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+                       (int)k, tiles_n, tiles_per_leaf, nblocks);
   return hipGetLastError();
 }
 

@@ -7,7 +7,9 @@
 // Both operands are staged k-contiguous in LDS so that every MFMA operand is
 // one 16-byte LDS read (8 consecutive k of one row or column): S slabs are
 // already k-contiguous in memory; T slabs are transposed on the way into LDS,
-// four k rows at a time, so each LDS store writes 8 bytes.
+// four k rows at a time, so each LDS store writes 8 bytes.  Two LDS buffers:
+// a slab held in registers is written to one, one barrier, then the next
+// slab's global loads stay in flight while the MFMAs consume the buffer.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -17,6 +19,8 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   const int64_t per = nb / 8, rem = nb % 8;
@@ -51,54 +55,32 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const uint16_t* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  uint4 ra[A_CHUNKS];
-  uint4 rb[B_GROUPS][4];
-  auto gload = [&](int k0) {
+  // Per-thread slab sources.  S: chunk (tid + 256 i) -> plane, row, 8-element k chunk.
+  // T: group (tid + 256 i) -> plane, 4 k rows, 8 columns.
+  const uint16_t* a_src[A_CHUNKS];
 #pragma unroll
-    for (int i = 0; i < A_CHUNKS; ++i) {
-      const int idx = tid + 256 * i;
-      const int pl = idx / (BM * BK / 8), rem = idx % (BM * BK / 8);
-      const int row = rem / (BK / 8), kc = rem % (BK / 8);
-      ra[i] = *reinterpret_cast<const uint4*>(Sl + pl * plane_s + (int64_t)row * k + k0 + kc * 8);
-    }
+  for (int i = 0; i < A_CHUNKS; ++i) {
+    const int idx = tid + 256 * i;
+    const int pl = idx / (BM * BK / 8), rem = idx % (BM * BK / 8);
+    a_src[i] = Sl + pl * plane_s + (int64_t)(rem / (BK / 8)) * k + (rem % (BK / 8)) * 8;
+  }
+  const uint16_t* b_src[B_GROUPS];
 #pragma unroll
-    for (int i = 0; i < B_GROUPS; ++i) {
-      const int idx = tid + 256 * i;
-      if (B_TOTAL % 256 && idx >= B_TOTAL) break;
-      const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
-      const int kg = rem / (BN / 8), cg = rem % (BN / 8);
+  for (int i = 0; i < B_GROUPS; ++i) {
+    const int idx = (tid + 256 * i) % B_TOTAL;  // threads past B_TOTAL mirror a valid group
+    const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
+    b_src[i] = Tl + pl * plane_t + (int64_t)((rem / (BN / 8)) * 4) * n + (rem % (BN / 8)) * 8;
+  }
+
+  // clang vector types (not HIP's uint4 struct) so the staging stays in registers
+  u32x4 ra[A_CHUNKS];
+  u32x4 rb[B_GROUPS][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        rb[i][r] = *reinterpret_cast<const uint4*>(Tl + pl * plane_t + (int64_t)(k0 + kg * 4 + r) * n + cg * 8);
-    }
-  };
-  auto sstore = [&](int buf) {
+  for (int i = 0; i < A_CHUNKS; ++i) ra[i] = *reinterpret_cast<const u32x4*>(a_src[i]);
 #pragma unroll
-    for (int i = 0; i < A_CHUNKS; ++i) {
-      const int idx = tid + 256 * i;
-      const int pl = idx / (BM * BK / 8), rem = idx % (BM * BK / 8);
-      const int row = rem / (BK / 8), kc = rem % (BK / 8);
-      *reinterpret_cast<uint4*>(&As[buf][pl][row][kc * 8]) = ra[i];
-    }
+  for (int i = 0; i < B_GROUPS; ++i)
 #pragma unroll
-    for (int i = 0; i < B_GROUPS; ++i) {
-      const int idx = tid + 256 * i;
-      if (B_TOTAL % 256 && idx >= B_TOTAL) break;
-      const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
-      const int kg = rem / (BN / 8), cg = rem % (BN / 8);
-      const uint16_t* h0 = reinterpret_cast<const uint16_t*>(&rb[i][0]);
-      const uint16_t* h1 = reinterpret_cast<const uint16_t*>(&rb[i][1]);
-      const uint16_t* h2 = reinterpret_cast<const uint16_t*>(&rb[i][2]);
-      const uint16_t* h3 = reinterpret_cast<const uint16_t*>(&rb[i][3]);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        uint2 w;
-        w.x = (uint32_t)h0[c] | ((uint32_t)h1[c] << 16);
-        w.y = (uint32_t)h2[c] | ((uint32_t)h3[c] << 16);
-        *reinterpret_cast<uint2*>(&Bs[buf][pl][cg * 8 + c][kg * 4]) = w;
-      }
-    }
-  };
+    for (int r = 0; r < 4; ++r) rb[i][r] = *reinterpret_cast<const u32x4*>(b_src[i] + (int64_t)r * n);
 
   floatx4 acc[FM][FN];
 #pragma unroll
@@ -106,14 +88,44 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const uint16_t* __restrict_
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int nk = k / BK;
   const int lr = lane & 15, lg = lane >> 4;
+  int cur = 0;
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+    // registers -> LDS buffer `cur`; T is transposed so that k is contiguous
+#pragma unroll
+    for (int i = 0; i < A_CHUNKS; ++i) {
+      const int idx = tid + 256 * i;
+      const int pl = idx / (BM * BK / 8), rem = idx % (BM * BK / 8);
+      *reinterpret_cast<u32x4*>(&As[cur][pl][rem / (BK / 8)][(rem % (BK / 8)) * 8]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_GROUPS; ++i) {
+      const int idx = tid + 256 * i;
+      if (B_TOTAL % 256 && idx >= B_TOTAL) break;
+      const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
+      const int kg = rem / (BN / 8), cg = rem % (BN / 8);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        // element c of each of the 4 rows: 16-bit halves of 32-bit word c / 2
+        const int w = c >> 1, sh = (c & 1) * 16;
+        u32x2 v;
+        v[0] = ((rb[i][0][w] >> sh) & 0xFFFFu) | (((rb[i][1][w] >> sh) & 0xFFFFu) << 16);
+        v[1] = ((rb[i][2][w] >> sh) & 0xFFFFu) | (((rb[i][3][w] >> sh) & 0xFFFFu) << 16);
+        *reinterpret_cast<u32x2*>(&Bs[cur][pl][cg * 8 + c][kg * 4]) = v;
+      }
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      const int k1 = (kt + 1) * BK;
+#pragma unroll
+      for (int i = 0; i < A_CHUNKS; ++i) ra[i] = *reinterpret_cast<const u32x4*>(a_src[i] + k1);
+#pragma unroll
+      for (int i = 0; i < B_GROUPS; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          rb[i][r] = *reinterpret_cast<const u32x4*>(b_src[i] + (int64_t)(k1 + r) * n);
+    }
     bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
@@ -133,8 +145,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const uint16_t* __restrict_
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
-    if (kt + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
+    cur ^= 1;
   }
 
 #pragma unroll
