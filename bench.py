@@ -8,6 +8,8 @@ and B, the batched leaf GEMM, and the scatter into C, with A and B resident
 in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --workload approx3072     # approximate scheme, bf16 hi+lo leaves
+    python bench.py --copy-calibration BYTES  # plain copy of known size (counter scale)
 """
 
 import argparse
@@ -67,17 +69,90 @@ def cpu_baseline(A, B):
                       "%.2f s" % dt}
 
 
+def _time_steps(fn, steps, warmup):
+    import torch
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn(i)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def approx3072(args):
+    """Approximate scheme at N = 3072: perturbed Strassen (Section 3.1 recipe, sigma = lambda),
+    three levels (343 leaves of 384^3), bf16 hi+lo leaves with f64 recombination, beside the
+    plain f32 recursive form on the same GPU; N(0,1) inputs (seeds 3001/3002)."""
+    import numpy as np
+    import torch
+
+    import paper_1905_07439_amd as rbc
+    import workloads
+
+    n = 3072
+    dev = "cuda:0"
+    A64 = workloads.gaussian((n, n), 3001)
+    B64 = workloads.gaussian((n, n), 3002)
+    A = torch.from_numpy(A64.astype(np.float32)).to(dev)
+    B = torch.from_numpy(B64.astype(np.float32)).to(dev)
+    ref = A.double() @ B.double()
+    C = torch.empty((n, n), dtype=torch.float32, device=dev)
+    S = rbc.Scheme.builtin("strassen")
+    rows = []
+    for lam in (1e-1, 1e-2, 1e-3, 1e-4):
+        P = rbc.Scheme.perturbed(S, lam, 42)
+        for prec in ("bf16x3", "f32"):
+            plan = rbc.Plan(n, n, n, [P] * 3, prec=prec)
+            ws = plan.workspace(dev)
+            for mode in ("none", "full"):
+                ms = _time_steps(lambda i: plan.matmul(A, B, C=C, seed=i % 16, mode=mode, workspace=ws),
+                                 args.steps, args.warmup)
+                errs = []
+                for seed in range(4):
+                    plan.matmul(A, B, C=C, seed=seed, mode=mode, workspace=ws)
+                    errs.append(float(torch.linalg.norm(C.double() - ref) / torch.linalg.norm(ref)))
+                rows.append({"lambda": lam, "prec": prec, "mode": mode, "ms": round(ms, 4),
+                             "tflops": round(2.0 * n ** 3 / ms / 1e9, 2),
+                             "rel_err_vs_fp64": [float("%.3g" % e) for e in errs]})
+    std_ms = _time_steps(lambda i: torch.matmul(A, B, out=C), args.steps, args.warmup)
+    out = {"metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
+           "unit": "TFLOP/s", "n_gpus": 1, "dtype": "bf16x3 leaves / f32 comparator", "data": "synthetic",
+           "config": {"workload": "perturbed Strassen (sigma=lambda) Q=3, N=3072, N(0,1)", "n": n},
+           "rows": rows, "standard_f32_gemm_same_gpu_ms": round(std_ms, 4)}
+    print(json.dumps(out), flush=True)
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of nbytes (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": x.numel() * 4, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="strassen4096", choices=["strassen4096", "approx3072"])
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this library has no multi-GPU path (requested --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
+    if args.workload == "approx3072":
+        return approx3072(args)
 
     import numpy as np
     import torch
