@@ -67,9 +67,14 @@ typedef enum {
 typedef enum {
   RBC_PREC_F64 = 0,    /* f64 everywhere; leaves on v_mfma_f64 */
   RBC_PREC_F32 = 1,    /* f32 everywhere; leaves on v_mfma_f32 */
-  RBC_PREC_BF16X3 = 2  /* f32 combinations; leaf operands split hi+lo in bf16,
+  RBC_PREC_BF16X3 = 2, /* f32 combinations; leaf operands split hi+lo in bf16,
                           3 bf16 MFMA products with f32 accumulation; the
                           W-recombination in f64, C rounded to f32 */
+  RBC_PREC_F16S = 3    /* f32 combinations; each leaf operand scaled by a power
+                          of two (from max|A| or max|B| and the coefficient
+                          1-norms along its path, so that |2^e S| <= 2^15) and
+                          rounded to f16; f16 MFMA with f32 accumulation, the
+                          product unscaled exactly; f32 W-recombination */
 } rbc_prec;
 
 typedef struct rbc_scheme_s* rbc_scheme;
@@ -88,6 +93,8 @@ typedef struct {
   size_t workspace_bytes;   /* minimum workspace for rbc_matmul */
   size_t off_S, off_T, off_P;      /* byte offsets of the leaf operands and products */
   size_t bytes_S, bytes_T, bytes_P;
+  size_t off_aux, bytes_aux;       /* RBC_PREC_F16S: max|A|, max|B| bits (2 x u32), then the
+                                      per-leaf exponents of S and of T (n_leaves int32 each) */
 } rbc_plan_info;
 
 const char* rbc_status_str(rbc_status s);
@@ -145,8 +152,8 @@ rbc_status rbc_fold(rbc_scheme s, const int32_t* signs, const int32_t* perms, in
  * call).  The leaf block sizes are the padded sizes divided by
  * prod b1, prod b2, prod b3, rounded up to the leaf GEMM tile; A and B are
  * zero padded virtually (never copied).  leaf_tile = 0 picks the tile
- * automatically; otherwise it is the square tile edge (f32/bf16x3: 64 or
- * 128; f64: 32 or 64).  levels may be 0 (plain product by the leaf kernel). */
+ * automatically; otherwise it is the square tile edge (f32, bf16x3: 64 or
+ * 128; f16s: 32, 64 or 128; f64: 16).  levels may be 0 (plain product by the leaf kernel). */
 rbc_status rbc_plan_create(int64_t M, int64_t K, int64_t N, int levels, const rbc_scheme* schemes,
                            rbc_prec prec, int leaf_tile, rbc_plan* out);
 rbc_status rbc_plan_get_info(rbc_plan p, rbc_plan_info* info);
@@ -172,7 +179,9 @@ rbc_status rbc_matmul_draws(rbc_plan p, const void* A, int64_t lda, const void* 
  * gather:  which = 0 forms every leaf S (from A), which = 1 every leaf T
  *          (from B), into the workspace at info.off_S / info.off_T, as
  *          n_leaves row-major blocks in leaf order (r_0 slowest).  For
- *          RBC_PREC_BF16X3 the region holds the hi plane then the lo plane.
+ *          RBC_PREC_BF16X3 the region holds the hi plane then the lo plane;
+ *          for RBC_PREC_F16S it holds f16 values and the gather also writes
+ *          the operand's per-leaf exponents in the auxiliary region.
  * leaf:    P_l = S_l T_l for every leaf l into info.off_P.
  * scatter: C from the P blocks through the folded W of every level.
  * The block combinations sum in a fixed order: S_r over (k, l) row-major and

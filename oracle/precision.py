@@ -61,6 +61,28 @@ def split_hi_lo(x, fmt="bf16"):
     return hi, lo
 
 
+def path_norms(schemes, side):
+    """Per leaf (r_0 slowest), the product over levels of the 1-norm of the coefficient
+    column of U (side "A") or V (side "B") used at that level.  Folding only permutes
+    and flips signs, so this bounds |leaf operand| / max|input| for every draw."""
+    norms = [np.sum(np.abs(np.asarray(s[0 if side == "A" else 1], np.float64)), axis=(0, 1)) for s in schemes]
+    g = np.ones(1)
+    for nr in norms:
+        g = (g[:, None] * nr[None, :]).reshape(-1)
+    return g
+
+
+def leaf_exponent(maxabs, G, target=32768.0):
+    """e = floor(log2(target / (G maxabs))) evaluated in float32 (0 when the bound is 0),
+    clamped to [-120, 120]: the power-of-two scale of an f16 leaf operand."""
+    bound = np.float32(G) * np.float32(maxabs)
+    if not (bound > 0 and np.isfinite(bound)):
+        return 0
+    q = np.float32(target) / bound
+    _, x = np.frexp(q)
+    return int(min(max(int(x) - 1, -120), 120))
+
+
 def pow2_scale(maxabs, target):
     """Power of two 2^e with maxabs * 2^e <= target (e chosen as large as possible)."""
     if maxabs == 0 or not np.isfinite(maxabs):

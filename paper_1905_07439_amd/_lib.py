@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "librbc.so")
 
 RBC_OK, RBC_EINVAL, RBC_ESCHEME, RBC_ENOMEM, RBC_EHIP, RBC_EUNSUPPORTED = range(6)
 MODES = {"full": 0, "signs": 1, "perms": 2, "none": 3}
-PRECS = {"f64": 0, "f32": 1, "bf16x3": 2}
+PRECS = {"f64": 0, "f32": 1, "bf16x3": 2, "f16s": 3}
 
 c_i64 = ctypes.c_int64
 c_dbl_p = ctypes.POINTER(ctypes.c_double)
@@ -25,7 +25,8 @@ class PlanInfo(ctypes.Structure):
                 ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t),
                 ("off_S", ctypes.c_size_t), ("off_T", ctypes.c_size_t), ("off_P", ctypes.c_size_t),
-                ("bytes_S", ctypes.c_size_t), ("bytes_T", ctypes.c_size_t), ("bytes_P", ctypes.c_size_t)]
+                ("bytes_S", ctypes.c_size_t), ("bytes_T", ctypes.c_size_t), ("bytes_P", ctypes.c_size_t),
+                ("off_aux", ctypes.c_size_t), ("bytes_aux", ctypes.c_size_t)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

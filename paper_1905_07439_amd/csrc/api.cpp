@@ -162,6 +162,7 @@ rbc_status rbc_plan_get_info(rbc_plan h, rbc_plan_info* info) {
   info->workspace_bytes = p.ws_bytes;
   info->off_S = p.off_S, info->off_T = p.off_T, info->off_P = p.off_P;
   info->bytes_S = p.bytes_S, info->bytes_T = p.bytes_T, info->bytes_P = p.bytes_P;
+  info->off_aux = p.off_aux, info->bytes_aux = p.bytes_aux;
   return RBC_OK;
 }
 
@@ -210,6 +211,12 @@ rbc_status ensure_device(Plan& p) {
     put(t.Vf.data(), t.Vf.size() * 4);
     put(t.Wf.data(), t.Wf.size() * 4);
     put(t.Wkf.data(), t.Wkf.size() * 4);
+  }
+  if (!p.gA.empty()) {
+    put(p.gA.data(), p.gA.size() * 4);
+    p.g_off[0] = p.tab_off.back();
+    put(p.gB.data(), p.gB.size() * 4);
+    p.g_off[1] = p.tab_off.back();
   }
   if (blob.empty()) blob.resize(256);
   void* d = nullptr;
@@ -317,6 +324,16 @@ rbc_status check_ws(const Plan& p, void* ws, size_t bytes) {
 rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx) {
   Plan& p = c.p;
   const bool f64 = p.prec == RBC_PREC_F64;
+  const bool f16s = p.prec == RBC_PREC_F16S;
+  int32_t* exps = nullptr;
+  if (f16s) {
+    uint32_t* maxbits = reinterpret_cast<uint32_t*>(c.ws + p.off_aux) + which;
+    exps = reinterpret_cast<int32_t*>(c.ws + p.off_aux + 256) + (size_t)which * p.n_leaves;
+    const float* G = reinterpret_cast<const float*>(static_cast<const char*>(p.dev_tables) + p.g_off[which]);
+    hipError_t e = launch_leaf_scales(static_cast<const float*>(X), ldx, which == 0 ? p.M : p.K,
+                                      which == 0 ? p.K : p.N, maxbits, G, exps, p.n_leaves, c.stream);
+    if (e != hipSuccess) return fail(RBC_EHIP, "scale launch: %s", hipGetErrorString(e));
+  }
   for (size_t gi = 0; gi < p.groups.size(); ++gi) {
     const Group& g = p.groups[gi];
     const bool last = gi + 1 == p.groups.size();
@@ -340,14 +357,16 @@ rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx) {
     gp.dst_batch = gp.rows_bot * gp.cols_bot;
     gp.n_in = g.n_in;
     const bool bf16_out = last && p.prec == RBC_PREC_BF16X3;
+    const bool f16_out = last && f16s;
     gp.plane = bf16_out ? (int64_t)p.n_leaves * gp.rows_bot * gp.cols_bot : 0;
+    gp.scale_exp = f16_out ? exps : nullptr;
     for (int d = g.d0; d < g.d1; ++d)
       fill_side(p, c.dr, d, which == 0 ? SIDE_A : SIDE_B, f64, false, gp.lev[d - g.d0]);
     const int br = which == 0 ? g.b1 : g.b2, bc = which == 0 ? g.b2 : g.b3;
     const int R = p.Q ? p.levels[g.d0].R : 1;
     const int vec = pick_vec(f64 ? 8 : 4, gp.cols_bot, {gp.ld_src, gp.src_batch, gp.dst_batch, gp.plane},
                              {gp.src, gp.dst}, f64, g.d1 - g.d0);
-    hipError_t e = launch_gather(f64 ? ELT_F64 : ELT_F32, bf16_out ? OUT_BF16X2 : OUT_SAME, vec,
+    hipError_t e = launch_gather(f64 ? ELT_F64 : ELT_F32, bf16_out ? OUT_BF16X2 : (f16_out ? OUT_F16S : OUT_SAME), vec,
                                  g.d1 - g.d0, br, bc, R, gp, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "gather launch: %s", hipGetErrorString(e));
   }
@@ -367,6 +386,12 @@ rbc_status run_leaf(Ctx& c) {
                         reinterpret_cast<const float*>(c.ws + p.off_T),
                         reinterpret_cast<float*>(c.ws + p.off_P), p.mM, p.mN, p.mK, p.n_leaves,
                         p.tile_m, c.stream);
+  else if (p.prec == RBC_PREC_F16S)
+    e = launch_gemm_f16s(reinterpret_cast<const uint16_t*>(c.ws + p.off_S),
+                         reinterpret_cast<const uint16_t*>(c.ws + p.off_T),
+                         reinterpret_cast<float*>(c.ws + p.off_P), p.mM, p.mN, p.mK, p.n_leaves, p.tile_m,
+                         reinterpret_cast<const int32_t*>(c.ws + p.off_aux + 256),
+                         reinterpret_cast<const int32_t*>(c.ws + p.off_aux + 256) + p.n_leaves, c.stream);
   else
     e = launch_gemm_bf16x3(reinterpret_cast<const uint16_t*>(c.ws + p.off_S),
                            reinterpret_cast<const uint16_t*>(c.ws + p.off_T),
@@ -378,7 +403,7 @@ rbc_status run_leaf(Ctx& c) {
 
 rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc) {
   Plan& p = c.p;
-  const bool f64_tabs = p.prec != RBC_PREC_F32;
+  const bool f64_tabs = p.prec == RBC_PREC_F64 || p.prec == RBC_PREC_BF16X3;
   for (size_t gi = p.groups.size(); gi-- > 0;) {
     const Group& g = p.groups[gi];
     const bool last = gi + 1 == p.groups.size();
@@ -399,7 +424,7 @@ rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc) {
     for (int d = g.d0; d < g.d1; ++d) fill_side(p, c.dr, d, SIDE_C, f64_tabs, kappa_scale, sp.lev[d - g.d0]);
     Elt tp, ta, to;
     if (p.prec == RBC_PREC_F64) tp = ta = to = ELT_F64;
-    else if (p.prec == RBC_PREC_F32) tp = ta = to = ELT_F32;
+    else if (p.prec == RBC_PREC_F32 || p.prec == RBC_PREC_F16S) tp = ta = to = ELT_F32;
     else tp = last ? ELT_F32 : ELT_F64, ta = ELT_F64, to = gi == 0 ? ELT_F32 : ELT_F64;
     const int R = p.Q ? p.levels[g.d0].R : 1;
     const int vec = pick_vec(to == ELT_F64 ? 8 : 4, sp.cols_bot, {sp.ld_dst, sp.dst_batch, sp.src_batch},

@@ -82,10 +82,18 @@ template <typename T, int OUTF, int V>
 struct GatherEmit {
   void* dst;
   int64_t dst_batch, plane, off;
+  const int32_t* scale_exp;
   __device__ __forceinline__ void operator()(int64_t idx, VecT<T, V> v) const {
     if constexpr (OUTF == OUT_SAME) {
       // streaming store: the leaf operands are read once, by the next kernel
       vstore<T, V>(static_cast<T*>(dst) + idx * dst_batch + off, v);
+    } else if constexpr (OUTF == OUT_F16S) {
+      // scaled leaf operand: rn_f16(2^e v), e chosen per leaf so nothing overflows
+      const int ex = scale_exp[idx];
+      VecT<uint16_t, V> h;
+#pragma unroll
+      for (int e = 0; e < V; ++e) h[e] = __builtin_bit_cast(uint16_t, (_Float16)ldexpf((float)v[e], ex));
+      vstore<uint16_t, V>(static_cast<uint16_t*>(dst) + idx * dst_batch + off, h);
     } else {
       // leaf operand split: hi = rn_bf16(v), lo = rn_bf16(v - hi) (v - hi is exact in f32)
       VecT<uint16_t, V> hi, lo;
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
           v[s][e] = (row < p.src_rows && col + e < p.src_cols) ? src[row * p.ld_src + col + e] : T(0);
       }
     }
-    GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos};
+    GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, p.scale_exp};
     gather_level<T, V, NL, BR, BC, R, 0>(v, p.lev, in, e);
   }
 }
@@ -339,7 +347,7 @@ hipError_t scatter_dispatch(int vec, int nl, int br, int bc, int R, const Scatte
 }
 
 #define RBC_GATHER_COMBOS(X) \
-  X(double, OUT_SAME) X(float, OUT_SAME) X(float, OUT_BF16X2)
+  X(double, OUT_SAME) X(float, OUT_SAME) X(float, OUT_BF16X2) X(float, OUT_F16S)
 #define RBC_SCATTER_COMBOS(X)                                                          \
   X(double, double, double) X(float, float, float) X(float, double, double)            \
   X(float, double, float) X(double, double, float)

@@ -92,6 +92,11 @@ struct Plan {
   std::vector<LevelTables> tables;
   std::vector<Group> groups;
   size_t ws_bytes = 0, off_S = 0, off_T = 0, off_P = 0, bytes_S = 0, bytes_T = 0, bytes_P = 0;
+  // f16s: auxiliary workspace (max bits, per-leaf exponents) and the per-leaf
+  // path norms G of the A and B sides (product over levels of coefficient 1-norms)
+  size_t off_aux = 0, bytes_aux = 0;
+  std::vector<float> gA, gB;
+  size_t g_off[2] = {0, 0};
   // element sizes: combination precision (gather side), recombination (scatter side)
   int comb_bytes = 4, recomb_bytes = 4;
 

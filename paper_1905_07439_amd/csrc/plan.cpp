@@ -8,6 +8,7 @@
 // folds its products back through W.  Padding (end of Section 2.1.1) is
 // virtual: reads outside A or B return zero, writes outside C are dropped.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 
@@ -49,7 +50,7 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   if (M < 1 || K < 1 || N < 1) return fail(RBC_EINVAL, "empty product %lldx%lldx%lld", (long long)M,
                                           (long long)K, (long long)N);
   if ((int)levels.size() > kMaxLevels) return fail(RBC_EINVAL, "at most %d levels", kMaxLevels);
-  if (prec != RBC_PREC_F64 && prec != RBC_PREC_F32 && prec != RBC_PREC_BF16X3)
+  if (prec != RBC_PREC_F64 && prec != RBC_PREC_F32 && prec != RBC_PREC_BF16X3 && prec != RBC_PREC_F16S)
     return fail(RBC_EUNSUPPORTED, "precision %d not implemented", (int)prec);
   Plan p;
   p.M = M, p.K = K, p.N = N;
@@ -70,6 +71,19 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     if (leaf_tile == 0) leaf_tile = 16;
     if (leaf_tile != 16) return fail(RBC_EUNSUPPORTED, "f64 leaf tile must be 16");
     p.tile_m = p.tile_n = 16, p.tile_k = 4;
+  } else if (prec == RBC_PREC_F16S) {
+    if (leaf_tile == 0) {
+      // the tile with the least padded leaf area (ties: the larger tile)
+      int64_t best = -1;
+      for (int t : {128, 64, 32}) {
+        const int64_t area = round_up(lm, t) * round_up(ln, t);
+        if (best < 0 || area < best) best = area, leaf_tile = t;
+      }
+    }
+    if (leaf_tile != 32 && leaf_tile != 64 && leaf_tile != 128)
+      return fail(RBC_EUNSUPPORTED, "f16s leaf tile must be 32, 64 or 128");
+    p.tile_m = p.tile_n = leaf_tile;
+    p.tile_k = 32;
   } else {
     if (leaf_tile == 0) {
       // 128 unless it pads the leaf by more than 1/8
@@ -87,8 +101,9 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   p.Mp = p.mM * P1, p.Kp = p.mK * P2, p.Np = p.mN * P3;
 
   p.comb_bytes = prec == RBC_PREC_F64 ? 8 : 4;
-  p.recomb_bytes = prec == RBC_PREC_F32 ? 4 : 8;
-  const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : 4;  // bf16x3: hi + lo planes of 2 bytes
+  p.recomb_bytes = (prec == RBC_PREC_F64 || prec == RBC_PREC_BF16X3) ? 8 : 4;
+  // bf16x3: hi + lo planes of 2 bytes; f16s: one plane of 2 bytes
+  const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : (prec == RBC_PREC_F16S ? 2 : 4);
   const int prod_bytes = prec == RBC_PREC_F64 ? 8 : 4;
 
   // Fused groups, formed from the deepest level upwards so that the
@@ -153,6 +168,27 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     g.off_a_bot = off, off = align256(off + nb * g.a_rows_bot * g.a_cols_bot * p.comb_bytes);
     g.off_b_bot = off, off = align256(off + nb * g.b_rows_bot * g.b_cols_bot * p.comb_bytes);
     g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * p.recomb_bytes);
+  }
+  if (prec == RBC_PREC_F16S) {
+    p.off_aux = off;
+    p.bytes_aux = 256 + 2 * (size_t)p.n_leaves * 4;
+    off = align256(off + p.bytes_aux);
+    // per-leaf path norms: leaf l = (r_0, ..., r_{Q-1}), r_{Q-1} fastest
+    p.gA.assign(p.n_leaves, 1.0f), p.gB.assign(p.n_leaves, 1.0f);
+    for (int64_t l = 0; l < p.n_leaves; ++l) {
+      double ga = 1.0, gb = 1.0;
+      int64_t rem = l;
+      for (int d = p.Q - 1; d >= 0; --d) {
+        const Scheme& s = levels[d];
+        const int r = (int)(rem % s.R);
+        rem /= s.R;
+        double nu = 0, nv = 0;
+        for (int i = 0; i < s.b1 * s.b2; ++i) nu += std::fabs(s.U[i * s.R + r]);
+        for (int i = 0; i < s.b2 * s.b3; ++i) nv += std::fabs(s.V[i * s.R + r]);
+        ga *= nu, gb *= nv;
+      }
+      p.gA[l] = (float)ga, p.gB[l] = (float)gb;
+    }
   }
   p.ws_bytes = std::max<size_t>(off, 256);
 

@@ -317,6 +317,52 @@ def test_bf16x3_end_to_end():
     assert e <= 1.5 * e_emu + 2e-7 and e <= 1e-4
 
 
+F16S_CASES = [(["laderman", "strassen"], 480, 480, 480, 0), (["laderman"], 192, 192, 192, 0),
+              (["strassen", "strassen"], 300, 260, 200, 32), (["laderman", "strassen", "strassen"], 1152, 1152, 1152, 0)]
+
+
+@pytest.mark.parametrize("case", range(len(F16S_CASES)))
+def test_f16s_scaled_leaves(case):
+    # f16 leaves with per-leaf power-of-two scales: exponents and scaled operands are
+    # bit-identical to the oracle's; the product is within the f16 emulation's error.
+    names, M, K, N, tile = F16S_CASES[case]
+    _say("f16s", names, M, K, N)
+    lib_s, ref_s = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec="f16s", leaf_tile=tile)
+    info = plan.info
+    A = workloads.scaled_gaussian((M, K), 4000 + case).astype(np.float32)
+    B = workloads.scaled_gaussian((K, N), 4100 + case).astype(np.float32)
+    s, p, dr = _level_draws(plan, ref_s, 7, "full")
+    ws = torch.zeros(info["workspace_bytes"], dtype=torch.uint8, device=DEV)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    plan.stage_gather(0, Ad, s, p, ws)
+    plan.stage_gather(1, Bd, s, p, ws)
+    torch.cuda.synchronize()
+    L, mM, mK, mN = info["n_leaves"], info["mM"], info["mK"], info["mN"]
+    Sg = _region(ws, info["off_S"], info["bytes_S"], torch.int16, (L, mM, mK)).view(np.float16)
+    Tg = _region(ws, info["off_T"], info["bytes_T"], torch.int16, (L, mK, mN)).view(np.float16)
+    ex = _region(ws, info["off_aux"] + 256, 2 * L * 4, torch.int32, (2, L))
+    dims = (mM, mK, mN)
+    ops = recursion.leaf_operands(A, B, ref_s, dr, arith="f32", leaf_dims=dims)
+    gA, gB = precision.path_norms(ref_s, "A"), precision.path_norms(ref_s, "B")
+    mA, mB = float(np.max(np.abs(A))), float(np.max(np.abs(B)))
+    prods = []
+    for l, (S, T) in enumerate(ops):
+        eA, eB = precision.leaf_exponent(mA, gA[l]), precision.leaf_exponent(mB, gB[l])
+        assert (ex[0, l], ex[1, l]) == (eA, eB), l
+        S16 = np.ldexp(S, eA).astype(np.float16)
+        T16 = np.ldexp(T, eB).astype(np.float16)
+        np.testing.assert_array_equal(Sg[l].view(np.uint16), S16.view(np.uint16))
+        np.testing.assert_array_equal(Tg[l].view(np.uint16), T16.view(np.uint16))
+        prods.append(np.ldexp(S16.astype(np.float64) @ T16.astype(np.float64), -(eA + eB)).astype(np.float32))
+    emu = recursion.combine(prods, M, N, K, ref_s, dr, arith="f32", leaf_dims=dims)
+    C = plan.matmul(Ad, Bd, seed=7).cpu().numpy()
+    AB = A.astype(np.float64) @ B.astype(np.float64)
+    e, e_emu = recursion.rel_err(C, AB), recursion.rel_err(emu, AB)
+    _say("f16s rel err %.3g, emulation %.3g" % (e, e_emu))
+    assert e <= 1.1 * e_emu + 1e-6 and e < 2e-2
+
+
 def test_results_are_deterministic_and_stream_ordered():
     _say("determinism")
     lib_s, _ = _schemes(["strassen"] * 3)

@@ -141,6 +141,19 @@ def test_plan_geometry():
     assert z.info["n_leaves"] == 1 and z.info["mM"] == 128 and z.info["n_groups"] == 1
 
 
+def test_f16s_plan_geometry():
+    L = rbc.Scheme.builtin("laderman")
+    S = rbc.Scheme.builtin("strassen")
+    p = rbc.Plan(480, 480, 480, [L, S], prec="f16s")
+    i = p.info
+    # leaf 80: tile 32 pads it to 96 (least padded area), K to a multiple of 32
+    assert (i["mM"], i["mK"], i["mN"], i["tile_m"]) == (96, 96, 96, 32)
+    assert i["bytes_S"] == 161 * 96 * 96 * 2
+    assert i["bytes_aux"] == 256 + 2 * 161 * 4 and i["off_aux"] >= i["off_P"] + i["bytes_P"]
+    q = rbc.Plan(768, 768, 768, [L, S], prec="f16s")
+    assert q.info["tile_m"] == 128 and q.info["mM"] == 128
+
+
 def test_plan_errors():
     S = rbc.Scheme.builtin("strassen")
     with pytest.raises(rbc.RbcError) as e:

@@ -39,3 +39,24 @@ def test_split_hi_lo_bf16_recovers_16_bits():
     hi, lo = precision.split_hi_lo(x, "bf16")
     rel = np.abs((hi.astype(np.float64) + lo) - x) / np.abs(x)
     assert rel.max() <= 2.0 ** -16
+
+
+def test_leaf_exponent_keeps_scaled_values_in_range():
+    rng = np.random.default_rng(1)
+    for _ in range(2000):
+        mx = float(np.float32(10 ** rng.uniform(-8, 8)))
+        G = float(rng.integers(1, 400))
+        e = precision.leaf_exponent(mx, G)
+        assert G * mx * 2.0 ** e <= 32768.0 * (1 + 2.0 ** -20)  # not above 2^15 (float32 rounding)
+        assert G * mx * 2.0 ** (e + 1) > 32768.0 * (1 - 1e-6)  # and the largest such power
+    assert precision.leaf_exponent(0.0, 5.0) == 0
+
+
+def test_path_norms_strassen_laderman():
+    from oracle import schemes
+    S, L = schemes.strassen(), schemes.laderman()
+    gA = precision.path_norms([L, S], "A")
+    assert gA.shape == (23 * 7,)
+    # Laderman product 1 uses 7 blocks of A, Strassen product 1 uses 2
+    assert gA[0] == 7 * 2
+    assert precision.path_norms([S], "B").tolist() == [2, 1, 2, 2, 1, 2, 2]
