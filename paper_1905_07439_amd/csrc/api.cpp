@@ -13,6 +13,7 @@
 
 #include "core.hpp"
 #include "kernels.hpp"
+#include "launches.hpp"
 
 namespace rbc {
 const char* last_error_text();
@@ -186,126 +187,6 @@ void rbc_plan_destroy(rbc_plan h) {
 
 namespace {
 
-// Upload the coefficient tables of every level on first use on a device.
-rbc_status ensure_device(Plan& p) {
-  int dev = -1;
-  HIP_CHECK(hipGetDevice(&dev));
-  if (p.dev_tables) {
-    if (dev != p.device) return fail(RBC_EINVAL, "plan was first used on device %d, now %d", p.device, dev);
-    return RBC_OK;
-  }
-  std::vector<char> blob;
-  p.tab_off.clear();
-  auto put = [&](const void* src, size_t bytes) {
-    const size_t off = (blob.size() + 255) & ~size_t(255);
-    blob.resize(off + bytes);
-    std::memcpy(blob.data() + off, src, bytes);
-    p.tab_off.push_back(off);
-  };
-  for (const LevelTables& t : p.tables) {
-    put(t.U.data(), t.U.size() * 8);
-    put(t.V.data(), t.V.size() * 8);
-    put(t.W.data(), t.W.size() * 8);
-    put(t.Wk.data(), t.Wk.size() * 8);
-    put(t.Uf.data(), t.Uf.size() * 4);
-    put(t.Vf.data(), t.Vf.size() * 4);
-    put(t.Wf.data(), t.Wf.size() * 4);
-    put(t.Wkf.data(), t.Wkf.size() * 4);
-  }
-  if (!p.gA.empty()) {
-    put(p.gA.data(), p.gA.size() * 4);
-    p.g_off[0] = p.tab_off.back();
-    put(p.gB.data(), p.gB.size() * 4);
-    p.g_off[1] = p.tab_off.back();
-  }
-  if (blob.empty()) blob.resize(256);
-  void* d = nullptr;
-  HIP_CHECK(hipMalloc(&d, blob.size()));
-  hipError_t e = hipMemcpy(d, blob.data(), blob.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(d);
-    return fail(RBC_EHIP, "table upload: %s", hipGetErrorString(e));
-  }
-  p.dev_tables = d;
-  p.device = dev;
-  return RBC_OK;
-}
-
-const void* table(const Plan& p, int level, TabKind kind, bool f64) {
-  const size_t idx = (size_t)level * 8 + (f64 ? 0 : 4) + (size_t)kind;
-  return static_cast<const char*>(p.dev_tables) + p.tab_off[idx];
-}
-
-// Per-level draw pointers into the concatenated arrays.
-struct Draws {
-  std::vector<int32_t> s, pm;
-  std::vector<size_t> off;
-};
-
-rbc_status check_draws(const Plan& p, const int32_t* signs, const int32_t* perms, Draws& d) {
-  if (p.Q > 0 && (!signs || !perms)) return fail(RBC_EINVAL, "null draw arrays");
-  size_t o = 0;
-  d.off.clear();
-  for (int l = 0; l < p.Q; ++l) {
-    const Scheme& s = p.levels[l];
-    if (!valid_draw(s.b1, s.b2, s.b3, signs + o, perms + o))
-      return fail(RBC_EINVAL, "invalid draw at level %d", l);
-    d.off.push_back(o);
-    o += s.b1 + s.b2 + s.b3;
-  }
-  d.s.assign(signs, signs + o);
-  d.pm.assign(perms, perms + o);
-  return RBC_OK;
-}
-
-enum Side { SIDE_A, SIDE_B, SIDE_C };
-
-// Positions per thread for a combination launch: the widest of 4, 2, 1 that
-// divides the block width, every leading dimension and block stride, and the
-// element alignment of every pointer.  8-byte accumulators use at most 2, and
-// 1 in two-level groups (register budget).
-// RBC_COMBINE_VEC (1, 2 or 4) lowers the cap for tuning.
-int max_vec_override() {
-  static const int v = [] {
-    const char* e = std::getenv("RBC_COMBINE_VEC");
-    const int x = e ? std::atoi(e) : 4;
-    return (x == 1 || x == 2 || x == 4) ? x : 4;
-  }();
-  return v;
-}
-
-int pick_vec(int elt_bytes, int64_t cols, std::initializer_list<int64_t> strides,
-             std::initializer_list<const void*> ptrs, bool wide_acc, int nl) {
-  const int cap = std::min(wide_acc ? (nl >= 2 ? 1 : 2) : 4, max_vec_override());
-  for (int v = cap; v > 1; v /= 2) {
-    bool ok = cols % v == 0;
-    for (int64_t s : strides) ok = ok && s % v == 0;
-    for (const void* q : ptrs) ok = ok && reinterpret_cast<uintptr_t>(q) % (size_t)(v * elt_bytes) == 0;
-    if (ok) return v;
-  }
-  return 1;
-}
-
-void fill_side(const Plan& p, const Draws& dr, int level, Side side, bool f64, bool kappa_scale,
-               SideLevel& L) {
-  const Scheme& s = p.levels[level];
-  const int32_t* sg = dr.s.data() + dr.off[level];
-  const int32_t* pm = dr.pm.data() + dr.off[level];
-  const int32_t *s1 = sg, *s2 = sg + s.b1, *s3 = sg + s.b1 + s.b2;
-  const int32_t *p1 = pm, *p2 = pm + s.b1, *p3 = pm + s.b1 + s.b2;
-  const int32_t *sr, *sc, *pr, *pc;
-  int nr, nc;
-  TabKind kind;
-  if (side == SIDE_A) sr = s1, sc = s2, pr = p1, pc = p2, nr = s.b1, nc = s.b2, kind = TAB_U;
-  else if (side == SIDE_B) sr = s2, sc = s3, pr = p2, pc = p3, nr = s.b2, nc = s.b3, kind = TAB_V;
-  else sr = s1, sc = s3, pr = p1, pc = p3, nr = s.b1, nc = s.b3, kind = kappa_scale ? TAB_WK : TAB_W;
-  std::memset(&L, 0, sizeof L);
-  for (int i = 0; i < nr; ++i) L.pr[i] = (int8_t)pr[i], L.sr[i] = (int8_t)sr[i];
-  for (int j = 0; j < nc; ++j) L.pc[j] = (int8_t)pc[j], L.sc[j] = (int8_t)sc[j];
-  L.R = s.R;
-  L.tab = table(p, level, kind, f64);
-}
-
 struct Ctx {
   Plan& p;
   char* ws;
@@ -313,123 +194,32 @@ struct Ctx {
   Draws dr;
 };
 
-rbc_status check_ws(const Plan& p, void* ws, size_t bytes) {
-  if (!ws) return fail(RBC_EINVAL, "null workspace");
-  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(RBC_EINVAL, "workspace not 256-byte aligned");
-  if (bytes < p.ws_bytes)
-    return fail(RBC_ENOMEM, "workspace of %zu bytes, plan needs %zu", bytes, p.ws_bytes);
-  return RBC_OK;
-}
-
 rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx) {
-  Plan& p = c.p;
-  const bool f64 = p.prec == RBC_PREC_F64;
-  const bool f16s = p.prec == RBC_PREC_F16S;
-  int32_t* exps = nullptr;
-  if (f16s) {
-    uint32_t* maxbits = reinterpret_cast<uint32_t*>(c.ws + p.off_aux) + which;
-    exps = reinterpret_cast<int32_t*>(c.ws + p.off_aux + 256) + (size_t)which * p.n_leaves;
-    const float* G = reinterpret_cast<const float*>(static_cast<const char*>(p.dev_tables) + p.g_off[which]);
-    hipError_t e = launch_leaf_scales(static_cast<const float*>(X), ldx, which == 0 ? p.M : p.K,
-                                      which == 0 ? p.K : p.N, maxbits, G, exps, p.n_leaves, c.stream);
+  std::vector<ScaleLaunch> scale;
+  std::vector<GatherLaunch> gl;
+  build_gather(c.p, c.dr, which, X, ldx, c.ws, scale, gl);
+  for (const ScaleLaunch& l : scale) {
+    hipError_t e = launch(l, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "scale launch: %s", hipGetErrorString(e));
   }
-  for (size_t gi = 0; gi < p.groups.size(); ++gi) {
-    const Group& g = p.groups[gi];
-    const bool last = gi + 1 == p.groups.size();
-    GatherParams gp;
-    std::memset(&gp, 0, sizeof gp);
-    const int64_t rows_top = which == 0 ? g.a_rows_top : g.b_rows_top;
-    const int64_t cols_top = which == 0 ? g.a_cols_top : g.b_cols_top;
-    if (gi == 0) {
-      gp.src = X, gp.ld_src = ldx, gp.src_batch = 0;
-      gp.src_rows = which == 0 ? p.M : p.K;
-      gp.src_cols = which == 0 ? p.K : p.N;
-    } else {
-      const Group& up = p.groups[gi - 1];
-      gp.src = c.ws + (which == 0 ? up.off_a_bot : up.off_b_bot);
-      gp.ld_src = cols_top, gp.src_batch = rows_top * cols_top;
-      gp.src_rows = rows_top, gp.src_cols = cols_top;
-    }
-    gp.rows_bot = which == 0 ? g.a_rows_bot : g.b_rows_bot;
-    gp.cols_bot = which == 0 ? g.a_cols_bot : g.b_cols_bot;
-    gp.dst = c.ws + (which == 0 ? g.off_a_bot : g.off_b_bot);
-    gp.dst_batch = gp.rows_bot * gp.cols_bot;
-    gp.n_in = g.n_in;
-    const bool bf16_out = last && p.prec == RBC_PREC_BF16X3;
-    const bool f16_out = last && f16s;
-    gp.plane = bf16_out ? (int64_t)p.n_leaves * gp.rows_bot * gp.cols_bot : 0;
-    gp.scale_exp = f16_out ? exps : nullptr;
-    for (int d = g.d0; d < g.d1; ++d)
-      fill_side(p, c.dr, d, which == 0 ? SIDE_A : SIDE_B, f64, false, gp.lev[d - g.d0]);
-    const int br = which == 0 ? g.b1 : g.b2, bc = which == 0 ? g.b2 : g.b3;
-    const int R = p.Q ? p.levels[g.d0].R : 1;
-    const int vec = pick_vec(f64 ? 8 : 4, gp.cols_bot, {gp.ld_src, gp.src_batch, gp.dst_batch, gp.plane},
-                             {gp.src, gp.dst}, f64, g.d1 - g.d0);
-    hipError_t e = launch_gather(f64 ? ELT_F64 : ELT_F32, bf16_out ? OUT_BF16X2 : (f16_out ? OUT_F16S : OUT_SAME), vec,
-                                 g.d1 - g.d0, br, bc, R, gp, c.stream);
+  for (const GatherLaunch& l : gl) {
+    hipError_t e = launch(l, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "gather launch: %s", hipGetErrorString(e));
   }
   return RBC_OK;
 }
 
 rbc_status run_leaf(Ctx& c) {
-  Plan& p = c.p;
-  hipError_t e;
-  if (p.prec == RBC_PREC_F64)
-    e = launch_gemm_f64(reinterpret_cast<const double*>(c.ws + p.off_S),
-                        reinterpret_cast<const double*>(c.ws + p.off_T),
-                        reinterpret_cast<double*>(c.ws + p.off_P), p.mM, p.mN, p.mK, p.n_leaves,
-                        c.stream);
-  else if (p.prec == RBC_PREC_F32)
-    e = launch_gemm_f32(reinterpret_cast<const float*>(c.ws + p.off_S),
-                        reinterpret_cast<const float*>(c.ws + p.off_T),
-                        reinterpret_cast<float*>(c.ws + p.off_P), p.mM, p.mN, p.mK, p.n_leaves,
-                        p.tile_m, c.stream);
-  else if (p.prec == RBC_PREC_F16S)
-    e = launch_gemm_f16s(reinterpret_cast<const uint16_t*>(c.ws + p.off_S),
-                         reinterpret_cast<const uint16_t*>(c.ws + p.off_T),
-                         reinterpret_cast<float*>(c.ws + p.off_P), p.mM, p.mN, p.mK, p.n_leaves, p.tile_m,
-                         reinterpret_cast<const int32_t*>(c.ws + p.off_aux + 256),
-                         reinterpret_cast<const int32_t*>(c.ws + p.off_aux + 256) + p.n_leaves, c.stream);
-  else
-    e = launch_gemm_bf16x3(reinterpret_cast<const uint16_t*>(c.ws + p.off_S),
-                           reinterpret_cast<const uint16_t*>(c.ws + p.off_T),
-                           reinterpret_cast<float*>(c.ws + p.off_P), p.mM, p.mN, p.mK, p.n_leaves,
-                           p.tile_m, c.stream);
+  hipError_t e = launch(build_leaf(c.p, c.ws), c.stream);
   if (e != hipSuccess) return fail(RBC_EHIP, "leaf launch: %s", hipGetErrorString(e));
   return RBC_OK;
 }
 
 rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc) {
-  Plan& p = c.p;
-  const bool f64_tabs = p.prec == RBC_PREC_F64 || p.prec == RBC_PREC_BF16X3;
-  for (size_t gi = p.groups.size(); gi-- > 0;) {
-    const Group& g = p.groups[gi];
-    const bool last = gi + 1 == p.groups.size();
-    ScatterParams sp;
-    std::memset(&sp, 0, sizeof sp);
-    sp.src = c.ws + g.off_c_bot;
-    sp.rows_bot = g.c_rows_bot, sp.cols_bot = g.c_cols_bot;
-    sp.src_batch = sp.rows_bot * sp.cols_bot;
-    if (gi == 0) {
-      sp.dst = C, sp.ld_dst = ldc, sp.dst_batch = 0, sp.dst_rows = p.M, sp.dst_cols = p.N;
-    } else {
-      const Group& up = p.groups[gi - 1];
-      sp.dst = c.ws + up.off_c_bot;
-      sp.ld_dst = g.c_cols_top, sp.dst_batch = g.c_rows_top * g.c_cols_top;
-      sp.dst_rows = g.c_rows_top, sp.dst_cols = g.c_cols_top;
-    }
-    sp.n_out = g.n_in;
-    for (int d = g.d0; d < g.d1; ++d) fill_side(p, c.dr, d, SIDE_C, f64_tabs, kappa_scale, sp.lev[d - g.d0]);
-    Elt tp, ta, to;
-    if (p.prec == RBC_PREC_F64) tp = ta = to = ELT_F64;
-    else if (p.prec == RBC_PREC_F32 || p.prec == RBC_PREC_F16S) tp = ta = to = ELT_F32;
-    else tp = last ? ELT_F32 : ELT_F64, ta = ELT_F64, to = gi == 0 ? ELT_F32 : ELT_F64;
-    const int R = p.Q ? p.levels[g.d0].R : 1;
-    const int vec = pick_vec(to == ELT_F64 ? 8 : 4, sp.cols_bot, {sp.ld_dst, sp.dst_batch, sp.src_batch},
-                             {sp.src, sp.dst}, ta == ELT_F64, g.d1 - g.d0);
-    hipError_t e = launch_scatter(tp, ta, to, vec, g.d1 - g.d0, g.b1, g.b3, R, sp, c.stream);
+  std::vector<ScatterLaunch> sl;
+  build_scatter(c.p, c.dr, kappa_scale, C, ldc, c.ws, sl);
+  for (const ScatterLaunch& l : sl) {
+    hipError_t e = launch(l, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "scatter launch: %s", hipGetErrorString(e));
   }
   return RBC_OK;
@@ -469,18 +259,6 @@ rbc_status matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, int64
   if ((st = record(p, c.stream, 4)) != RBC_OK) return st;
   if (p.timing) ++p.recorded;
   return RBC_OK;
-}
-
-void seeded_draws(const Plan& p, uint64_t seed, rbc_mode mode, std::vector<int32_t>& s,
-                  std::vector<int32_t>& pm) {
-  s.clear(), pm.clear();
-  for (int d = 0; d < p.Q; ++d) {
-    const Scheme& sc = p.levels[d];
-    const int n = sc.b1 + sc.b2 + sc.b3;
-    const size_t o = s.size();
-    s.resize(o + n), pm.resize(o + n);
-    draw_level(seed, d, sc.b1, sc.b2, sc.b3, mode, s.data() + o, pm.data() + o);
-  }
 }
 
 }  // namespace

@@ -152,41 +152,48 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
   }
 }
 
+// One workgroup's share of a gather: 256 threads x V positions (block bx of
+// the position range) of top block `in`.  Used by k_gather and by the batch
+// engine's persistent kernel.
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
-__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
+__device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, int64_t in) {
   constexpr int BB = BR * BC;
   constexpr int NSRC = ipow(BB, NL);
   const int64_t npos = p.rows_bot * p.cols_bot;
-  const int64_t pos = ((int64_t)blockIdx.x * 256 + threadIdx.x) * V;
+  const int64_t pos = (bx * 256 + threadIdx.x) * V;
   if (pos >= npos) return;
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;  // cols_bot % V == 0
-  for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
-    const T* src = static_cast<const T*>(p.src) + in * p.src_batch;
-    VecT<T, V> v[NSRC];
+  const T* src = static_cast<const T*>(p.src) + in * p.src_batch;
+  VecT<T, V> v[NSRC];
 #pragma unroll
-    for (int s = 0; s < NSRC; ++s) {
-      int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
-      int rem = s;
+  for (int s = 0; s < NSRC; ++s) {
+    int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
+    int rem = s;
 #pragma unroll
-      for (int t = 0; t < NL; ++t) {  // least significant digit = deepest level
-        const int d = rem % BB;
-        rem /= BB;
-        row += (d / BC) * hs;
-        col += (d % BC) * ws;
-        hs *= BR;
-        ws *= BC;
-      }
-      if (row < p.src_rows && col + V <= p.src_cols) {
-        v[s] = vload<T, V>(src + row * p.ld_src + col);  // aligned: checked by the host
-      } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e)
-          v[s][e] = (row < p.src_rows && col + e < p.src_cols) ? src[row * p.ld_src + col + e] : T(0);
-      }
+    for (int t = 0; t < NL; ++t) {  // least significant digit = deepest level
+      const int d = rem % BB;
+      rem /= BB;
+      row += (d / BC) * hs;
+      col += (d % BC) * ws;
+      hs *= BR;
+      ws *= BC;
     }
-    GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, p.scale_exp};
-    gather_level<T, V, NL, BR, BC, R, 0>(v, p.lev, in, e);
+    if (row < p.src_rows && col + V <= p.src_cols) {
+      v[s] = vload<T, V>(src + row * p.ld_src + col);  // aligned: checked by the host
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; ++e)
+        v[s][e] = (row < p.src_rows && col + e < p.src_cols) ? src[row * p.ld_src + col + e] : T(0);
+    }
   }
+  GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, p.scale_exp};
+  gather_level<T, V, NL, BR, BC, R, 0>(v, p.lev, in, e);
+}
+
+template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
+__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
+  for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y)
+    gather_block<T, OUTF, V, NL, BR, BC, R>(p, blockIdx.x, in);
 }
 
 // Level LT of a scatter group: returns in `out` the BB^(NL-LT) values of the
@@ -230,44 +237,50 @@ __device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, 
   }
 }
 
+// One workgroup's share of a scatter: 256 threads x V positions (block bx)
+// of top block o.
 template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
-__global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
+__device__ __forceinline__ void scatter_block(const ScatterParams& p, int64_t bx, int64_t o) {
   constexpr int BB = BR * BC;
   constexpr int NOUT = ipow(BB, NL);
   const int64_t npos = p.rows_bot * p.cols_bot;
-  const int64_t pos = ((int64_t)blockIdx.x * 256 + threadIdx.x) * V;
+  const int64_t pos = (bx * 256 + threadIdx.x) * V;
   if (pos >= npos) return;
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
   const TP* src = static_cast<const TP*>(p.src);
-  for (int64_t o = blockIdx.y; o < p.n_out; o += gridDim.y) {
-    VecT<TA, V> out[NOUT];
-    scatter_level<TP, TA, V, NL, BR, BC, R, 0>(src, p.src_batch, pos, p.lev, o, out);
-    TO* dst = static_cast<TO*>(p.dst) + o * p.dst_batch;
+  VecT<TA, V> out[NOUT];
+  scatter_level<TP, TA, V, NL, BR, BC, R, 0>(src, p.src_batch, pos, p.lev, o, out);
+  TO* dst = static_cast<TO*>(p.dst) + o * p.dst_batch;
 #pragma unroll
-    for (int s = 0; s < NOUT; ++s) {
-      int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
-      int rem = s;
+  for (int s = 0; s < NOUT; ++s) {
+    int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
+    int rem = s;
 #pragma unroll
-      for (int t = 0; t < NL; ++t) {
-        const int d = rem % BB;
-        rem /= BB;
-        row += (d / BC) * hs;
-        col += (d % BC) * ws;
-        hs *= BR;
-        ws *= BC;
-      }
-      VecT<TO, V> w;
+    for (int t = 0; t < NL; ++t) {
+      const int d = rem % BB;
+      rem /= BB;
+      row += (d / BC) * hs;
+      col += (d % BC) * ws;
+      hs *= BR;
+      ws *= BC;
+    }
+    VecT<TO, V> w;
 #pragma unroll
-      for (int e = 0; e < V; ++e) w[e] = (TO)out[s][e];
-      if (row < p.dst_rows && col + V <= p.dst_cols) {
-        *reinterpret_cast<VecT<TO, V>*>(dst + row * p.ld_dst + col) = w;  // aligned: checked by the host
-      } else {
+    for (int e = 0; e < V; ++e) w[e] = (TO)out[s][e];
+    if (row < p.dst_rows && col + V <= p.dst_cols) {
+      *reinterpret_cast<VecT<TO, V>*>(dst + row * p.ld_dst + col) = w;  // aligned: checked by the host
+    } else {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (row < p.dst_rows && col + e < p.dst_cols) dst[row * p.ld_dst + col + e] = w[e];
-      }
+      for (int e = 0; e < V; ++e)
+        if (row < p.dst_rows && col + e < p.dst_cols) dst[row * p.ld_dst + col + e] = w[e];
     }
   }
+}
+
+template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
+__global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
+  for (int64_t o = blockIdx.y; o < p.n_out; o += gridDim.y)
+    scatter_block<TP, TA, TO, V, NL, BR, BC, R>(p, blockIdx.x, o);
 }
 
 inline dim3 grid_for(int64_t npos, int64_t nbatch) {

@@ -20,148 +20,22 @@
 // read straight from global memory (small leaves; latency bound).
 #include <hip/hip_runtime.h>
 
-#include "kernels.hpp"
+#include "gemm_tiles.hpp"
 
 namespace rbc {
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
-// Block id -> logical tile id such that consecutive logical tiles share an XCD.
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
-  const int64_t per = nb / 8, rem = nb % 8;
-  const int64_t xcd = bid % 8, local = bid / 8;
-  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
-}
+using tiles::doublex4;
+using tiles::F32Tile;
 
 template <int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ S,
                                                   const float* __restrict__ T, float* __restrict__ P,
                                                   int m, int n, int k, int tiles_n,
                                                   int tiles_per_leaf, int64_t nblocks) {
-  constexpr int LDA = BK + 4;                 // S slab row: k-contiguous, padded
-  constexpr int LDB = BN + 4;                 // T slab row: n-contiguous, padded
-  constexpr int WM = BM / 2, WN = BN / 2;
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int KQ = BK / 4;                  // float4 chunks per S row of a slab
-  constexpr int A_VEC = BM * KQ / 256;        // float4 loads per thread per slab
-  constexpr int B_VEC = BK * (BN / 4) / 256;
-  constexpr int LDE = WN + 4;                 // epilogue row of a wavefront's quarter
-  static_assert(A_VEC >= 1 && B_VEC >= 1, "tile too small for 256 threads");
-  // One LDS block: two S and two T slab buffers during the K loop, the four
-  // wavefronts' output quarters in the epilogue.
-  constexpr int A_FLOATS = 2 * BM * LDA, B_FLOATS = 2 * BK * LDB, E_FLOATS = 4 * WM * LDE;
-  constexpr int SMEM = A_FLOATS + B_FLOATS > E_FLOATS ? A_FLOATS + B_FLOATS : E_FLOATS;
-  __shared__ __attribute__((aligned(16))) float smem[SMEM];
-  float(*As)[BM][LDA] = reinterpret_cast<float(*)[BM][LDA]>(smem);
-  float(*Bs)[BK][LDB] = reinterpret_cast<float(*)[BK][LDB]>(smem + A_FLOATS);
-
-  const int64_t bid = xcd_remap(blockIdx.x, nblocks);
-  const int64_t leaf = bid / tiles_per_leaf;
-  const int t = (int)(bid - leaf * tiles_per_leaf);
-  const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
-  const float* Sl = S + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
-  const float* Tl = T + leaf * (int64_t)k * n + (int64_t)tn * BN;
-  float* Pl = P + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-
-  // Per-thread slab sources: S row (tid + 256 i) / KQ, chunk % KQ; T row (tid + 256 i) / (BN/4).
-  const float* a_src[A_VEC];
-  const float* b_src[B_VEC];
-#pragma unroll
-  for (int i = 0; i < A_VEC; ++i) {
-    const int idx = tid + 256 * i;
-    a_src[i] = Sl + (int64_t)(idx / KQ) * k + (idx % KQ) * 4;
-  }
-#pragma unroll
-  for (int i = 0; i < B_VEC; ++i) {
-    const int idx = tid + 256 * i;
-    b_src[i] = Tl + (int64_t)(idx / (BN / 4)) * n + (idx % (BN / 4)) * 4;
-  }
-  const int64_t b_step = (int64_t)BK * n;
-
-  // clang vector types (not HIP's float4 struct) so the staging stays in registers
-  floatx4 ra[A_VEC], rb[B_VEC];
-#pragma unroll
-  for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i]);
-#pragma unroll
-  for (int i = 0; i < B_VEC; ++i) rb[i] = *reinterpret_cast<const floatx4*>(b_src[i]);
-
-  floatx4 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  const int nk = k / BK;
-  const int lr = lane & 15, lg = lane >> 4;
-  int cur = 0;
-  for (int kt = 0; kt < nk; ++kt) {
-#pragma unroll
-    for (int i = 0; i < A_VEC; ++i) {
-      const int idx = tid + 256 * i;
-      *reinterpret_cast<floatx4*>(&As[cur][idx / KQ][(idx % KQ) * 4]) = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < B_VEC; ++i) {
-      const int idx = tid + 256 * i;
-      *reinterpret_cast<floatx4*>(&Bs[cur][idx / (BN / 4)][(idx % (BN / 4)) * 4]) = rb[i];
-    }
-    __syncthreads();
-    if (kt + 1 < nk) {
-#pragma unroll
-      for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i] + (kt + 1) * BK);
-#pragma unroll
-      for (int i = 0; i < B_VEC; ++i)
-        rb[i] = *reinterpret_cast<const floatx4*>(b_src[i] + (kt + 1) * b_step);
-    }
-    // 16 k per chunk: in MFMA step j, lane group lg carries k = 16 c + 4 lg + j for both
-    // operands, so one 16-byte read of S gives a lane its operands for four steps.
-#pragma unroll
-    for (int c = 0; c < BK / 16; ++c) {
-      floatx4 a[FM];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-        a[i] = *reinterpret_cast<const floatx4*>(&As[cur][wm * WM + i * 16 + lr][c * 16 + lg * 4]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float b[FN];
-#pragma unroll
-        for (int q = 0; q < FN; ++q) b[q] = Bs[cur][c * 16 + lg * 4 + j][wn * WN + q * 16 + lr];
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int q = 0; q < FN; ++q)
-            acc[i][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[q], acc[i][q], 0, 0, 0);
-      }
-    }
-    cur ^= 1;
-  }
-
-  // Epilogue through LDS: each wavefront parks its (BM/2) x (BN/2) quarter (D layout of the
-  // 16x16 MFMA: lane holds column lane & 15, rows 4 (lane >> 4) + v), then writes it back
-  // row by row with 16-byte stores, 16 lanes per row.
-  __syncthreads();  // every wavefront is done reading the operand buffers
-  float* Es = smem + wave * WM * LDE;
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Es[(i * 16 + lg * 4 + v) * LDE + j * 16 + lr] = acc[i][j][v];
-  __syncthreads();
-  constexpr int LPR = WN / 4;            // lanes per row (16-byte chunks)
-  constexpr int RPI = 64 / LPR;          // rows per store instruction
-  float* Pw = Pl + (int64_t)(wm * WM) * n + wn * WN;
-  const int er = lane / LPR, ec = (lane % LPR) * 4;
-#pragma unroll
-  for (int r0 = 0; r0 < WM; r0 += RPI) {
-    const floatx4 v = *reinterpret_cast<const floatx4*>(&Es[(r0 + er) * LDE + ec]);
-    *reinterpret_cast<floatx4*>(Pw + (int64_t)(r0 + er) * n + ec) = v;
-  }
+  __shared__ __attribute__((aligned(16))) float smem[F32Tile<BM, BN, BK>::SMEM];
+  tiles::gemm_f32_tile<BM, BN, BK>(S, T, P, m, n, k, tiles_n, tiles_per_leaf,
+                                   tiles::xcd_remap(blockIdx.x, nblocks), smem);
 }
 
 __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ S,

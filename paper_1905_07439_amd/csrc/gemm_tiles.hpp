@@ -1,0 +1,327 @@
+// Device-side leaf product tiles, shared by the leaf kernels (gemm.hip,
+// gemm_lowp.hip) and by the batch engine's persistent kernel (batch.hip).
+// Each function computes one output tile given its logical tile index and a
+// pointer to the workgroup's LDS block.
+//
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace rbc {
+namespace tiles {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Block id -> logical tile id such that consecutive logical tiles share an XCD
+// (workgroups are dispatched round robin over the 8 XCDs).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
+  const int64_t per = nb / 8, rem = nb % 8;
+  const int64_t xcd = bid % 8, local = bid / 8;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+template <int BM, int BN, int BK>
+struct F32Tile {
+  static constexpr int LDA = BK + 4, LDB = BN + 4, WM = BM / 2, WN = BN / 2, LDE = WN + 4;
+  static constexpr int A_FLOATS = 2 * BM * LDA, B_FLOATS = 2 * BK * LDB, E_FLOATS = 4 * WM * LDE;
+  // LDS floats: two S and two T slab buffers in the K loop, the output quarters in the epilogue
+  static constexpr int SMEM = A_FLOATS + B_FLOATS > E_FLOATS ? A_FLOATS + B_FLOATS : E_FLOATS;
+};
+
+// Output tile `bid` (leaf-major, then tile row, then tile column) of the batched leaf product.
+template <int BM, int BN, int BK>
+__device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const float* __restrict__ T,
+                                              float* __restrict__ P, int m, int n, int k, int tiles_n,
+                                              int tiles_per_leaf, int64_t bid, float* smem) {
+  constexpr int LDA = F32Tile<BM, BN, BK>::LDA;  // S slab row: k-contiguous, padded
+  constexpr int LDB = F32Tile<BM, BN, BK>::LDB;  // T slab row: n-contiguous, padded
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int KQ = BK / 4;                  // float4 chunks per S row of a slab
+  constexpr int A_VEC = BM * KQ / 256;        // float4 loads per thread per slab
+  constexpr int B_VEC = BK * (BN / 4) / 256;
+  constexpr int LDE = F32Tile<BM, BN, BK>::LDE;  // epilogue row of a wavefront's quarter
+  static_assert(A_VEC >= 1 && B_VEC >= 1, "tile too small for 256 threads");
+  constexpr int A_FLOATS = F32Tile<BM, BN, BK>::A_FLOATS;
+  float(*As)[BM][LDA] = reinterpret_cast<float(*)[BM][LDA]>(smem);
+  float(*Bs)[BK][LDB] = reinterpret_cast<float(*)[BK][LDB]>(smem + A_FLOATS);
+
+  const int64_t leaf = bid / tiles_per_leaf;
+  const int t = (int)(bid - leaf * tiles_per_leaf);
+  const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
+  const float* Sl = S + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
+  const float* Tl = T + leaf * (int64_t)k * n + (int64_t)tn * BN;
+  float* Pl = P + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // Per-thread slab sources: S row (tid + 256 i) / KQ, chunk % KQ; T row (tid + 256 i) / (BN/4).
+  const float* a_src[A_VEC];
+  const float* b_src[B_VEC];
+#pragma unroll
+  for (int i = 0; i < A_VEC; ++i) {
+    const int idx = tid + 256 * i;
+    a_src[i] = Sl + (int64_t)(idx / KQ) * k + (idx % KQ) * 4;
+  }
+#pragma unroll
+  for (int i = 0; i < B_VEC; ++i) {
+    const int idx = tid + 256 * i;
+    b_src[i] = Tl + (int64_t)(idx / (BN / 4)) * n + (idx % (BN / 4)) * 4;
+  }
+  const int64_t b_step = (int64_t)BK * n;
+
+  // clang vector types (not HIP's float4 struct) so the staging stays in registers
+  floatx4 ra[A_VEC], rb[B_VEC];
+#pragma unroll
+  for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i]);
+#pragma unroll
+  for (int i = 0; i < B_VEC; ++i) rb[i] = *reinterpret_cast<const floatx4*>(b_src[i]);
+
+  floatx4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = k / BK;
+  const int lr = lane & 15, lg = lane >> 4;
+  int cur = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int i = 0; i < A_VEC; ++i) {
+      const int idx = tid + 256 * i;
+      *reinterpret_cast<floatx4*>(&As[cur][idx / KQ][(idx % KQ) * 4]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_VEC; ++i) {
+      const int idx = tid + 256 * i;
+      *reinterpret_cast<floatx4*>(&Bs[cur][idx / (BN / 4)][(idx % (BN / 4)) * 4]) = rb[i];
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+#pragma unroll
+      for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i] + (kt + 1) * BK);
+#pragma unroll
+      for (int i = 0; i < B_VEC; ++i)
+        rb[i] = *reinterpret_cast<const floatx4*>(b_src[i] + (kt + 1) * b_step);
+    }
+    // 16 k per chunk: in MFMA step j, lane group lg carries k = 16 c + 4 lg + j for both
+    // operands, so one 16-byte read of S gives a lane its operands for four steps.
+#pragma unroll
+    for (int c = 0; c < BK / 16; ++c) {
+      floatx4 a[FM];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        a[i] = *reinterpret_cast<const floatx4*>(&As[cur][wm * WM + i * 16 + lr][c * 16 + lg * 4]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float b[FN];
+#pragma unroll
+        for (int q = 0; q < FN; ++q) b[q] = Bs[cur][c * 16 + lg * 4 + j][wn * WN + q * 16 + lr];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int q = 0; q < FN; ++q)
+            acc[i][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[q], acc[i][q], 0, 0, 0);
+      }
+    }
+    cur ^= 1;
+  }
+
+  // Epilogue through LDS: each wavefront parks its (BM/2) x (BN/2) quarter (D layout of the
+  // 16x16 MFMA: lane holds column lane & 15, rows 4 (lane >> 4) + v), then writes it back
+  // row by row with 16-byte stores, 16 lanes per row.
+  __syncthreads();  // every wavefront is done reading the operand buffers
+  float* Es = smem + wave * WM * LDE;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Es[(i * 16 + lg * 4 + v) * LDE + j * 16 + lr] = acc[i][j][v];
+  __syncthreads();
+  constexpr int LPR = WN / 4;            // lanes per row (16-byte chunks)
+  constexpr int RPI = 64 / LPR;          // rows per store instruction
+  float* Pw = Pl + (int64_t)(wm * WM) * n + wn * WN;
+  const int er = lane / LPR, ec = (lane % LPR) * 4;
+#pragma unroll
+  for (int r0 = 0; r0 < WM; r0 += RPI) {
+    const floatx4 v = *reinterpret_cast<const floatx4*>(&Es[(r0 + er) * LDE + ec]);
+    *reinterpret_cast<floatx4*>(Pw + (int64_t)(r0 + er) * n + ec) = v;
+  }
+}
+
+enum LowpKind { LOWP_BF16X3 = 0, LOWP_F16S = 1 };
+
+template <int KIND>
+__device__ __forceinline__ floatx4 mfma16(u32x4 a, u32x4 b, floatx4 c) {
+  if constexpr (KIND == LOWP_BF16X3)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                    c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b),
+                                                   c, 0, 0, 0);
+}
+
+template <int KIND, int BM, int BN>
+struct LowpTile {
+  static constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1, BK = 32, LDK = BK + 8;
+  static constexpr int SMEM_HALVES = 2 * NP * (BM + BN) * LDK;  // two buffers of S and T slabs
+};
+
+// Output tile `bid` of the batched reduced-precision leaf product.
+template <int KIND, int BM, int BN>
+__device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
+                                               const uint16_t* __restrict__ T, float* __restrict__ P,
+                                               int m, int n, int k, int64_t plane_s, int64_t plane_t,
+                                               const int32_t* __restrict__ eS,
+                                               const int32_t* __restrict__ eT, int tiles_n,
+                                               int tiles_per_leaf, int64_t bid, uint16_t* smem) {
+  constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1;  // operand planes (hi, lo)
+  constexpr int BK = 32;
+  constexpr int LDK = BK + 8;  // padded row of 40 halves (80 bytes)
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int A_TOTAL = NP * BM * BK / 8;          // 16-byte chunks of an S slab
+  constexpr int A_ITER = (A_TOTAL + 255) / 256;
+  constexpr int B_TOTAL = NP * (BK / 4) * (BN / 8);  // 4k x 8n groups of a T slab
+  constexpr int B_ITER = (B_TOTAL + 255) / 256;
+  uint16_t(*As)[NP][BM][LDK] = reinterpret_cast<uint16_t(*)[NP][BM][LDK]>(smem);  // [buf][plane][row][k]
+  uint16_t(*Bs)[NP][BN][LDK] =
+      reinterpret_cast<uint16_t(*)[NP][BN][LDK]>(smem + 2 * NP * BM * LDK);        // [buf][plane][col][k]
+  const int64_t leaf = bid / tiles_per_leaf;
+  const int t = (int)(bid - leaf * tiles_per_leaf);
+  const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
+  const uint16_t* Sl = S + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
+  const uint16_t* Tl = T + leaf * (int64_t)k * n + (int64_t)tn * BN;
+  float* Pl = P + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // Per-thread slab sources (threads past a total mirror a valid chunk and do not store).
+  const uint16_t* a_src[A_ITER];
+#pragma unroll
+  for (int i = 0; i < A_ITER; ++i) {
+    const int idx = (tid + 256 * i) % A_TOTAL;
+    const int pl = idx / (BM * BK / 8), rem = idx % (BM * BK / 8);
+    a_src[i] = Sl + pl * plane_s + (int64_t)(rem / (BK / 8)) * k + (rem % (BK / 8)) * 8;
+  }
+  const uint16_t* b_src[B_ITER];
+#pragma unroll
+  for (int i = 0; i < B_ITER; ++i) {
+    const int idx = (tid + 256 * i) % B_TOTAL;
+    const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
+    b_src[i] = Tl + pl * plane_t + (int64_t)((rem / (BN / 8)) * 4) * n + (rem % (BN / 8)) * 8;
+  }
+
+  // clang vector types (not HIP's uint4 struct) so the staging stays in registers
+  u32x4 ra[A_ITER];
+  u32x4 rb[B_ITER][4];
+#pragma unroll
+  for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const u32x4*>(a_src[i]);
+#pragma unroll
+  for (int i = 0; i < B_ITER; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rb[i][r] = *reinterpret_cast<const u32x4*>(b_src[i] + (int64_t)r * n);
+
+  floatx4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = k / BK;
+  const int lr = lane & 15, lg = lane >> 4;
+  int cur = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    // registers -> LDS buffer `cur`; T is transposed so that k is contiguous
+#pragma unroll
+    for (int i = 0; i < A_ITER; ++i) {
+      const int idx = tid + 256 * i;
+      if (A_TOTAL % 256 && idx >= A_TOTAL) break;
+      const int pl = idx / (BM * BK / 8), rem = idx % (BM * BK / 8);
+      *reinterpret_cast<u32x4*>(&As[cur][pl][rem / (BK / 8)][(rem % (BK / 8)) * 8]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_ITER; ++i) {
+      const int idx = tid + 256 * i;
+      if (B_TOTAL % 256 && idx >= B_TOTAL) break;
+      const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
+      const int kg = rem / (BN / 8), cg = rem % (BN / 8);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        // element c of each of the 4 rows: 16-bit halves of 32-bit word c / 2
+        const int w = c >> 1, sh = (c & 1) * 16;
+        u32x2 v;
+        v[0] = ((rb[i][0][w] >> sh) & 0xFFFFu) | (((rb[i][1][w] >> sh) & 0xFFFFu) << 16);
+        v[1] = ((rb[i][2][w] >> sh) & 0xFFFFu) | (((rb[i][3][w] >> sh) & 0xFFFFu) << 16);
+        *reinterpret_cast<u32x2*>(&Bs[cur][pl][cg * 8 + c][kg * 4]) = v;
+      }
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      const int k1 = (kt + 1) * BK;
+#pragma unroll
+      for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const u32x4*>(a_src[i] + k1);
+#pragma unroll
+      for (int i = 0; i < B_ITER; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          rb[i][r] = *reinterpret_cast<const u32x4*>(b_src[i] + (int64_t)(k1 + r) * n);
+    }
+    u32x4 ah[FM], bh[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      ah[i] = *reinterpret_cast<const u32x4*>(&As[cur][0][wm * WM + i * 16 + lr][lg * 8]);
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      bh[j] = *reinterpret_cast<const u32x4*>(&Bs[cur][0][wn * WN + j * 16 + lr][lg * 8]);
+    if constexpr (NP == 2) {
+      u32x4 al[FM], bl[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        al[i] = *reinterpret_cast<const u32x4*>(&As[cur][NP - 1][wm * WM + i * 16 + lr][lg * 8]);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        bl[j] = *reinterpret_cast<const u32x4*>(&Bs[cur][NP - 1][wn * WN + j * 16 + lr][lg * 8]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = mfma16<KIND>(al[i], bh[j], acc[i][j]);
+          acc[i][j] = mfma16<KIND>(ah[i], bl[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<KIND>(ah[i], bh[j], acc[i][j]);
+    cur ^= 1;
+  }
+
+  int unscale = 0;
+  if constexpr (KIND == LOWP_F16S) unscale = -(eS[leaf] + eT[leaf]);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wm * WM + i * 16 + lg * 4 + v, col = wn * WN + j * 16 + lr;
+        float x = acc[i][j][v];
+        if constexpr (KIND == LOWP_F16S) x = ldexpf(x, unscale);
+        Pl[(int64_t)row * n + col] = x;
+      }
+}
+
+}  // namespace tiles
+}  // namespace rbc

@@ -1,0 +1,72 @@
+// Host-side construction of the kernel launches of one product: the same
+// descriptions drive the per-stage launches (api.cpp) and the batch engine's
+// task table (batch.cpp).
+#pragma once
+
+#include <vector>
+
+#include "core.hpp"
+#include "kernels.hpp"
+
+namespace rbc {
+
+// Per-level draws, concatenated as in include/rbc.h.
+struct Draws {
+  std::vector<int32_t> s, pm;
+  std::vector<size_t> off;
+};
+
+rbc_status check_draws(const Plan& p, const int32_t* signs, const int32_t* perms, Draws& d);
+void seeded_draws(const Plan& p, uint64_t seed, rbc_mode mode, std::vector<int32_t>& s,
+                  std::vector<int32_t>& pm);
+rbc_status check_ws(const Plan& p, void* ws, size_t bytes);
+// Upload the coefficient tables of every level on first use on a device.
+rbc_status ensure_device(Plan& p);
+
+struct ScaleLaunch {  // f16s: max|X| and the per-leaf exponents of one operand
+  const float* X;
+  int64_t ld, rows, cols;
+  uint32_t* maxbits;
+  const float* G;
+  int32_t* e;
+  int64_t n_leaves;
+};
+
+struct GatherLaunch {
+  GatherParams p;
+  Elt elt;
+  GatherOut out;
+  int vec, nl, br, bc, R;
+};
+
+struct LeafLaunch {
+  rbc_prec prec;
+  const void* S;
+  const void* T;
+  void* P;
+  int64_t m, n, k, batch;
+  int tile;
+  const int32_t* eS;
+  const int32_t* eT;
+};
+
+struct ScatterLaunch {
+  ScatterParams p;
+  Elt tp, ta, to;
+  int vec, nl, br, bc, R;
+};
+
+// which = 0: A (M x K), 1: B (K x N).  `scale` is filled for f16s plans.
+void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int64_t ldx, char* ws,
+                  std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out);
+LeafLaunch build_leaf(const Plan& p, char* ws);
+// In execution order (deepest group first).
+void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, int64_t ldc, char* ws,
+                   std::vector<ScatterLaunch>& out);
+
+hipError_t launch(const ScaleLaunch& l, hipStream_t s);
+hipError_t launch(const GatherLaunch& l, hipStream_t s);
+hipError_t launch(const LeafLaunch& l, hipStream_t s);
+hipError_t launch(const ScatterLaunch& l, hipStream_t s);
+
+}  // namespace rbc
