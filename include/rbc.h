@@ -79,6 +79,7 @@ typedef enum {
 
 typedef struct rbc_scheme_s* rbc_scheme;
 typedef struct rbc_plan_s* rbc_plan;
+typedef struct rbc_batch_s* rbc_batch;
 
 /* Plan geometry, see rbc_plan_get_info. */
 typedef struct {
@@ -202,6 +203,96 @@ rbc_status rbc_stage_scatter(rbc_plan p, const int32_t* signs, const int32_t* pe
  * them.  At most 4096 calls may be recorded between collects (RBC_ENOMEM). */
 rbc_status rbc_plan_set_timing(rbc_plan p, int on);
 rbc_status rbc_plan_timing_collect(rbc_plan p, double ms[4], int64_t* calls);
+
+
+/* ---- batches: many independent products in one persistent launch ---------
+ * A batch holds products C_i = F-hat^(Q_i)(A_i, B_i), each with its own plan,
+ * operands, seed and mode, all of one precision (RBC_PREC_F32 or
+ * RBC_PREC_F16S; every level shape must be Strassen-shaped <2,2,2> with 7
+ * products or Laderman-shaped <3,3,3> with 23).  The library turns every
+ * product into tasks (pieces of its gather, leaf and scatter stages), orders
+ * them so that dependencies come first, and runs them all in one persistent
+ * kernel whose workgroups take tasks from a queue and wait on per-subproblem
+ * completion counters.  Each product's result is bitwise identical to
+ * rbc_matmul with the same plan, operands, seed and mode: the tasks run the
+ * same arithmetic in the same order.
+ *
+ * Ownership: the batch keeps pointers to the plans and operand buffers given
+ * to rbc_batch_add; they must stay valid until the batch is destroyed.  The
+ * caller owns the workspace (rbc_batch_workspace bytes, 256-byte aligned),
+ * which holds the task table, the counters and every product's stage buffers.
+ *
+ * Waits inside the kernel are bounded by timeout_ms of wall-clock time; a
+ * wait that exceeds it stops the whole kernel and rbc_batch_check reports
+ * RBC_EHIP (the results are then incomplete). */
+typedef struct {
+  int32_t window;      /* products whose tasks are interleaved in the queue (0: 4) */
+  int32_t grid;        /* workgroups of the persistent kernel (0: resident maximum) */
+  int32_t timeout_ms;  /* limit of one dependency wait (0: 5000) */
+  int32_t reserved;
+  int64_t task_bytes;  /* HBM bytes one task aims to move (0: 256 KiB) */
+  int64_t item_budget; /* bytes for the products' stage buffers (0: one region per product).
+                        * With a budget the regions form a ring: a product reuses the
+                        * bytes of earlier ones and its first tasks wait until those
+                        * have finished.  Must hold the largest product's buffers. */
+} rbc_batch_options;
+
+typedef struct {
+  int64_t n_items, n_tasks, n_counters;
+  int64_t scale_tasks, gather_tasks, leaf_tasks, scatter_tasks, gate_tasks;
+  size_t workspace_bytes; /* total, as rbc_batch_workspace */
+  size_t control_bytes;   /* task table, parameters and counters (the rest is stage buffers) */
+  int32_t grid, prec;
+} rbc_batch_info;
+
+/* One task of the persistent kernel, as rbc_batch_task_table returns them
+ * (queue order).  kind: 0 max|X| of an f16s operand, 1 its per-leaf
+ * exponents, 2 gather, 3 leaf products, 4 scatter, 5 gate (no work: waits
+ * for an earlier product that used the same workspace bytes).  The task covers pieces
+ * [first, first + count) of its stage (pieces are workgroup-sized: 256
+ * threads' positions of a combination, one output tile of the leaf
+ * product), for top block `sub` of a gather or output block `sub` of a
+ * scatter.  It waits until counter wait[i] reaches need[i] (wait[i] < 0: no
+ * wait) and adds count to counter `signal` when done. */
+typedef struct {
+  int16_t kind, variant;
+  int32_t param;
+  int32_t wait[2], need[2];
+  int32_t signal, count;
+  int64_t first, sub;
+} rbc_batch_task;
+
+/* opt may be NULL (defaults). */
+rbc_status rbc_batch_create(const rbc_batch_options* opt, rbc_batch* out);
+/* Append a product; *index (may be NULL) receives its position. */
+rbc_status rbc_batch_add(rbc_batch b, rbc_plan p, const void* A, int64_t lda, const void* B, int64_t ldb,
+                         void* C, int64_t ldc, uint64_t seed, rbc_mode mode, int kappa_scale,
+                         int64_t* index);
+rbc_status rbc_batch_workspace(rbc_batch b, size_t* bytes);
+/* Build the task table for this workspace and upload it (synchronously on
+ * stream).  Call again after adding products or to use another workspace. */
+rbc_status rbc_batch_prepare(rbc_batch b, void* workspace, size_t ws_bytes, void* stream);
+/* Enqueue one run on stream: a counter reset and the persistent kernel.
+ * use_graph != 0 captures both into a HIP graph on first use (stream must
+ * not be the default stream) and replays it afterwards. */
+rbc_status rbc_batch_launch(rbc_batch b, void* stream, int use_graph);
+/* Wait for stream, then report RBC_EHIP if a dependency wait timed out. */
+rbc_status rbc_batch_check(rbc_batch b, void* stream);
+rbc_status rbc_batch_get_info(rbc_batch b, rbc_batch_info* info);
+/* Where a product's stage buffers live in the workspace (byte offset and
+ * size), the queue index of its first task, and its two counters: the one
+ * its first tasks wait on (previous users of its bytes) and the one its last
+ * stage fills. */
+typedef struct {
+  size_t region_offset, region_bytes;
+  int64_t first_task;
+  int32_t gate_counter, done_counter;
+} rbc_batch_item;
+rbc_status rbc_batch_get_item(rbc_batch b, int64_t index, rbc_batch_item* out);
+/* Copy up to cap tasks of the last built table into out (host memory; out may
+ * be NULL with cap 0) and the table's length into *n. */
+rbc_status rbc_batch_task_table(rbc_batch b, rbc_batch_task* out, int64_t cap, int64_t* n);
+void rbc_batch_destroy(rbc_batch b);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import MODES, PRECS, PlanInfo, RbcError, check, lib  # noqa: F401
+from ._lib import MODES, PRECS, BatchInfo, BatchItem, BatchOptions, PlanInfo, RbcError, check, lib  # noqa: F401
 
 __all__ = ["Scheme", "Plan", "draw", "fold", "RbcError", "lib"]
 
@@ -245,6 +245,114 @@ class Plan:
         if h is not None and h.value:
             try:
                 lib().rbc_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = ctypes.c_void_p()
+
+
+# Layout of rbc_batch_task (include/rbc.h).
+TASK_DTYPE = np.dtype([("kind", np.int16), ("variant", np.int16), ("param", np.int32),
+                       ("wait", np.int32, 2), ("need", np.int32, 2), ("signal", np.int32),
+                       ("count", np.int32), ("first", np.int64), ("sub", np.int64)])
+TASK_KINDS = {0: "maxabs", 1: "exponents", 2: "gather", 3: "leaf", 4: "scatter", 5: "gate"}
+
+
+class Batch:
+    """Independent products run together by one persistent kernel (include/rbc.h, batches).
+
+    Every product keeps the result ``Plan.matmul`` gives for the same plan,
+    operands, seed and mode, bit for bit.  The batch holds references to the
+    plans and tensors added to it; they must not be freed or resized while the
+    batch is in use.
+    """
+
+    def __init__(self, window=0, grid=0, timeout_ms=0, task_bytes=0, item_budget=0):
+        opt = BatchOptions(window=window, grid=grid, timeout_ms=timeout_ms, task_bytes=task_bytes,
+                           item_budget=item_budget)
+        h = ctypes.c_void_p()
+        check(lib().rbc_batch_create(ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+        self.items = []
+        self._ws = None
+
+    def add(self, plan, A, B, C=None, seed=0, mode="full", kappa_scale=None):
+        """Append C = F-hat(A, B) with plan's schemes; returns (index, C)."""
+        import torch
+        if kappa_scale is None:
+            kappa_scale = mode != "none"
+        M, K, N = plan.info["M"], plan.info["K"], plan.info["N"]
+        for name, X, shape in (("A", A, (M, K)), ("B", B, (K, N))):
+            if tuple(X.shape) != shape or X.dtype != plan.dtype or not X.is_cuda or X.stride(1) != 1:
+                raise ValueError("%s must be a row-major %s CUDA tensor of shape %s" % (name, plan.dtype, shape))
+        if C is None:
+            C = torch.empty((M, N), dtype=plan.dtype, device=A.device)
+        if tuple(C.shape) != (M, N) or C.dtype != plan.dtype or C.stride(1) != 1:
+            raise ValueError("C must be a row-major %s tensor of shape %s" % (plan.dtype, (M, N)))
+        idx = ctypes.c_int64()
+        check(lib().rbc_batch_add(self._h, plan._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C),
+                                  C.stride(0), seed & 0xFFFFFFFFFFFFFFFF, MODES[mode], int(bool(kappa_scale)),
+                                  ctypes.byref(idx)))
+        self._keep.append((plan, A, B, C))
+        self.items.append(C)
+        self._ws = None
+        return idx.value, C
+
+    @property
+    def workspace_bytes(self):
+        n = ctypes.c_size_t()
+        check(lib().rbc_batch_workspace(self._h, ctypes.byref(n)))
+        return n.value
+
+    def prepare(self, workspace=None, stream=None, device=None):
+        """Build and upload the task table; allocates the workspace unless one is given."""
+        import torch
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device or "cuda")
+        st = stream if stream is not None else torch.cuda.current_stream(workspace.device)
+        check(lib().rbc_batch_prepare(self._h, _ptr(workspace), workspace.numel(), ctypes.c_void_p(st.cuda_stream)))
+        self._ws = workspace
+        return workspace
+
+    def launch(self, graph=False, stream=None):
+        """One run of every product, asynchronously on ``stream`` (a captured graph if ``graph``)."""
+        import torch
+        if self._ws is None:
+            self.prepare(stream=stream)
+        st = stream if stream is not None else torch.cuda.current_stream(self._ws.device)
+        check(lib().rbc_batch_launch(self._h, ctypes.c_void_p(st.cuda_stream), int(bool(graph))))
+
+    def check(self, stream=None):
+        """Wait for ``stream``; raises if a dependency wait inside the kernel timed out."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self._ws.device)
+        check(lib().rbc_batch_check(self._h, ctypes.c_void_p(st.cuda_stream)))
+
+    def task_table(self):
+        """The task table of the last prepare or workspace query, as a numpy structured array."""
+        n = ctypes.c_int64()
+        check(lib().rbc_batch_task_table(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=TASK_DTYPE)
+        check(lib().rbc_batch_task_table(self._h, out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                         ctypes.byref(n)))
+        return out
+
+    def item(self, index):
+        """Workspace region, first queue index and counters of product ``index``."""
+        it = BatchItem()
+        check(lib().rbc_batch_get_item(self._h, index, ctypes.byref(it)))
+        return it.as_dict()
+
+    def info(self):
+        inf = BatchInfo()
+        check(lib().rbc_batch_get_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().rbc_batch_destroy(h)
             except Exception:
                 pass
             self._h = ctypes.c_void_p()

@@ -32,6 +32,29 @@ class PlanInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("grid", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("task_bytes", c_i64), ("item_budget", c_i64)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_items", c_i64), ("n_tasks", c_i64), ("n_counters", c_i64),
+                ("scale_tasks", c_i64), ("gather_tasks", c_i64), ("leaf_tasks", c_i64),
+                ("scatter_tasks", c_i64), ("gate_tasks", c_i64), ("workspace_bytes", ctypes.c_size_t),
+                ("control_bytes", ctypes.c_size_t), ("grid", ctypes.c_int32), ("prec", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("region_offset", ctypes.c_size_t), ("region_bytes", ctypes.c_size_t), ("first_task", c_i64),
+                ("gate_counter", ctypes.c_int32), ("done_counter", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # name -> (restype, argtypes); every function of include/rbc.h
 SIGNATURES = {
     "rbc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
@@ -61,6 +84,17 @@ SIGNATURES = {
                                          ctypes.c_size_t, c_vp]),
     "rbc_plan_set_timing": (ctypes.c_int, [c_vp, ctypes.c_int]),
     "rbc_plan_timing_collect": (ctypes.c_int, [c_vp, c_dbl_p, ctypes.POINTER(c_i64)]),
+    "rbc_batch_create": (ctypes.c_int, [ctypes.POINTER(BatchOptions), ctypes.POINTER(c_vp)]),
+    "rbc_batch_add": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, ctypes.c_uint64,
+                                     ctypes.c_int, ctypes.c_int, ctypes.POINTER(c_i64)]),
+    "rbc_batch_workspace": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "rbc_batch_prepare": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "rbc_batch_launch": (ctypes.c_int, [c_vp, c_vp, ctypes.c_int]),
+    "rbc_batch_check": (ctypes.c_int, [c_vp, c_vp]),
+    "rbc_batch_get_info": (ctypes.c_int, [c_vp, ctypes.POINTER(BatchInfo)]),
+    "rbc_batch_get_item": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(BatchItem)]),
+    "rbc_batch_task_table": (ctypes.c_int, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
+    "rbc_batch_destroy": (None, [c_vp]),
 }
 
 _lib = None

@@ -25,8 +25,9 @@ HOST_ONLY = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 
 
 def _extra(name):
-    # The block-combination kernels must not contract c * x + acc into an FMA.
-    return ["-ffp-contract=off"] if name.startswith("combine") else []
+    # The block-combination kernels (stand-alone and inside the batch engine)
+    # must not contract c * x + acc into an FMA.
+    return ["-ffp-contract=off"] if name.startswith(("combine", "batch")) else []
 
 
 def _hipcc():

@@ -13,6 +13,7 @@
 
 #include "core.hpp"
 #include "kernels.hpp"
+#include "handles.hpp"
 #include "launches.hpp"
 
 namespace rbc {
@@ -21,12 +22,6 @@ const char* last_error_text();
 
 using namespace rbc;
 
-struct rbc_scheme_s {
-  Scheme s;
-};
-struct rbc_plan_s {
-  Plan p;
-};
 
 #define RBC_GUARD_BEGIN try {
 #define RBC_GUARD_END                                                  \

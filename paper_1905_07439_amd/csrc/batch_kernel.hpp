@@ -1,0 +1,220 @@
+// The persistent batch kernel (see batch.hpp for the task model).
+//
+// Synchronisation: a task's writes are made visible at agent scope by a
+// release fence in every thread, then one barrier, then thread 0 adds the
+// task's piece count to its completion counter.  A waiting task's thread 0
+// polls its counters with agent-scope atomic loads (sleeping between polls),
+// then every thread takes an agent-scope acquire fence before reading the
+// data.  The fences write back and invalidate the per-XCD L2 as the memory
+// model requires, so producers and consumers may run on different XCDs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "combine.hpp"
+#include "gemm_tiles.hpp"
+#include "scale.hpp"
+
+namespace rbc {
+namespace batch {
+
+template <int PREC>
+struct Smem {
+  static constexpr size_t bytes =
+      PREC == RBC_PREC_F32 ? sizeof(float) * tiles::F32Tile<64, 64, 32>::SMEM
+                           : sizeof(uint16_t) * tiles::LowpTile<tiles::LOWP_F16S, 128, 128>::SMEM_HALVES;
+};
+
+template <int PREC>
+constexpr bool gather_in(const CombVariant& v) {
+  return v.out == OUT_SAME || (PREC == RBC_PREC_F16S && v.out == OUT_F16S);
+}
+
+template <int OUTF, int V, int NL, int BR, int BC, int R>
+__device__ __forceinline__ void gather_task(const GatherParams& p, int64_t first, int count, int64_t in) {
+  for (int c = 0; c < count; ++c) comb::gather_block<float, OUTF, V, NL, BR, BC, R>(p, first + c, in);
+}
+
+template <int V, int NL, int BR, int BC, int R>
+__device__ __forceinline__ void scatter_task(const ScatterParams& p, int64_t first, int count, int64_t o) {
+  for (int c = 0; c < count; ++c) comb::scatter_block<float, float, float, V, NL, BR, BC, R>(p, first + c, o);
+}
+
+template <int PREC, int TILE, int BK>
+__device__ __forceinline__ void leaf_task(const LeafDesc& d, int64_t first, int count, void* smem) {
+  for (int c = 0; c < count; ++c) {
+    if (c) __syncthreads();  // the previous tile's LDS reads are done
+    if constexpr (PREC == RBC_PREC_F32)
+      tiles::gemm_f32_tile<TILE, TILE, BK>(static_cast<const float*>(d.S), static_cast<const float*>(d.T),
+                                           d.P, d.m, d.n, d.k, d.tiles_n, d.tiles_per_leaf, first + c,
+                                           static_cast<float*>(smem));
+    else
+      tiles::gemm_lowp_tile<tiles::LOWP_F16S, TILE, TILE>(
+          static_cast<const uint16_t*>(d.S), static_cast<const uint16_t*>(d.T), d.P, d.m, d.n, d.k,
+          d.plane_s, d.plane_t, d.eS, d.eT, d.tiles_n, d.tiles_per_leaf, first + c,
+          static_cast<uint16_t*>(smem));
+  }
+}
+
+template <int PREC, int I>
+__device__ __forceinline__ void run_gather(int v, const GatherParams& p, int64_t first, int count,
+                                           int64_t in) {
+  if constexpr (I < kNumGathers) {
+    constexpr CombVariant G = kGathers[I];
+    if constexpr (gather_in<PREC>(G)) {
+      if (v == I) return gather_task<G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, first, count, in);
+    }
+    run_gather<PREC, I + 1>(v, p, first, count, in);
+  }
+}
+
+template <int I>
+__device__ __forceinline__ void run_scatter(int v, const ScatterParams& p, int64_t first, int count,
+                                            int64_t o) {
+  if constexpr (I < kNumScatters) {
+    constexpr CombVariant S = kScatters[I];
+    if (v == I) return scatter_task<S.vec, S.nl, S.br, S.bc, S.R>(p, first, count, o);
+    run_scatter<I + 1>(v, p, first, count, o);
+  }
+}
+
+template <int PREC, int I>
+__device__ __forceinline__ void run_leaf(int v, const LeafDesc& d, int64_t first, int count, void* smem) {
+  if constexpr (I < kNumLeaves) {
+    constexpr LeafVariant L = kLeaves[I];
+    if constexpr (L.prec == PREC) {
+      if (v == I) return leaf_task<PREC, L.tile, L.bk>(d, first, count, smem);
+    }
+    run_leaf<PREC, I + 1>(v, d, first, count, smem);
+  }
+}
+
+__device__ __forceinline__ int32_t load_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 only.  True once counter c reaches need; false on abort or time-out
+// (the time-out raises the abort flag and records the task).
+__device__ __forceinline__ bool wait_for(const int32_t* c, int32_t need, int32_t* ctl, int64_t task,
+                                         int64_t timeout) {
+  if (load_relaxed(c) >= need) return true;
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t spins = 0;; ++spins) {
+    __builtin_amdgcn_s_sleep(2);
+    if (load_relaxed(c) >= need) return true;
+    if (load_relaxed(ctl + CTL_ABORT)) return false;
+    // wall-clock limit, with a poll-count backstop (each poll sleeps at least 128 cycles)
+    if ((int64_t)(wall_clock64() - t0) > timeout || spins >= (1u << 22)) {
+      atomicCAS(ctl + CTL_STUCK_TASK, 0, (int32_t)(task + 1));
+      __hip_atomic_store(ctl + CTL_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+}
+
+// Leader steps of the task loop (thread 0 acts, the others return at once).
+// They are kept out of line on purpose: with them inlined, the compiler may
+// merge the leader block that ends one iteration with the one that starts
+// the next into a single divergent region across the loop's back edge and
+// restructure the loop so that the other lanes reach the next barrier without
+// the leader, re-reading the previous task.  Called by every thread, the
+// functions leave the kernel's loop without any divergent branch.
+__device__ __noinline__ void leader_pop(int32_t* ctl, int64_t n_tasks, int32_t* slot) {
+  if (threadIdx.x == 0) {
+    int32_t t = atomicAdd(ctl + CTL_HEAD, 1);
+    if (load_relaxed(ctl + CTL_ABORT)) t = (int32_t)n_tasks;
+    *slot = t;
+  }
+}
+
+__device__ __noinline__ void leader_wait(const Task* task, int32_t* ctl, int32_t t, int64_t timeout,
+                                         int32_t* slot) {
+  if (threadIdx.x == 0) {
+    int32_t* cnt = ctl + CTL_WORDS;
+    bool ok = true;
+    if (task->wait[0] >= 0) ok = wait_for(cnt + task->wait[0], task->need[0], ctl, t, timeout);
+    if (ok && task->wait[1] >= 0) ok = wait_for(cnt + task->wait[1], task->need[1], ctl, t, timeout);
+    *slot = ok;
+  }
+}
+
+__device__ __noinline__ void leader_signal(int32_t* ctl, int32_t signal, int32_t count) {
+  if (threadIdx.x == 0 && signal >= 0) atomicAdd(ctl + CTL_WORDS + signal, count);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks, int64_t n_tasks,
+                                                  const GatherParams* __restrict__ gather,
+                                                  const ScatterParams* __restrict__ scatter,
+                                                  const LeafDesc* __restrict__ leaf,
+                                                  const ScaleDesc* __restrict__ scale_d, int32_t* ctl,
+                                                  int64_t timeout_ticks) {
+  __shared__ __attribute__((aligned(16))) char smem[Smem<PREC>::bytes];
+  __shared__ int32_t s_task;
+  __shared__ int32_t s_ok;
+  for (;;) {
+    leader_pop(ctl, n_tasks, &s_task);
+    __syncthreads();
+    // Every thread reads the same value; saying so keeps the task and its
+    // parameters in scalar registers.
+    const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
+    if (t >= n_tasks) break;
+    const Task& task = tasks[t];
+    leader_wait(&task, ctl, t, timeout_ticks, &s_ok);
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    switch (task.kind) {
+      case TK_MAXABS: {
+        const ScaleDesc& d = scale_d[task.param];
+        for (int c = 0; c < task.count; ++c)
+          scale::maxabs_part(d.X, d.ld, d.rows, d.cols, d.maxbits, (task.first + c) * 256, d.pieces * 256);
+        break;
+      }
+      case TK_EXPONENTS: {
+        const ScaleDesc& d = scale_d[task.param];
+        const float mx = __uint_as_float(__hip_atomic_load(d.maxbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const gbl<const float>* G = global_ptr(d.G);
+        gbl<int32_t>* e = global_ptr(d.e);
+        for (int64_t l = threadIdx.x; l < d.n_leaves; l += 256) e[l] = scale::leaf_exponent(mx, G[l]);
+        break;
+      }
+      case TK_GATHER:
+        run_gather<PREC, 0>(task.variant, gather[task.param], task.first, task.count, task.sub);
+        break;
+      case TK_LEAF:
+        run_leaf<PREC, 0>(task.variant, leaf[task.param], task.first, task.count, smem);
+        break;
+      case TK_SCATTER:
+        run_scatter<0>(task.variant, scatter[task.param], task.first, task.count, task.sub);
+        break;
+      default:
+        break;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    leader_signal(ctl, task.signal, task.count);
+  }
+}
+static __global__ void k_zero_words(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+template <int PREC>
+hipError_t occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<PREC>, 256, 0);
+}
+
+template <int PREC>
+hipError_t launch(const KernelArgs& a, int grid, hipStream_t s) {
+  int64_t zb = (a.n_ctl + 255) / 256;
+  if (zb > 1024) zb = 1024;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)zb), dim3(256), 0, s, a.ctl, a.n_ctl);
+  hipLaunchKernelGGL(k_batch<PREC>, dim3((unsigned)grid), dim3(256), 0, s, a.tasks, a.n_tasks, a.gather,
+                     a.scatter, a.leaf, a.scale, a.ctl, a.timeout_ticks);
+  return hipGetLastError();
+}
+
+}  // namespace batch
+}  // namespace rbc

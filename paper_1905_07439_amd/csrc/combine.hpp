@@ -19,6 +19,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "devptr.hpp"
 #include "kernels.hpp"
 
 #pragma clang fp contract(off)
@@ -43,7 +44,7 @@ __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * i
 // block times the two signs (eq. randomized-algorithm).
 template <typename T, int BC>
 __device__ __forceinline__ T coef(const SideLevel& L, int k, int l, int r, int R) {
-  const T* tab = static_cast<const T*>(L.tab);
+  const gbl<const T>* tab = global_ptr(static_cast<const T*>(L.tab));
   const T c = tab[(L.pr[k] * BC + L.pc[l]) * R + r];
   return (L.sr[k] * L.sc[l] < 0) ? -c : c;
 }
@@ -61,20 +62,20 @@ template <typename T, int V>
 using VecT = T __attribute__((ext_vector_type(V)));
 
 template <typename T, int V>
-__device__ __forceinline__ VecT<T, V> vload(const T* p) {
+__device__ __forceinline__ VecT<T, V> vload(const gbl<const T>* p) {
 #if RBC_NT_LOADS
-  return __builtin_nontemporal_load(reinterpret_cast<const VecT<T, V>*>(p));
+  return __builtin_nontemporal_load(reinterpret_cast<const gbl<const VecT<T, V>>*>(p));
 #else
-  return *reinterpret_cast<const VecT<T, V>*>(p);
+  return *reinterpret_cast<const gbl<const VecT<T, V>>*>(p);
 #endif
 }
 
 template <typename T, int V>
-__device__ __forceinline__ void vstore(T* p, VecT<T, V> v) {
+__device__ __forceinline__ void vstore(gbl<T>* p, VecT<T, V> v) {
 #if RBC_NT_STORES
-  __builtin_nontemporal_store(v, reinterpret_cast<VecT<T, V>*>(p));
+  __builtin_nontemporal_store(v, reinterpret_cast<gbl<VecT<T, V>>*>(p));
 #else
-  *reinterpret_cast<VecT<T, V>*>(p) = v;
+  *reinterpret_cast<gbl<VecT<T, V>>*>(p) = v;
 #endif
 }
 
@@ -86,14 +87,14 @@ struct GatherEmit {
   __device__ __forceinline__ void operator()(int64_t idx, VecT<T, V> v) const {
     if constexpr (OUTF == OUT_SAME) {
       // streaming store: the leaf operands are read once, by the next kernel
-      vstore<T, V>(static_cast<T*>(dst) + idx * dst_batch + off, v);
+      vstore<T, V>(global_ptr(static_cast<T*>(dst)) + idx * dst_batch + off, v);
     } else if constexpr (OUTF == OUT_F16S) {
       // scaled leaf operand: rn_f16(2^e v), e chosen per leaf so nothing overflows
-      const int ex = scale_exp[idx];
+      const int ex = global_ptr(scale_exp)[idx];
       VecT<uint16_t, V> h;
 #pragma unroll
       for (int e = 0; e < V; ++e) h[e] = __builtin_bit_cast(uint16_t, (_Float16)ldexpf((float)v[e], ex));
-      vstore<uint16_t, V>(static_cast<uint16_t*>(dst) + idx * dst_batch + off, h);
+      vstore<uint16_t, V>(global_ptr(static_cast<uint16_t*>(dst)) + idx * dst_batch + off, h);
     } else {
       // leaf operand split: hi = rn_bf16(v), lo = rn_bf16(v - hi) (v - hi is exact in f32)
       VecT<uint16_t, V> hi, lo;
@@ -103,7 +104,7 @@ struct GatherEmit {
         hi[e] = bf16_rne(f);
         lo[e] = bf16_rne(f - bf16_to_float(hi[e]));
       }
-      uint16_t* d = static_cast<uint16_t*>(dst) + idx * dst_batch + off;
+      gbl<uint16_t>* d = global_ptr(static_cast<uint16_t*>(dst)) + idx * dst_batch + off;
       vstore<uint16_t, V>(d, hi);
       vstore<uint16_t, V>(d + plane, lo);
     }
@@ -163,7 +164,7 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, 
   const int64_t pos = (bx * 256 + threadIdx.x) * V;
   if (pos >= npos) return;
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;  // cols_bot % V == 0
-  const T* src = static_cast<const T*>(p.src) + in * p.src_batch;
+  const gbl<const T>* src = global_ptr(static_cast<const T*>(p.src)) + in * p.src_batch;
   VecT<T, V> v[NSRC];
 #pragma unroll
   for (int s = 0; s < NSRC; ++s) {
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
 // Level LT of a scatter group: returns in `out` the BB^(NL-LT) values of the
 // block at this level for subproblem prefix idx.
 template <typename TP, typename TA, int V, int NL, int BR, int BC, int R, int LT>
-__device__ __forceinline__ void scatter_level(const TP* src, int64_t src_batch, int64_t off,
+__device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t src_batch, int64_t off,
                                               const SideLevel* lev, int64_t idx, VecT<TA, V>* out) {
   if constexpr (LT == NL) {
     const VecT<TP, V> x = vload<TP, V>(src + idx * src_batch + off);
@@ -247,10 +248,10 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, int64_t bx
   const int64_t pos = (bx * 256 + threadIdx.x) * V;
   if (pos >= npos) return;
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
-  const TP* src = static_cast<const TP*>(p.src);
+  const gbl<const TP>* src = global_ptr(static_cast<const TP*>(p.src));
   VecT<TA, V> out[NOUT];
   scatter_level<TP, TA, V, NL, BR, BC, R, 0>(src, p.src_batch, pos, p.lev, o, out);
-  TO* dst = static_cast<TO*>(p.dst) + o * p.dst_batch;
+  gbl<TO>* dst = global_ptr(static_cast<TO*>(p.dst)) + o * p.dst_batch;
 #pragma unroll
   for (int s = 0; s < NOUT; ++s) {
     int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
@@ -268,7 +269,7 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, int64_t bx
 #pragma unroll
     for (int e = 0; e < V; ++e) w[e] = (TO)out[s][e];
     if (row < p.dst_rows && col + V <= p.dst_cols) {
-      *reinterpret_cast<VecT<TO, V>*>(dst + row * p.ld_dst + col) = w;  // aligned: checked by the host
+      *reinterpret_cast<gbl<VecT<TO, V>>*>(dst + row * p.ld_dst + col) = w;  // aligned: checked by the host
     } else {
 #pragma unroll
       for (int e = 0; e < V; ++e)

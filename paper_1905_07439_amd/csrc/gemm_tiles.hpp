@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "devptr.hpp"
 #include "kernels.hpp"
 
 namespace rbc {
@@ -56,16 +57,16 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
   const int64_t leaf = bid / tiles_per_leaf;
   const int t = (int)(bid - leaf * tiles_per_leaf);
   const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
-  const float* Sl = S + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
-  const float* Tl = T + leaf * (int64_t)k * n + (int64_t)tn * BN;
-  float* Pl = P + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
+  const gbl<const float>* Sl = global_ptr(S) + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
+  const gbl<const float>* Tl = global_ptr(T) + leaf * (int64_t)k * n + (int64_t)tn * BN;
+  gbl<float>* Pl = global_ptr(P) + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
   // Per-thread slab sources: S row (tid + 256 i) / KQ, chunk % KQ; T row (tid + 256 i) / (BN/4).
-  const float* a_src[A_VEC];
-  const float* b_src[B_VEC];
+  const gbl<const float>* a_src[A_VEC];
+  const gbl<const float>* b_src[B_VEC];
 #pragma unroll
   for (int i = 0; i < A_VEC; ++i) {
     const int idx = tid + 256 * i;
@@ -81,9 +82,9 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
   // clang vector types (not HIP's float4 struct) so the staging stays in registers
   floatx4 ra[A_VEC], rb[B_VEC];
 #pragma unroll
-  for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i]);
+  for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const gbl<const floatx4>*>(a_src[i]);
 #pragma unroll
-  for (int i = 0; i < B_VEC; ++i) rb[i] = *reinterpret_cast<const floatx4*>(b_src[i]);
+  for (int i = 0; i < B_VEC; ++i) rb[i] = *reinterpret_cast<const gbl<const floatx4>*>(b_src[i]);
 
   floatx4 acc[FM][FN];
 #pragma unroll
@@ -108,10 +109,10 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
     __syncthreads();
     if (kt + 1 < nk) {
 #pragma unroll
-      for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const floatx4*>(a_src[i] + (kt + 1) * BK);
+      for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const gbl<const floatx4>*>(a_src[i] + (kt + 1) * BK);
 #pragma unroll
       for (int i = 0; i < B_VEC; ++i)
-        rb[i] = *reinterpret_cast<const floatx4*>(b_src[i] + (kt + 1) * b_step);
+        rb[i] = *reinterpret_cast<const gbl<const floatx4>*>(b_src[i] + (kt + 1) * b_step);
     }
     // 16 k per chunk: in MFMA step j, lane group lg carries k = 16 c + 4 lg + j for both
     // operands, so one 16-byte read of S gives a lane its operands for four steps.
@@ -150,12 +151,12 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
   __syncthreads();
   constexpr int LPR = WN / 4;            // lanes per row (16-byte chunks)
   constexpr int RPI = 64 / LPR;          // rows per store instruction
-  float* Pw = Pl + (int64_t)(wm * WM) * n + wn * WN;
+  gbl<float>* Pw = Pl + (int64_t)(wm * WM) * n + wn * WN;
   const int er = lane / LPR, ec = (lane % LPR) * 4;
 #pragma unroll
   for (int r0 = 0; r0 < WM; r0 += RPI) {
     const floatx4 v = *reinterpret_cast<const floatx4*>(&Es[(r0 + er) * LDE + ec]);
-    *reinterpret_cast<floatx4*>(Pw + (int64_t)(r0 + er) * n + ec) = v;
+    *reinterpret_cast<gbl<floatx4>*>(Pw + (int64_t)(r0 + er) * n + ec) = v;
   }
 }
 
@@ -200,22 +201,22 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
   const int64_t leaf = bid / tiles_per_leaf;
   const int t = (int)(bid - leaf * tiles_per_leaf);
   const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
-  const uint16_t* Sl = S + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
-  const uint16_t* Tl = T + leaf * (int64_t)k * n + (int64_t)tn * BN;
-  float* Pl = P + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
+  const gbl<const uint16_t>* Sl = global_ptr(S) + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
+  const gbl<const uint16_t>* Tl = global_ptr(T) + leaf * (int64_t)k * n + (int64_t)tn * BN;
+  gbl<float>* Pl = global_ptr(P) + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
   // Per-thread slab sources (threads past a total mirror a valid chunk and do not store).
-  const uint16_t* a_src[A_ITER];
+  const gbl<const uint16_t>* a_src[A_ITER];
 #pragma unroll
   for (int i = 0; i < A_ITER; ++i) {
     const int idx = (tid + 256 * i) % A_TOTAL;
     const int pl = idx / (BM * BK / 8), rem = idx % (BM * BK / 8);
     a_src[i] = Sl + pl * plane_s + (int64_t)(rem / (BK / 8)) * k + (rem % (BK / 8)) * 8;
   }
-  const uint16_t* b_src[B_ITER];
+  const gbl<const uint16_t>* b_src[B_ITER];
 #pragma unroll
   for (int i = 0; i < B_ITER; ++i) {
     const int idx = (tid + 256 * i) % B_TOTAL;
@@ -227,11 +228,11 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
   u32x4 ra[A_ITER];
   u32x4 rb[B_ITER][4];
 #pragma unroll
-  for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const u32x4*>(a_src[i]);
+  for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i]);
 #pragma unroll
   for (int i = 0; i < B_ITER; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) rb[i][r] = *reinterpret_cast<const u32x4*>(b_src[i] + (int64_t)r * n);
+    for (int r = 0; r < 4; ++r) rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)r * n);
 
   floatx4 acc[FM][FN];
 #pragma unroll
@@ -271,12 +272,12 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
     if (kt + 1 < nk) {
       const int k1 = (kt + 1) * BK;
 #pragma unroll
-      for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const u32x4*>(a_src[i] + k1);
+      for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i] + k1);
 #pragma unroll
       for (int i = 0; i < B_ITER; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          rb[i][r] = *reinterpret_cast<const u32x4*>(b_src[i] + (int64_t)(k1 + r) * n);
+          rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)(k1 + r) * n);
     }
     u32x4 ah[FM], bh[FN];
 #pragma unroll
@@ -309,7 +310,7 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
   }
 
   int unscale = 0;
-  if constexpr (KIND == LOWP_F16S) unscale = -(eS[leaf] + eT[leaf]);
+  if constexpr (KIND == LOWP_F16S) unscale = -(global_ptr(eS)[leaf] + global_ptr(eT)[leaf]);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll

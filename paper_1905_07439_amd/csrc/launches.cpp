@@ -62,8 +62,11 @@ rbc_status ensure_device(Plan& p) {
 
 namespace {
 
+// Device address of a level's table (null before the tables are uploaded,
+// when launch descriptions are built only to size a batch).
 const void* table(const Plan& p, int level, TabKind kind, bool f64) {
   const size_t idx = (size_t)level * 8 + (f64 ? 0 : 4) + (size_t)kind;
+  if (!p.dev_tables || idx >= p.tab_off.size()) return nullptr;
   return static_cast<const char*>(p.dev_tables) + p.tab_off[idx];
 }
 

@@ -1,14 +1,9 @@
-// Per-leaf power-of-two scales of the f16 leaf operands.
-//
-// A leaf operand S_l is a chain of folded combinations of blocks of A, so
-// |S_l| <= G_l max|A| with G_l the product over levels of the 1-norm of the
-// coefficient column used at that level (signs and permutations leave the
-// norm unchanged).  The gather writes rn_f16(2^e_l S_l) with
-// e_l = floor(log2(2^15 / (G_l max|A|))): no value can exceed 2^15 < 65504,
-// and the leaf kernel multiplies its f32 result by 2^-(eS_l + eT_l), exactly.
+// Per-leaf power-of-two scales of the f16 leaf operands (the bound is
+// explained in scale.hpp): max|X|, then one exponent per leaf.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "scale.hpp"
 
 namespace rbc {
 namespace {
@@ -18,35 +13,16 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     p[i] = v;
 }
 
-// max |X| over a rows x cols row-major matrix, as the bits of a non-negative
-// float (which order like unsigned integers), folded into *out by atomic max.
 __global__ __launch_bounds__(256) void k_maxabs(const float* __restrict__ X, int64_t ld, int64_t rows,
                                                 int64_t cols, uint32_t* out) {
-  float m = 0.f;
-  const int64_t total = rows * cols;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-    const int64_t r = i / cols, c = i - r * cols;
-    m = fmaxf(m, fabsf(X[r * ld + c]));
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+  scale::maxabs_part(X, ld, rows, cols, out, (int64_t)blockIdx.x * 256, (int64_t)gridDim.x * 256);
 }
 
 __global__ void k_leaf_scales(const uint32_t* maxbits, const float* __restrict__ G, int32_t* e,
                               int64_t n) {
   const float mx = __uint_as_float(*maxbits);
-  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x) {
-    const float bound = G[l] * mx;
-    int ex = 0;
-    if (bound > 0.f && isfinite(bound)) {
-      int x;
-      frexpf(32768.0f / bound, &x);  // 32768 / bound = m 2^x, m in [0.5, 1)
-      ex = x - 1;
-      ex = ex < -120 ? -120 : (ex > 120 ? 120 : ex);
-    }
-    e[l] = ex;
-  }
+  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x)
+    e[l] = scale::leaf_exponent(mx, G[l]);
 }
 
 }  // namespace

@@ -1,0 +1,50 @@
+// Device parts of the per-leaf power-of-two scales of f16 leaf operands,
+// shared by the stand-alone kernels and the batch engine.
+//
+// A leaf operand S_l is a chain of folded combinations of blocks of A, so
+// |S_l| <= G_l max|A| with G_l the product over levels of the 1-norm of the
+// coefficient column used at that level (signs and permutations leave the
+// norm unchanged).  The gather writes rn_f16(2^e_l S_l) with
+// e_l = floor(log2(2^15 / (G_l max|A|))): no value can exceed 2^15 < 65504,
+// and the leaf kernel multiplies its f32 result by 2^-(eS_l + eT_l), exactly.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "devptr.hpp"
+
+namespace rbc {
+namespace scale {
+
+// max |X| over elements i = first, first + stride, ... of a rows x cols
+// row-major matrix (256 threads), folded into *out as the bits of a
+// non-negative float (which order like unsigned integers) by atomic max.
+__device__ __forceinline__ void maxabs_part(const float* __restrict__ X, int64_t ld, int64_t rows,
+                                            int64_t cols, uint32_t* out, int64_t first, int64_t stride) {
+  const gbl<const float>* Xg = global_ptr(X);
+  float m = 0.f;
+  const int64_t total = rows * cols;
+  for (int64_t i = first + threadIdx.x; i < total; i += stride) {
+    const int64_t r = i / cols, c = i - r * cols;
+    m = fmaxf(m, fabsf(Xg[r * ld + c]));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__device__ __forceinline__ int32_t leaf_exponent(float mx, float G) {
+  const float bound = G * mx;
+  int ex = 0;
+  if (bound > 0.f && isfinite(bound)) {
+    int x;
+    frexpf(32768.0f / bound, &x);  // 32768 / bound = m 2^x, m in [0.5, 1)
+    ex = x - 1;
+    ex = ex < -120 ? -120 : (ex > 120 ? 120 : ex);
+  }
+  return ex;
+}
+
+}  // namespace scale
+}  // namespace rbc

@@ -1,0 +1,151 @@
+"""GPU checks of the batch engine (one persistent launch for many products).
+
+Every product of a batch must equal, bit for bit, the same product run alone
+by Plan.matmul (the stand-alone path, itself checked against the oracle in
+test_gpu_parity): the batch runs the same arithmetic in the same order.
+Exact schemes on small integers must also give the exact product, which
+checks the batch against the plain definition independently of the
+stand-alone path.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1905_07439_amd as rbc
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_PLANS = {}
+
+
+def _plan(n, names, prec):
+    key = (n, tuple(names), prec)
+    if key not in _PLANS:
+        _PLANS[key] = rbc.Plan(n, n, n, [rbc.Scheme.builtin(s) for s in names], prec)
+    return _PLANS[key]
+
+
+def _operands(n, seed, kind):
+    if kind == "int":
+        A = workloads.integers((n, n), 4000 + seed)
+        B = workloads.integers((n, n), 5000 + seed)
+    else:  # entries N(0,1) times 10^U(-3,3) per matrix
+        A = workloads.scaled_gaussian((n, n), 4000 + seed)
+        B = workloads.scaled_gaussian((n, n), 5000 + seed)
+    return (torch.from_numpy(np.ascontiguousarray(A, np.float32)).to(DEV),
+            torch.from_numpy(np.ascontiguousarray(B, np.float32)).to(DEV))
+
+
+F32_SPECS = [(("strassen", "strassen"), 256), (("laderman",), 192), (("laderman", "strassen"), 384),
+             (("strassen", "strassen", "strassen"), 512), (("strassen",), 320)]
+F16S_SPECS = [(("laderman",), 192), (("laderman",), 288), (("laderman", "strassen"), 480),
+              (("laderman", "strassen", "strassen"), 768), (("laderman", "strassen", "strassen"), 864),
+              (("laderman", "strassen", "strassen", "strassen"), 1536)]
+MODES = ["full", "signs", "perms", "none"]
+
+
+def _build(prec, specs, kind, reps=1, **opt):
+    items = []
+    b = rbc.Batch(**opt)
+    for r in range(reps):
+        for i, (names, n) in enumerate(specs):
+            seed = r * len(specs) + i
+            plan = _plan(n, names, prec)
+            A, B = _operands(n, seed, kind)
+            mode = MODES[seed % len(MODES)]
+            _, C = b.add(plan, A, B, seed=seed, mode=mode)
+            items.append((plan, A, B, seed, mode, C))
+    return b, items
+
+
+def _alone(items):
+    out = []
+    for plan, A, B, seed, mode, _ in items:
+        out.append(plan.matmul(A, B, seed=seed, mode=mode).clone())
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("prec,specs", [("f32", F32_SPECS), ("f16s", F16S_SPECS)])
+def test_batch_equals_alone_bitwise(prec, specs):
+    b, items = _build(prec, specs, "gauss")
+    _say("batch", prec, b.info())
+    b.prepare()
+    b.launch()
+    b.check()
+    ref = _alone(items)
+    for (plan, A, B, seed, mode, C), R in zip(items, ref):
+        _say("  n=%d seed=%d mode=%s" % (A.shape[0], seed, mode))
+        assert torch.isfinite(C).all()
+        assert torch.equal(C, R), (A.shape[0], seed, mode, (C - R).abs().max().item())
+
+
+def test_batch_f32_integers_exact():
+    b, items = _build("f32", F32_SPECS, "int")
+    b.prepare()
+    b.launch()
+    b.check()
+    for plan, A, B, seed, mode, C in items:
+        exact = (A.double().cpu() @ B.double().cpu())
+        assert torch.equal(C.double().cpu(), exact), (A.shape[0], seed)
+
+
+def test_batch_options_ring_and_graph_replays():
+    """Window, task size and a workspace ring change the schedule, not one bit of any result;
+    graph replays, with other work between them, repeat the eager result."""
+    base, items = _build("f16s", F16S_SPECS, "gauss", reps=2)
+    base.prepare()
+    base.launch()
+    base.check()
+    want = [it[5].clone() for it in items]
+    biggest = max(it[0].workspace_bytes for it in items)
+    for opt in (dict(window=1), dict(window=8, task_bytes=1 << 16),
+                dict(item_budget=int(biggest * 1.6), window=3)):
+        b, its = _build("f16s", F16S_SPECS, "gauss", reps=2, **opt)
+        _say("options", opt, b.info())
+        b.prepare()
+        b.launch()
+        b.check()
+        for it, w in zip(its, want):
+            assert torch.equal(it[5], w), opt
+    s = torch.cuda.Stream()
+    b, its = _build("f16s", F16S_SPECS, "gauss", reps=1, item_budget=int(biggest * 1.6))
+    with torch.cuda.stream(s):
+        b.prepare(stream=s)
+    for rep in range(3):
+        for it in its:
+            it[5].fill_(float("nan"))
+        x = torch.randn(1024, 1024, device=DEV)
+        (x @ x).sum().item()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        b.launch(graph=True, stream=s)
+        b.check(stream=s)
+        for it, w in zip(its, want):
+            assert torch.equal(it[5], w), rep
+
+
+def test_batch_reruns_and_check():
+    b, items = _build("f32", F32_SPECS[:2], "gauss")
+    b.prepare()
+    for _ in range(3):
+        b.launch()
+    b.check()
+    ref = _alone(items)
+    for it, R in zip(items, ref):
+        assert torch.equal(it[5], R)
