@@ -9,6 +9,7 @@ in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload approx3072     # approximate scheme, bf16 hi+lo leaves
+    python bench.py --workload batch512       # 512 products of mixed N in one persistent launch
     python bench.py --copy-calibration BYTES  # plain copy of known size (counter scale)
 """
 
@@ -124,6 +125,129 @@ def approx3072(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_levels(n):
+    """Laderman at the top, then Strassen until the leaf side is at most 128."""
+    m, s = n // 3, 0
+    while m > 128:
+        m //= 2
+        s += 1
+    return ["laderman"] + ["strassen"] * s
+
+
+def batch512(args):
+    """512 independent products, N_i = 96 k_i with k_i uniform on {2..24} (size seed 4000),
+    Laderman then Strassen to leaves of 64..128, f16 leaves with per-leaf power-of-two scales,
+    all in one persistent launch replayed from a HIP graph.  A_i, B_i are N(0,1) times one
+    factor 10^U(-3,3) per matrix (factor seeds 4000+i / 14000+i, entries from torch's
+    Philox generator seeded alike, on the GPU); algorithm seed i, mode full."""
+    import numpy as np
+    import torch
+
+    import paper_1905_07439_amd as rbc
+    import workloads
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    count = args.batch_count
+    sizes = workloads.batch_sizes(count, 4000)
+    L, S = rbc.Scheme.builtin("laderman"), rbc.Scheme.builtin("strassen")
+    plans16, plans32 = {}, {}
+    As, Bs, Cs = [], [], []
+    g = torch.Generator(device=dev)
+    for i, n in enumerate(sizes):
+        lv = batch_levels(n)
+        if n not in plans16:
+            sch = [L] + [S] * (len(lv) - 1)
+            plans16[n] = rbc.Plan(n, n, n, sch, prec="f16s")
+            plans32[n] = rbc.Plan(n, n, n, sch, prec="f32")
+        fa = 10.0 ** np.random.default_rng(4000 + i).uniform(-3, 3)
+        fb = 10.0 ** np.random.default_rng(14000 + i).uniform(-3, 3)
+        g.manual_seed(4000 + i)
+        As.append(torch.randn(n, n, device=dev, generator=g) * fa)
+        g.manual_seed(14000 + i)
+        Bs.append(torch.randn(n, n, device=dev, generator=g) * fb)
+        Cs.append(torch.empty(n, n, device=dev))
+    flops = sum(2.0 * n ** 3 for n in sizes)
+    traffic = sum(sum(plans16[n].traffic().values()) for n in sizes)
+
+    batch = rbc.Batch(item_budget=args.batch_budget_gb << 30)
+    for i, n in enumerate(sizes):
+        batch.add(plans16[n], As[i], Bs[i], C=Cs[i], seed=i, mode="full")
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        batch.prepare(stream=stream)
+    prep_s = time.perf_counter() - t0
+    info = batch.info()
+    for _ in range(args.warmup):
+        batch.launch(graph=True, stream=stream)
+    batch.check(stream=stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        batch.launch(graph=True, stream=stream)
+        ev[k + 1].record(stream)
+    batch.check(stream=stream)
+    wall_ms = (time.perf_counter() - w0) * 1e3 / args.steps
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    ms = float(np.mean(per))
+    value = flops / (ms * 1e-3) / 1e12
+
+    # accuracy of every product against the float64 product of the same operands
+    errs = []
+    for i in range(count):
+        ref = As[i].double() @ Bs[i].double()
+        errs.append(float(torch.linalg.norm(Cs[i].double() - ref) / torch.linalg.norm(ref)))
+    errs = np.array(errs)
+
+    # the same products one by one on the same GPU: stand-alone f16s path, the plain f32
+    # recursive form, and the standard f32 product (torch -> hipBLASLt)
+    def seq(fn, reps=1):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    C32 = [torch.empty_like(c) for c in Cs[:1]]
+    seq16 = seq(lambda: [plans16[n].matmul(As[i], Bs[i], C=Cs[i], seed=i) for i, n in enumerate(sizes)])
+    seq32 = seq(lambda: [plans32[n].matmul(As[i], Bs[i], C=Cs[i], seed=i) for i, n in enumerate(sizes)])
+    errs32 = []
+    for i in range(0, count, 16):
+        ref = As[i].double() @ Bs[i].double()
+        errs32.append(float(torch.linalg.norm(Cs[i].double() - ref) / torch.linalg.norm(ref)))
+    std32 = seq(lambda: [torch.matmul(As[i], Bs[i], out=Cs[i]) for i in range(count)])
+    del C32
+
+    out = {
+        "metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "wall_ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16 leaves (f32 accumulate)",
+        "data": "synthetic",
+        "config": {"workload": "batch of %d products, N = 96k, k ~ U{2..24}, Laderman then Strassen to "
+                               "leaves 64..128, f16 leaves with per-leaf 2^e scales, one persistent launch "
+                               "in a HIP graph" % count,
+                   "count": count, "effective_tflop": round(flops / 1e12, 4),
+                   "item_budget_gb": args.batch_budget_gb, "parallelism": "single GPU"},
+        "rel_err_vs_fp64": {"median": float(np.median(errs)), "max": float(errs.max())},
+        "batch": {k: info[k] for k in ("n_tasks", "gather_tasks", "leaf_tasks", "scatter_tasks", "gate_tasks",
+                                       "grid", "workspace_bytes")},
+        "prepare_s": round(prep_s, 3),
+        "same_gpu": {"f16s_one_by_one_ms": round(seq16, 3), "f32_recursive_one_by_one_ms": round(seq32, 3),
+                     "f32_recursive_rel_err_max": max(errs32),
+                     "standard_f32_gemm_one_by_one_ms": round(std32, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(traffic / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes": traffic},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes):
     """A plain device copy of nbytes (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
     import torch
@@ -142,7 +266,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="strassen4096", choices=["strassen4096", "approx3072"])
+    ap.add_argument("--workload", default="strassen4096", choices=["strassen4096", "approx3072", "batch512"])
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-budget-gb", type=int, default=24)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -153,6 +279,8 @@ def main():
         return copy_calibration(args.copy_calibration)
     if args.workload == "approx3072":
         return approx3072(args)
+    if args.workload == "batch512":
+        return batch512(args)
 
     import numpy as np
     import torch

@@ -154,10 +154,17 @@ rbc_status rbc_fold(rbc_scheme s, const int32_t* signs, const int32_t* perms, in
  * prod b1, prod b2, prod b3, rounded up to the leaf GEMM tile; A and B are
  * zero padded virtually (never copied).  leaf_tile = 0 picks the tile
  * automatically; otherwise it is the square tile edge (f32, bf16x3: 64 or
- * 128; f16s: 32, 64 or 128; f64: 16).  levels may be 0 (plain product by the leaf kernel). */
+ * 128; f16s: 32, 64, 96 or 128; f64: 16).  levels may be 0 (plain product by the leaf kernel). */
 rbc_status rbc_plan_create(int64_t M, int64_t K, int64_t N, int levels, const rbc_scheme* schemes,
                            rbc_prec prec, int leaf_tile, rbc_plan* out);
 rbc_status rbc_plan_get_info(rbc_plan p, rbc_plan_info* info);
+/* Algorithmic HBM bytes of one product, per stage: bytes[0] gathers of A,
+ * bytes[1] gathers of B (with the max|X| pass of f16s), bytes[2] leaf
+ * products (S and T read once, P written once), bytes[3] scatters.  Every
+ * stage counts each element it must read and write once: the readable part
+ * of a top block (virtual padding is never read), every bottom block, and the
+ * writable part of C. */
+rbc_status rbc_plan_traffic(rbc_plan p, double bytes[4]);
 void rbc_plan_destroy(rbc_plan p);
 
 /* ---- products ------------------------------------------------------------ */
@@ -226,10 +233,10 @@ rbc_status rbc_plan_timing_collect(rbc_plan p, double ms[4], int64_t* calls);
  * wait that exceeds it stops the whole kernel and rbc_batch_check reports
  * RBC_EHIP (the results are then incomplete). */
 typedef struct {
-  int32_t window;      /* products whose tasks are interleaved in the queue (0: 4) */
+  int32_t window;      /* products whose tasks are interleaved in the queue (0: 32) */
   int32_t grid;        /* workgroups of the persistent kernel (0: resident maximum) */
   int32_t timeout_ms;  /* limit of one dependency wait (0: 5000) */
-  int32_t reserved;
+  int32_t trace;       /* nonzero: record per-task timestamps (rbc_batch_trace) */
   int64_t task_bytes;  /* HBM bytes one task aims to move (0: 256 KiB) */
   int64_t item_budget; /* bytes for the products' stage buffers (0: one region per product).
                         * With a budget the regions form a ring: a product reuses the
@@ -289,6 +296,12 @@ typedef struct {
   int32_t gate_counter, done_counter;
 } rbc_batch_item;
 rbc_status rbc_batch_get_item(rbc_batch b, int64_t index, rbc_batch_item* out);
+/* With options.trace: after a run has completed, copy up to cap records of
+ * 4 words per task (queue order): device wall-clock ticks when the task was
+ * taken, when its dependencies were met and when it was signalled, then the
+ * workgroup that ran it.  *n receives the task count, *ticks_per_us (may be
+ * NULL) the clock rate. */
+rbc_status rbc_batch_trace(rbc_batch b, uint64_t* out, int64_t cap, int64_t* n, double* ticks_per_us);
 /* Copy up to cap tasks of the last built table into out (host memory; out may
  * be NULL with cap 0) and the table's length into *n. */
 rbc_status rbc_batch_task_table(rbc_batch b, rbc_batch_task* out, int64_t cap, int64_t* n);

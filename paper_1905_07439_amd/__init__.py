@@ -150,6 +150,12 @@ class Plan:
     def workspace_bytes(self):
         return self.info["workspace_bytes"]
 
+    def traffic(self):
+        """Algorithmic HBM bytes per stage: {gather_A, gather_B, leaf, scatter}."""
+        b = (ctypes.c_double * 4)()
+        check(lib().rbc_plan_traffic(self._h, b))
+        return dict(zip(("gather_A", "gather_B", "leaf", "scatter"), list(b)))
+
     @property
     def dtype(self):
         import torch
@@ -266,9 +272,9 @@ class Batch:
     batch is in use.
     """
 
-    def __init__(self, window=0, grid=0, timeout_ms=0, task_bytes=0, item_budget=0):
+    def __init__(self, window=0, grid=0, timeout_ms=0, task_bytes=0, item_budget=0, trace=False):
         opt = BatchOptions(window=window, grid=grid, timeout_ms=timeout_ms, task_bytes=task_bytes,
-                           item_budget=item_budget)
+                           item_budget=item_budget, trace=int(bool(trace)))
         h = ctypes.c_void_p()
         check(lib().rbc_batch_create(ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -336,6 +342,19 @@ class Batch:
         check(lib().rbc_batch_task_table(self._h, out.ctypes.data_as(ctypes.c_void_p), n.value,
                                          ctypes.byref(n)))
         return out
+
+    def trace(self):
+        """Per-task (taken, ready, done) times in microseconds from the first task taken, and
+        the workgroup, of the last completed run (needs ``trace=True``)."""
+        n = ctypes.c_int64()
+        rate = ctypes.c_double()
+        check(lib().rbc_batch_trace(self._h, None, 0, ctypes.byref(n), ctypes.byref(rate)))
+        raw = np.zeros((n.value, 4), dtype=np.uint64)
+        check(lib().rbc_batch_trace(self._h, raw.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n),
+                                    None))
+        t = raw[:, :3].astype(np.float64)
+        t0 = t[:, 0].min() if len(t) else 0.0
+        return (t - t0) / rate.value, raw[:, 3].astype(np.int64)
 
     def item(self, index):
         """Workspace region, first queue index and counters of product ``index``."""

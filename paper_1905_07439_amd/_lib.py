@@ -34,7 +34,7 @@ class PlanInfo(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("grid", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("task_bytes", c_i64), ("item_budget", c_i64)]
+                ("trace", ctypes.c_int32), ("task_bytes", c_i64), ("item_budget", c_i64)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -72,6 +72,7 @@ SIGNATURES = {
     "rbc_plan_create": (ctypes.c_int, [c_i64, c_i64, c_i64, ctypes.c_int, ctypes.POINTER(c_vp),
                                        ctypes.c_int, ctypes.c_int, ctypes.POINTER(c_vp)]),
     "rbc_plan_get_info": (ctypes.c_int, [c_vp, ctypes.POINTER(PlanInfo)]),
+    "rbc_plan_traffic": (ctypes.c_int, [c_vp, c_dbl_p]),
     "rbc_plan_destroy": (None, [c_vp]),
     "rbc_matmul": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, ctypes.c_uint64,
                                   ctypes.c_int, ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]),
@@ -92,6 +93,7 @@ SIGNATURES = {
     "rbc_batch_launch": (ctypes.c_int, [c_vp, c_vp, ctypes.c_int]),
     "rbc_batch_check": (ctypes.c_int, [c_vp, c_vp]),
     "rbc_batch_get_info": (ctypes.c_int, [c_vp, ctypes.POINTER(BatchInfo)]),
+    "rbc_batch_trace": (ctypes.c_int, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64), c_dbl_p]),
     "rbc_batch_get_item": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(BatchItem)]),
     "rbc_batch_task_table": (ctypes.c_int, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
     "rbc_batch_destroy": (None, [c_vp]),

@@ -162,6 +162,37 @@ rbc_status rbc_plan_get_info(rbc_plan h, rbc_plan_info* info) {
   return RBC_OK;
 }
 
+rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
+  if (!h || !bytes) return fail(RBC_EINVAL, "null argument");
+  const Plan& p = h->p;
+  const double e = p.prec == RBC_PREC_F64 ? 8 : 4;              // combination element
+  const double e_leaf = p.prec == RBC_PREC_F64 ? 8 : (p.prec == RBC_PREC_F16S ? 2 : 4);  // leaf operand
+  const double e_prod = p.prec == RBC_PREC_F64 ? 8 : 4;         // leaf product
+  const double e_mid = (p.prec == RBC_PREC_F64 || p.prec == RBC_PREC_BF16X3) ? 8 : 4;  // recombination
+  const double e_out = p.prec == RBC_PREC_F64 ? 8 : 4;          // C
+  for (int i = 0; i < 4; ++i) bytes[i] = 0;
+  const size_t ng = p.groups.size();
+  for (size_t gi = 0; gi < ng; ++gi) {
+    const Group& g = p.groups[gi];
+    const bool last = gi + 1 == ng;
+    const double n_out = (double)g.n_in * g.Rg;
+    // gathers: the readable part of every top block once, every bottom block once
+    const double rdA = gi == 0 ? (double)p.M * p.K : (double)g.n_in * g.a_rows_top * g.a_cols_top;
+    const double rdB = gi == 0 ? (double)p.K * p.N : (double)g.n_in * g.b_rows_top * g.b_cols_top;
+    const double wo = last ? e_leaf : e;
+    bytes[0] += rdA * e + n_out * g.a_rows_bot * g.a_cols_bot * wo;
+    bytes[1] += rdB * e + n_out * g.b_rows_bot * g.b_cols_bot * wo;
+    // scatter: every bottom block once, the writable part of every top block once
+    const double rp = last ? e_prod : e_mid;
+    const double wc = gi == 0 ? (double)p.M * p.N * e_out : (double)g.n_in * g.c_rows_top * g.c_cols_top * e_mid;
+    bytes[3] += n_out * g.c_rows_bot * g.c_cols_bot * rp + wc;
+  }
+  if (p.prec == RBC_PREC_F16S) bytes[0] += (double)p.M * p.K * 4, bytes[1] += (double)p.K * p.N * 4;  // max|X|
+  bytes[2] = (double)p.n_leaves * ((double)p.mM * p.mK * e_leaf + (double)p.mK * p.mN * e_leaf +
+                                   (double)p.mM * p.mN * e_prod);
+  return RBC_OK;
+}
+
 void rbc_plan_destroy(rbc_plan h) {
   if (!h) return;
   Plan& p = h->p;

@@ -41,7 +41,7 @@ struct Item {
 };
 
 struct Layout {  // byte offsets inside the batch workspace
-  size_t tasks = 0, gather = 0, scatter = 0, leaf = 0, scale = 0, ctl = 0, items = 0, total = 0;
+  size_t tasks = 0, gather = 0, scatter = 0, leaf = 0, scale = 0, ctl = 0, trace = 0, items = 0, total = 0;
   std::vector<size_t> item_ws;
 };
 
@@ -244,8 +244,7 @@ struct Builder {
         d.maxbits = nullptr;  // the counter word cbits[sd], set once the layout is known
         b.cslots.push_back(cbits[sd]);
         d.G = l.G, d.e = l.e, d.n_leaves = l.n_leaves;
-        const int64_t total = l.rows * l.cols;
-        d.pieces = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+        d.pieces = l.rows;  // one piece per row
         max_pieces[sd] = d.pieces;
         b.cparams.push_back(d);
       }
@@ -256,7 +255,8 @@ struct Builder {
         Task t = proto;
         t.kind = TK_MAXABS, t.param = cidx + sd, t.signal = cmax[sd];
         t.wait[0] = out.gate, t.need[0] = 0;  // entry task; the need is set with the schedule
-        split(T, t, 0, max_pieces[sd], pieces_per_task(256 * 4));
+        const ScaleDesc& d = b.cparams[cidx + sd];
+        split(T, t, 0, max_pieces[sd], pieces_per_task(d.cols * 4));
       }
       for (int sd = 0; sd < 2; ++sd) {
         Task t = proto;
@@ -368,7 +368,7 @@ rbc_status make_schedule(const rbc_batch_s& b, const std::vector<size_t>& order,
   if (ring && biggest > budget)
     return fail(RBC_EINVAL, "batch: item budget %zu bytes < %zu needed by one product", budget, biggest);
   sc.region_bytes = ring ? budget : total;
-  const int window = b.opt.window > 0 ? b.opt.window : 4;
+  const int window = b.opt.window > 0 ? b.opt.window : 32;
   const size_t chunk = 32;
   struct Live {
     size_t item, lo, hi;
@@ -498,7 +498,8 @@ rbc_status build(rbc_batch_s& b, char* ws) {
   L.leaf = align_up(L.scatter + b.sparams.size() * sizeof(ScatterParams));
   L.scale = align_up(L.leaf + b.lparams.size() * sizeof(LeafDesc));
   L.ctl = align_up(L.scale + b.cparams.size() * sizeof(ScaleDesc));
-  L.items = align_up(L.ctl + (CTL_WORDS + b.n_counters) * sizeof(int32_t));
+  L.trace = align_up(L.ctl + (CTL_WORDS + b.n_counters) * sizeof(int32_t));
+  L.items = align_up(L.trace + (b.opt.trace ? b.tasks.size() * 4 * sizeof(uint64_t) : 0));
   L.total = L.items + sc.region_bytes;
   L.item_ws = sc.offs;
   b.ws = ws;
@@ -630,6 +631,7 @@ rbc_status enqueue(rbc_batch_s& b, hipStream_t s) {
   a.ctl = reinterpret_cast<int32_t*>(b.ws + L.ctl);
   a.n_ctl = CTL_WORDS + b.n_counters;
   a.timeout_ticks = b.timeout_ticks;
+  a.trace = b.opt.trace ? reinterpret_cast<uint64_t*>(b.ws + L.trace) : nullptr;
   HIP_CHECK(launch_batch(b.prec, a, b.grid, s));
   return RBC_OK;
 }
@@ -710,6 +712,21 @@ rbc_status rbc_batch_task_table(rbc_batch b, rbc_batch_task* out, int64_t cap, i
   *n = (int64_t)b->tasks.size();
   const int64_t k = std::min<int64_t>(cap, *n);
   if (k > 0) std::memcpy(out, b->tasks.data(), (size_t)k * sizeof(Task));
+  return RBC_OK;
+}
+
+rbc_status rbc_batch_trace(rbc_batch b, uint64_t* out, int64_t cap, int64_t* n, double* ticks_per_us) {
+  if (!b || !n) return fail(RBC_EINVAL, "null argument");
+  if (!b->opt.trace || !b->prepared) return fail(RBC_EINVAL, "batch has no trace (options.trace, then prepare)");
+  *n = (int64_t)b->tasks.size();
+  if (ticks_per_us) {
+    int rate_khz = 0;
+    HIP_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device));
+    *ticks_per_us = rate_khz / 1000.0;
+  }
+  if (cap < 0 || (cap > 0 && !out)) return fail(RBC_EINVAL, "bad output buffer");
+  const int64_t k = std::min<int64_t>(cap, *n);
+  if (k > 0) HIP_CHECK(hipMemcpy(out, b->ws + b->lay.trace, (size_t)k * 4 * sizeof(uint64_t), hipMemcpyDeviceToHost));
   return RBC_OK;
 }
 

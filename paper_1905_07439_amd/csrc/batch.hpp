@@ -55,9 +55,8 @@ struct LeafDesc {
   const int32_t* eT;
 };
 
-// f16s operand scale of one item side: maxabs pieces cover 256 elements
-// per piece with a stride of `pieces` * 256; the exponent task writes every
-// leaf's exponent.
+// f16s operand scale of one item side: a maxabs piece is one row of the
+// operand (pieces = rows); the exponent task writes every leaf's exponent.
 struct ScaleDesc {
   const float* X;
   int64_t ld, rows, cols;
@@ -97,7 +96,7 @@ constexpr CombVariant kScatters[] = {
 // the plan's tile, which keeps the kernel's register budget.
 constexpr LeafVariant kLeaves[] = {
     {RBC_PREC_F32, 64, 32}, {RBC_PREC_F32, 64, 16},
-    {RBC_PREC_F16S, 128, 32}, {RBC_PREC_F16S, 64, 32}, {RBC_PREC_F16S, 32, 32},
+    {RBC_PREC_F16S, 128, 32}, {RBC_PREC_F16S, 96, 32}, {RBC_PREC_F16S, 64, 32}, {RBC_PREC_F16S, 32, 32},
 };
 constexpr int kNumGathers = sizeof(kGathers) / sizeof(kGathers[0]);
 constexpr int kNumScatters = sizeof(kScatters) / sizeof(kScatters[0]);
@@ -116,6 +115,7 @@ struct KernelArgs {
   int32_t* ctl;            // CTL_WORDS control words, then the counters
   int64_t n_ctl;           // words zeroed before every run (control + counters)
   int64_t timeout_ticks;   // wall-clock limit of one dependency wait
+  uint64_t* trace;         // null, or 4 words per task (taken, ready, done, workgroup)
 };
 
 // Host side of the kernel (batch.hip).  prec selects the kernel instance:

@@ -1,12 +1,17 @@
 // The persistent batch kernel (see batch.hpp for the task model).
 //
-// Synchronisation: a task's writes are made visible at agent scope by a
-// release fence in every thread, then one barrier, then thread 0 adds the
-// task's piece count to its completion counter.  A waiting task's thread 0
-// polls its counters with agent-scope atomic loads (sleeping between polls),
-// then every thread takes an agent-scope acquire fence before reading the
-// data.  The fences write back and invalidate the per-XCD L2 as the memory
-// model requires, so producers and consumers may run on different XCDs.
+// Synchronisation: after a task, a barrier (which waits until every
+// wavefront's stores have completed) is followed by thread 0's agent-scope
+// release fence and the atomic add of the task's piece count to its
+// completion counter.  A waiting task's thread 0 polls its counters with
+// agent-scope atomic loads (sleeping between polls) and then takes an
+// agent-scope acquire fence before the barrier that releases the other
+// wavefronts.  On this hardware those fences act on caches that the whole
+// workgroup shares: the release writes back the XCD's L2 (which holds every
+// wavefront's completed stores), the acquire invalidates the CU's L1 and the
+// XCD's L2 before any wavefront of the workgroup loads task data.  So one
+// fence per task and direction is enough, and producers and consumers may run
+// on different XCDs.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -25,14 +30,28 @@ struct Smem {
                            : sizeof(uint16_t) * tiles::LowpTile<tiles::LOWP_F16S, 128, 128>::SMEM_HALVES;
 };
 
+// Most outputs per top block among the compiled gathers (f16s exponents in LDS).
+constexpr int max_gather_outputs() {
+  int m = 0;
+  for (const CombVariant& v : kGathers) {
+    int o = 1;
+    for (int l = 0; l < v.nl; ++l) o *= v.R;
+    m = o > m ? o : m;
+  }
+  return m;
+}
+constexpr int kMaxGatherOutputs = max_gather_outputs();
+
 template <int PREC>
 constexpr bool gather_in(const CombVariant& v) {
   return v.out == OUT_SAME || (PREC == RBC_PREC_F16S && v.out == OUT_F16S);
 }
 
 template <int OUTF, int V, int NL, int BR, int BC, int R>
-__device__ __forceinline__ void gather_task(const GatherParams& p, int64_t first, int count, int64_t in) {
-  for (int c = 0; c < count; ++c) comb::gather_block<float, OUTF, V, NL, BR, BC, R>(p, first + c, in);
+__device__ __forceinline__ void gather_task(const GatherParams& p, int64_t first, int count, int64_t in,
+                                            int32_t* exps) {
+  if constexpr (OUTF == OUT_F16S) comb::load_exponents<NL, R>(p, in, exps);
+  for (int c = 0; c < count; ++c) comb::gather_block<float, OUTF, V, NL, BR, BC, R>(p, first + c, in, exps);
 }
 
 template <int V, int NL, int BR, int BC, int R>
@@ -58,13 +77,13 @@ __device__ __forceinline__ void leaf_task(const LeafDesc& d, int64_t first, int 
 
 template <int PREC, int I>
 __device__ __forceinline__ void run_gather(int v, const GatherParams& p, int64_t first, int count,
-                                           int64_t in) {
+                                           int64_t in, int32_t* exps) {
   if constexpr (I < kNumGathers) {
     constexpr CombVariant G = kGathers[I];
     if constexpr (gather_in<PREC>(G)) {
-      if (v == I) return gather_task<G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, first, count, in);
+      if (v == I) return gather_task<G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, first, count, in, exps);
     }
-    run_gather<PREC, I + 1>(v, p, first, count, in);
+    run_gather<PREC, I + 1>(v, p, first, count, in, exps);
   }
 }
 
@@ -119,6 +138,9 @@ __device__ __forceinline__ bool wait_for(const int32_t* c, int32_t need, int32_t
 // restructure the loop so that the other lanes reach the next barrier without
 // the leader, re-reading the previous task.  Called by every thread, the
 // functions leave the kernel's loop without any divergent branch.
+// With a trace buffer, thread 0 records per task: the wall clock when the
+// task was taken, when its dependencies were met, when it was signalled, and
+// the workgroup that ran it.
 __device__ __noinline__ void leader_pop(int32_t* ctl, int64_t n_tasks, int32_t* slot) {
   if (threadIdx.x == 0) {
     int32_t t = atomicAdd(ctl + CTL_HEAD, 1);
@@ -128,18 +150,30 @@ __device__ __noinline__ void leader_pop(int32_t* ctl, int64_t n_tasks, int32_t* 
 }
 
 __device__ __noinline__ void leader_wait(const Task* task, int32_t* ctl, int32_t t, int64_t timeout,
-                                         int32_t* slot) {
+                                         int32_t* slot, uint64_t* trace) {
   if (threadIdx.x == 0) {
+    const uint64_t t0 = trace ? wall_clock64() : 0;
     int32_t* cnt = ctl + CTL_WORDS;
     bool ok = true;
     if (task->wait[0] >= 0) ok = wait_for(cnt + task->wait[0], task->need[0], ctl, t, timeout);
     if (ok && task->wait[1] >= 0) ok = wait_for(cnt + task->wait[1], task->need[1], ctl, t, timeout);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *slot = ok;
+    if (trace) {
+      trace[(int64_t)t * 4 + 0] = t0;
+      trace[(int64_t)t * 4 + 1] = wall_clock64();
+      trace[(int64_t)t * 4 + 3] = blockIdx.x;
+    }
   }
 }
 
-__device__ __noinline__ void leader_signal(int32_t* ctl, int32_t signal, int32_t count) {
-  if (threadIdx.x == 0 && signal >= 0) atomicAdd(ctl + CTL_WORDS + signal, count);
+__device__ __noinline__ void leader_signal(int32_t* ctl, int32_t t, int32_t signal, int32_t count,
+                                           uint64_t* trace) {
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (signal >= 0) atomicAdd(ctl + CTL_WORDS + signal, count);
+    if (trace) trace[(int64_t)t * 4 + 2] = wall_clock64();
+  }
 }
 
 template <int PREC>
@@ -148,10 +182,11 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
                                                   const ScatterParams* __restrict__ scatter,
                                                   const LeafDesc* __restrict__ leaf,
                                                   const ScaleDesc* __restrict__ scale_d, int32_t* ctl,
-                                                  int64_t timeout_ticks) {
+                                                  int64_t timeout_ticks, uint64_t* trace) {
   __shared__ __attribute__((aligned(16))) char smem[Smem<PREC>::bytes];
   __shared__ int32_t s_task;
   __shared__ int32_t s_ok;
+  __shared__ int32_t s_exps[kMaxGatherOutputs];
   for (;;) {
     leader_pop(ctl, n_tasks, &s_task);
     __syncthreads();
@@ -160,15 +195,13 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
     const int32_t t = __builtin_amdgcn_readfirstlane(s_task);
     if (t >= n_tasks) break;
     const Task& task = tasks[t];
-    leader_wait(&task, ctl, t, timeout_ticks, &s_ok);
+    leader_wait(&task, ctl, t, timeout_ticks, &s_ok, trace);
     __syncthreads();
     if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     switch (task.kind) {
       case TK_MAXABS: {
         const ScaleDesc& d = scale_d[task.param];
-        for (int c = 0; c < task.count; ++c)
-          scale::maxabs_part(d.X, d.ld, d.rows, d.cols, d.maxbits, (task.first + c) * 256, d.pieces * 256);
+        scale::maxabs_fold(scale::maxabs_rows(d.X, d.ld, d.cols, task.first, task.count), d.maxbits);
         break;
       }
       case TK_EXPONENTS: {
@@ -180,7 +213,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
         break;
       }
       case TK_GATHER:
-        run_gather<PREC, 0>(task.variant, gather[task.param], task.first, task.count, task.sub);
+        run_gather<PREC, 0>(task.variant, gather[task.param], task.first, task.count, task.sub, s_exps);
         break;
       case TK_LEAF:
         run_leaf<PREC, 0>(task.variant, leaf[task.param], task.first, task.count, smem);
@@ -191,9 +224,8 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
       default:
         break;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    leader_signal(ctl, task.signal, task.count);
+    leader_signal(ctl, t, task.signal, task.count, trace);
   }
 }
 static __global__ void k_zero_words(int32_t* p, int64_t n) {
@@ -212,7 +244,7 @@ hipError_t launch(const KernelArgs& a, int grid, hipStream_t s) {
   if (zb > 1024) zb = 1024;
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)zb), dim3(256), 0, s, a.ctl, a.n_ctl);
   hipLaunchKernelGGL(k_batch<PREC>, dim3((unsigned)grid), dim3(256), 0, s, a.tasks, a.n_tasks, a.gather,
-                     a.scatter, a.leaf, a.scale, a.ctl, a.timeout_ticks);
+                     a.scatter, a.leaf, a.scale, a.ctl, a.timeout_ticks, a.trace);
   return hipGetLastError();
 }
 

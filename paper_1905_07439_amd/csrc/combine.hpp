@@ -83,14 +83,15 @@ template <typename T, int OUTF, int V>
 struct GatherEmit {
   void* dst;
   int64_t dst_batch, plane, off;
-  const int32_t* scale_exp;
+  const int32_t* exps;  // f16s: LDS copy of the exponents of outputs exp_base, exp_base + 1, ...
+  int64_t exp_base;
   __device__ __forceinline__ void operator()(int64_t idx, VecT<T, V> v) const {
     if constexpr (OUTF == OUT_SAME) {
       // streaming store: the leaf operands are read once, by the next kernel
       vstore<T, V>(global_ptr(static_cast<T*>(dst)) + idx * dst_batch + off, v);
     } else if constexpr (OUTF == OUT_F16S) {
       // scaled leaf operand: rn_f16(2^e v), e chosen per leaf so nothing overflows
-      const int ex = global_ptr(scale_exp)[idx];
+      const int ex = exps[idx - exp_base];
       VecT<uint16_t, V> h;
 #pragma unroll
       for (int e = 0; e < V; ++e) h[e] = __builtin_bit_cast(uint16_t, (_Float16)ldexpf((float)v[e], ex));
@@ -153,11 +154,31 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
   }
 }
 
+// Outputs of one top block in a gather group (R == 0: the level's own count,
+// at most kMaxR for a single level).
+template <int NL, int R>
+constexpr int group_outputs() {
+  return R ? ipow(R, NL) : kMaxR;
+}
+
+// f16s: copy the scale exponents of top block `in`'s outputs into LDS (every
+// thread of the workgroup calls this; it ends with a barrier).  Each output
+// block's exponent is then one LDS read instead of a dependent global load.
+template <int NL, int R>
+__device__ __forceinline__ void load_exponents(const GatherParams& p, int64_t in, int32_t* lds) {
+  const int n = R ? ipow(R, NL) : p.lev[0].R;
+  const gbl<const int32_t>* e = global_ptr(p.scale_exp) + in * n;
+  for (int j = threadIdx.x; j < n; j += 256) lds[j] = e[j];
+  __syncthreads();
+}
+
 // One workgroup's share of a gather: 256 threads x V positions (block bx of
 // the position range) of top block `in`.  Used by k_gather and by the batch
-// engine's persistent kernel.
+// engine's persistent kernel.  exps: for f16s outputs, top block `in`'s
+// exponents in LDS (load_exponents).
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
-__device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, int64_t in) {
+__device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, int64_t in,
+                                             const int32_t* exps) {
   constexpr int BB = BR * BC;
   constexpr int NSRC = ipow(BB, NL);
   const int64_t npos = p.rows_bot * p.cols_bot;
@@ -187,14 +208,24 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, 
         v[s][e] = (row < p.src_rows && col + e < p.src_cols) ? src[row * p.ld_src + col + e] : T(0);
     }
   }
-  GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, p.scale_exp};
+  const int64_t n_out = R ? ipow(R, NL) : p.lev[0].R;
+  GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, exps, in * n_out};
   gather_level<T, V, NL, BR, BC, R, 0>(v, p.lev, in, e);
 }
 
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
 __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
-  for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y)
-    gather_block<T, OUTF, V, NL, BR, BC, R>(p, blockIdx.x, in);
+  if constexpr (OUTF == OUT_F16S) {
+    __shared__ int32_t exps[group_outputs<NL, R>()];
+    for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
+      if (in != blockIdx.y) __syncthreads();  // the previous block's readers are done
+      load_exponents<NL, R>(p, in, exps);
+      gather_block<T, OUTF, V, NL, BR, BC, R>(p, blockIdx.x, in, exps);
+    }
+  } else {
+    for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y)
+      gather_block<T, OUTF, V, NL, BR, BC, R>(p, blockIdx.x, in, nullptr);
+  }
 }
 
 // Level LT of a scatter group: returns in `out` the BB^(NL-LT) values of the

@@ -7,7 +7,7 @@
 //           one power-of-two scale per leaf operand chosen by the gather so that
 //           no value can overflow; v_mfma_f32_16x16x32_f16.  The unscaling is exact.
 //
-// Tile BM x BN (32, 64 or 128) per workgroup of 4 wavefronts, each a
+// Tile BM x BN (32, 64, 96 or 128) per workgroup of 4 wavefronts, each a
 // (BM/2) x (BN/2) quarter of 16x16 MFMA tiles, K slabs of 32.  Both operands
 // are staged k-contiguous in LDS so that every MFMA operand is one 16-byte LDS
 // read (8 consecutive k of one row or column): S slabs are already k-contiguous
@@ -43,7 +43,7 @@ hipError_t launch_lowp(const uint16_t* S, const uint16_t* T, float* P, int64_t m
                        int64_t batch, int tile, const int32_t* eS, const int32_t* eT,
                        hipStream_t stream) {
   if (batch == 0 || m == 0 || n == 0) return hipSuccess;
-  if (m % tile || n % tile || k % 32 || (tile != 32 && tile != 64 && tile != 128))
+  if (m % tile || n % tile || k % 32 || (tile != 32 && tile != 64 && tile != 96 && tile != 128))
     return hipErrorInvalidValue;
   const int tiles_n = (int)(n / tile), tiles_per_leaf = (int)((m / tile) * tiles_n);
   const int64_t nblocks = batch * tiles_per_leaf;
@@ -52,6 +52,9 @@ hipError_t launch_lowp(const uint16_t* S, const uint16_t* T, float* P, int64_t m
   const dim3 grid((unsigned)nblocks), block(256);
   if (tile == 128)
     hipLaunchKernelGGL((k_gemm_lowp<KIND, 128, 128>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+                       (int)k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);
+  else if (tile == 96)
+    hipLaunchKernelGGL((k_gemm_lowp<KIND, 96, 96>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
                        (int)k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);
   else if (tile == 64)
     hipLaunchKernelGGL((k_gemm_lowp<KIND, 64, 64>), grid, block, 0, stream, S, T, P, (int)m, (int)n,

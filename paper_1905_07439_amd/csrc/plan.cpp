@@ -75,13 +75,13 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     if (leaf_tile == 0) {
       // the tile with the least padded leaf area (ties: the larger tile)
       int64_t best = -1;
-      for (int t : {128, 64, 32}) {
+      for (int t : {128, 96, 64, 32}) {
         const int64_t area = round_up(lm, t) * round_up(ln, t);
         if (best < 0 || area < best) best = area, leaf_tile = t;
       }
     }
-    if (leaf_tile != 32 && leaf_tile != 64 && leaf_tile != 128)
-      return fail(RBC_EUNSUPPORTED, "f16s leaf tile must be 32, 64 or 128");
+    if (leaf_tile != 32 && leaf_tile != 64 && leaf_tile != 96 && leaf_tile != 128)
+      return fail(RBC_EUNSUPPORTED, "f16s leaf tile must be 32, 64, 96 or 128");
     p.tile_m = p.tile_n = leaf_tile;
     p.tile_k = 32;
   } else {

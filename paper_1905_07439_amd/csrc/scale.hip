@@ -15,7 +15,10 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 
 __global__ __launch_bounds__(256) void k_maxabs(const float* __restrict__ X, int64_t ld, int64_t rows,
                                                 int64_t cols, uint32_t* out) {
-  scale::maxabs_part(X, ld, rows, cols, out, (int64_t)blockIdx.x * 256, (int64_t)gridDim.x * 256);
+  // rows blockIdx.x, blockIdx.x + gridDim.x, ...
+  float m = 0.f;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) m = fmaxf(m, scale::maxabs_rows(X, ld, cols, r, 1));
+  scale::maxabs_fold(m, out);
 }
 
 __global__ void k_leaf_scales(const uint32_t* maxbits, const float* __restrict__ G, int32_t* e,
@@ -30,9 +33,7 @@ __global__ void k_leaf_scales(const uint32_t* maxbits, const float* __restrict__
 hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, uint32_t* maxbits,
                               const float* G, int32_t* e, int64_t n_leaves, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, maxbits, (int64_t)1, 0u);
-  const int64_t total = rows * cols;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  int64_t blocks = rows < 4096 ? rows : 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_maxabs, dim3((unsigned)blocks), dim3(256), 0, s, X, ld, rows, cols, maxbits);
   int64_t lb = (n_leaves + 255) / 256;

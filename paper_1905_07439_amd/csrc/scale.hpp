@@ -17,18 +17,21 @@
 namespace rbc {
 namespace scale {
 
-// max |X| over elements i = first, first + stride, ... of a rows x cols
-// row-major matrix (256 threads), folded into *out as the bits of a
-// non-negative float (which order like unsigned integers) by atomic max.
-__device__ __forceinline__ void maxabs_part(const float* __restrict__ X, int64_t ld, int64_t rows,
-                                            int64_t cols, uint32_t* out, int64_t first, int64_t stride) {
+// max |X| over rows [row0, row0 + nrows) of a row-major matrix with cols
+// columns and row stride ld: this thread's share (256 threads stride along
+// each row).
+__device__ __forceinline__ float maxabs_rows(const float* __restrict__ X, int64_t ld, int64_t cols,
+                                             int64_t row0, int64_t nrows) {
   const gbl<const float>* Xg = global_ptr(X);
   float m = 0.f;
-  const int64_t total = rows * cols;
-  for (int64_t i = first + threadIdx.x; i < total; i += stride) {
-    const int64_t r = i / cols, c = i - r * cols;
-    m = fmaxf(m, fabsf(Xg[r * ld + c]));
-  }
+  for (int64_t r = row0; r < row0 + nrows; ++r)
+    for (int64_t c = threadIdx.x; c < cols; c += 256) m = fmaxf(m, fabsf(Xg[r * ld + c]));
+  return m;
+}
+
+// Fold the threads' maxima into *out as the bits of a non-negative float
+// (which order like unsigned integers): one atomic max per wavefront.
+__device__ __forceinline__ void maxabs_fold(float m, uint32_t* out) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));

@@ -318,7 +318,8 @@ def test_bf16x3_end_to_end():
 
 
 F16S_CASES = [(["laderman", "strassen"], 480, 480, 480, 0), (["laderman"], 192, 192, 192, 0),
-              (["strassen", "strassen"], 300, 260, 200, 32), (["laderman", "strassen", "strassen"], 1152, 1152, 1152, 0)]
+              (["strassen", "strassen"], 300, 260, 200, 32), (["laderman", "strassen", "strassen"], 1152, 1152, 1152, 0),
+              (["strassen"], 200, 190, 180, 96)]
 
 
 @pytest.mark.parametrize("case", range(len(F16S_CASES)))

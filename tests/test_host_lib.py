@@ -146,8 +146,12 @@ def test_f16s_plan_geometry():
     S = rbc.Scheme.builtin("strassen")
     p = rbc.Plan(480, 480, 480, [L, S], prec="f16s")
     i = p.info
-    # leaf 80: tile 32 pads it to 96 (least padded area), K to a multiple of 32
-    assert (i["mM"], i["mK"], i["mN"], i["tile_m"]) == (96, 96, 96, 32)
+    # leaf 80: pads to 96 with the least padded area (tiles 96 and 32 tie; the larger
+    # wins), K to a multiple of 32
+    assert (i["mM"], i["mK"], i["mN"], i["tile_m"]) == (96, 96, 96, 96)
+    assert rbc.Plan(480, 480, 480, [L, S], prec="f16s", leaf_tile=32).info["mM"] == 96
+    with pytest.raises(rbc.RbcError):
+        rbc.Plan(480, 480, 480, [L, S], prec="f16s", leaf_tile=48)
     assert i["bytes_S"] == 161 * 96 * 96 * 2
     assert i["bytes_aux"] == 256 + 2 * 161 * 4 and i["off_aux"] >= i["off_P"] + i["bytes_P"]
     q = rbc.Plan(768, 768, 768, [L, S], prec="f16s")
