@@ -70,11 +70,17 @@ typedef enum {
   RBC_PREC_BF16X3 = 2, /* f32 combinations; leaf operands split hi+lo in bf16,
                           3 bf16 MFMA products with f32 accumulation; the
                           W-recombination in f64, C rounded to f32 */
-  RBC_PREC_F16S = 3    /* f32 combinations; each leaf operand scaled by a power
+  RBC_PREC_F16S = 3,   /* f32 combinations; each leaf operand scaled by a power
                           of two (from max|A| or max|B| and the coefficient
                           1-norms along its path, so that |2^e S| <= 2^15) and
                           rounded to f16; f16 MFMA with f32 accumulation, the
                           product unscaled exactly; f32 W-recombination */
+  RBC_PREC_FP8C = 4    /* f32 combinations; each leaf operand scaled as for
+                          f16s but to |2^e S| <= 448, then split into OCP e4m3
+                          hi = rn(2^e S) and lo = rn(16 (2^e S - hi)); fp8 MFMA
+                          with f32 accumulation of hi*hi and, in one correction
+                          pass, hi*lo + lo*hi (weighted 1/16); the product
+                          unscaled exactly; f32 W-recombination */
 } rbc_prec;
 
 typedef struct rbc_scheme_s* rbc_scheme;
@@ -94,8 +100,9 @@ typedef struct {
   size_t workspace_bytes;   /* minimum workspace for rbc_matmul */
   size_t off_S, off_T, off_P;      /* byte offsets of the leaf operands and products */
   size_t bytes_S, bytes_T, bytes_P;
-  size_t off_aux, bytes_aux;       /* RBC_PREC_F16S: max|A|, max|B| bits (2 x u32), then the
-                                      per-leaf exponents of S and of T (n_leaves int32 each) */
+  size_t off_aux, bytes_aux;       /* RBC_PREC_F16S, RBC_PREC_FP8C: max|A|, max|B| bits (2 x u32),
+                                      then the per-leaf exponents of S and of T (n_leaves int32
+                                      each) */
 } rbc_plan_info;
 
 const char* rbc_status_str(rbc_status s);
@@ -154,7 +161,7 @@ rbc_status rbc_fold(rbc_scheme s, const int32_t* signs, const int32_t* perms, in
  * prod b1, prod b2, prod b3, rounded up to the leaf GEMM tile; A and B are
  * zero padded virtually (never copied).  leaf_tile = 0 picks the tile
  * automatically; otherwise it is the square tile edge (f32, bf16x3: 64 or
- * 128; f16s: 32, 64, 96 or 128; f64: 16).  levels may be 0 (plain product by the leaf kernel). */
+ * 128; f16s, fp8c: 32, 64, 96 or 128; f64: 16).  levels may be 0 (plain product by the leaf kernel). */
 rbc_status rbc_plan_create(int64_t M, int64_t K, int64_t N, int levels, const rbc_scheme* schemes,
                            rbc_prec prec, int leaf_tile, rbc_plan* out);
 rbc_status rbc_plan_get_info(rbc_plan p, rbc_plan_info* info);
@@ -189,7 +196,9 @@ rbc_status rbc_matmul_draws(rbc_plan p, const void* A, int64_t lda, const void* 
  *          n_leaves row-major blocks in leaf order (r_0 slowest).  For
  *          RBC_PREC_BF16X3 the region holds the hi plane then the lo plane;
  *          for RBC_PREC_F16S it holds f16 values and the gather also writes
- *          the operand's per-leaf exponents in the auxiliary region.
+ *          the operand's per-leaf exponents in the auxiliary region; for
+ *          RBC_PREC_FP8C it holds the e4m3 hi plane then the lo plane (one
+ *          byte per element each), with exponents as for f16s.
  * leaf:    P_l = S_l T_l for every leaf l into info.off_P.
  * scatter: C from the P blocks through the folded W of every level.
  * The block combinations sum in a fixed order: S_r over (k, l) row-major and
@@ -214,8 +223,8 @@ rbc_status rbc_plan_timing_collect(rbc_plan p, double ms[4], int64_t* calls);
 
 /* ---- batches: many independent products in one persistent launch ---------
  * A batch holds products C_i = F-hat^(Q_i)(A_i, B_i), each with its own plan,
- * operands, seed and mode, all of one precision (RBC_PREC_F32 or
- * RBC_PREC_F16S; every level shape must be Strassen-shaped <2,2,2> with 7
+ * operands, seed and mode, all of one precision (RBC_PREC_F32,
+ * RBC_PREC_F16S or RBC_PREC_FP8C; every level shape must be Strassen-shaped <2,2,2> with 7
  * products or Laderman-shaped <3,3,3> with 23).  The library turns every
  * product into tasks (pieces of its gather, leaf and scatter stages), orders
  * them so that dependencies come first, and runs them all in one persistent

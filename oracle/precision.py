@@ -53,6 +53,27 @@ def round_e4m3(x, saturate=True):
 ROUND = {"bf16": round_bf16, "f16": round_f16, "e4m3": round_e4m3}
 
 
+def decode_e4m3(codes):
+    """Values of OCP E4M3FN byte codes: sign bit 7, exponent bits 6..3 (bias 7), fraction
+    bits 2..0; exponent 0 is subnormal (f * 2^-9); 0x7F and 0xFF are NaN."""
+    c = np.asarray(codes, dtype=np.uint8).astype(np.int64)
+    e = (c >> 3) & 15
+    f = c & 7
+    mag = np.where(e == 0, f * 2.0 ** -9, (8 + f) * 2.0 ** (e - 10))
+    mag = np.where((c & 0x7F) == 0x7F, np.nan, mag)
+    return np.where(c & 0x80, -mag, mag)
+
+
+def split_e4m3_scaled(y):
+    """The fp8 leaf split of an already scaled operand y (|y| <= 448): hi = rn_e4m3(y) and
+    lo = rn_e4m3(16 (y - hi)), so that y ~ hi + lo / 16 (y - hi computed in float64, exact
+    for float32 y)."""
+    y = np.asarray(y, dtype=np.float64)
+    hi = round_e4m3(y).astype(np.float64)
+    lo = round_e4m3(16.0 * (y - hi)).astype(np.float64)
+    return hi, lo
+
+
 def split_hi_lo(x, fmt="bf16"):
     rn = ROUND[fmt]
     x = np.asarray(x, dtype=np.float32)

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "librbc.so")
 
 RBC_OK, RBC_EINVAL, RBC_ESCHEME, RBC_ENOMEM, RBC_EHIP, RBC_EUNSUPPORTED = range(6)
 MODES = {"full": 0, "signs": 1, "perms": 2, "none": 3}
-PRECS = {"f64": 0, "f32": 1, "bf16x3": 2, "f16s": 3}
+PRECS = {"f64": 0, "f32": 1, "bf16x3": 2, "f16s": 3, "fp8c": 4}
 
 c_i64 = ctypes.c_int64
 c_dbl_p = ctypes.POINTER(ctypes.c_double)

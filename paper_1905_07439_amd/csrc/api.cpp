@@ -166,7 +166,8 @@ rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
   if (!h || !bytes) return fail(RBC_EINVAL, "null argument");
   const Plan& p = h->p;
   const double e = p.prec == RBC_PREC_F64 ? 8 : 4;              // combination element
-  const double e_leaf = p.prec == RBC_PREC_F64 ? 8 : (p.prec == RBC_PREC_F16S ? 2 : 4);  // leaf operand
+  const double e_leaf =
+      p.prec == RBC_PREC_F64 ? 8 : ((p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C) ? 2 : 4);  // leaf operand
   const double e_prod = p.prec == RBC_PREC_F64 ? 8 : 4;         // leaf product
   const double e_mid = (p.prec == RBC_PREC_F64 || p.prec == RBC_PREC_BF16X3) ? 8 : 4;  // recombination
   const double e_out = p.prec == RBC_PREC_F64 ? 8 : 4;          // C
@@ -187,7 +188,8 @@ rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
     const double wc = gi == 0 ? (double)p.M * p.N * e_out : (double)g.n_in * g.c_rows_top * g.c_cols_top * e_mid;
     bytes[3] += n_out * g.c_rows_bot * g.c_cols_bot * rp + wc;
   }
-  if (p.prec == RBC_PREC_F16S) bytes[0] += (double)p.M * p.K * 4, bytes[1] += (double)p.K * p.N * 4;  // max|X|
+  if (p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C)
+    bytes[0] += (double)p.M * p.K * 4, bytes[1] += (double)p.K * p.N * 4;  // max|X|
   bytes[2] = (double)p.n_leaves * ((double)p.mM * p.mK * e_leaf + (double)p.mK * p.mN * e_leaf +
                                    (double)p.mM * p.mN * e_prod);
   return RBC_OK;

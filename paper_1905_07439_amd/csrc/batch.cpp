@@ -96,7 +96,8 @@ int scatter_variant(const ScatterLaunch& s) {
 }
 
 // Leaf variant and tile geometry: f32 runs 64 x 64 tiles with the stand-alone
-// launch's K slab; f16s keeps the plan's tile.
+// launch's K slab; f16s keeps the plan's tile; fp8c keeps it except 128,
+// which runs as 64.
 int leaf_variant(const LeafLaunch& l, int* tile) {
   int t = 0, bk = 32;
   if (l.prec == RBC_PREC_F32) {
@@ -104,6 +105,9 @@ int leaf_variant(const LeafLaunch& l, int* tile) {
     bk = l.k % 32 == 0 ? 32 : 16;
   } else if (l.prec == RBC_PREC_F16S) {
     t = l.tile;
+  } else if (l.prec == RBC_PREC_FP8C) {
+    t = l.tile == 128 ? 64 : l.tile;
+    bk = 64;
   } else {
     return -1;
   }
@@ -116,8 +120,8 @@ int leaf_variant(const LeafLaunch& l, int* tile) {
 }
 
 rbc_status check_plan(const Plan& p) {
-  if (p.prec != RBC_PREC_F32 && p.prec != RBC_PREC_F16S)
-    return fail(RBC_EUNSUPPORTED, "batch: precision must be f32 or f16s");
+  if (p.prec != RBC_PREC_F32 && p.prec != RBC_PREC_F16S && p.prec != RBC_PREC_FP8C)
+    return fail(RBC_EUNSUPPORTED, "batch: precision must be f32, f16s or fp8c");
   if (p.Q < 1) return fail(RBC_EUNSUPPORTED, "batch: plans need at least one level");
   for (const Group& g : p.groups) {
     const int nl = g.d1 - g.d0;
@@ -180,8 +184,8 @@ struct Builder {
     out.gate = (int32_t)next++;
     out.done = (int32_t)next++;
     int32_t cmax[2] = {-1, -1}, cexp[2] = {-1, -1}, cbits[2] = {-1, -1};
-    const bool f16s = p.prec == RBC_PREC_F16S;
-    if (f16s)
+    const bool scaled = p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C;
+    if (scaled)
       for (int sd = 0; sd < 2; ++sd)
         cmax[sd] = (int32_t)next++, cexp[sd] = (int32_t)next++, cbits[sd] = (int32_t)next++;
     std::vector<int64_t> cg[2], cls;  // per group: first counter index
@@ -234,9 +238,9 @@ struct Builder {
     std::memset(&proto, 0, sizeof proto);
     proto.wait[0] = proto.wait[1] = proto.signal = -1;
 
-    // f16s: max|A|, max|B|, then the per-leaf exponents
+    // f16s, fp8c: max|A|, max|B|, then the per-leaf exponents
     int64_t max_pieces[2] = {0, 0};
-    if (f16s) {
+    if (scaled) {
       for (int sd = 0; sd < 2; ++sd) {
         const ScaleLaunch& l = (sd == 0 ? scA : scB)[0];
         ScaleDesc d;
@@ -245,12 +249,13 @@ struct Builder {
         b.cslots.push_back(cbits[sd]);
         d.G = l.G, d.e = l.e, d.n_leaves = l.n_leaves;
         d.pieces = l.rows;  // one piece per row
+        d.target = l.target, d.pad_ = 0;
         max_pieces[sd] = d.pieces;
         b.cparams.push_back(d);
       }
     }
-    const int32_t cidx = (int32_t)b.cparams.size() - (f16s ? 2 : 0);
-    if (f16s) {
+    const int32_t cidx = (int32_t)b.cparams.size() - (scaled ? 2 : 0);
+    if (scaled) {
       for (int sd = 0; sd < 2; ++sd) {
         Task t = proto;
         t.kind = TK_MAXABS, t.param = cidx + sd, t.signal = cmax[sd];
@@ -270,7 +275,7 @@ struct Builder {
     const int64_t R_last = p.groups[ng - 1].Rg;
     const int64_t tpl = ld.tiles_per_leaf;
     const int64_t leaf_piece_bytes =
-        (int64_t)tile * tile * 4 + (int64_t)2 * tile * lf.k * (f16s ? 2 : 4);
+        (int64_t)tile * tile * 4 + (int64_t)2 * tile * lf.k * (scaled ? 2 : 4);
 
     // depth-first emission
     struct Frame {
@@ -294,11 +299,11 @@ struct Builder {
           } else {
             t.wait[0] = out.gate, t.need[0] = 0;  // entry task
           }
-          if (g == ng - 1 && f16s) t.wait[1] = cexp[sd], t.need[1] = 1;
+          if (g == ng - 1 && scaled) t.wait[1] = cexp[sd], t.need[1] = 1;
           t.signal = (int32_t)(cg[sd][g] + fr.in);
           const CombVariant& v = kGathers[gvar[sd][g]];
           const int64_t nsrc = ipow(v.br * v.bc, v.nl);
-          const int out_bytes = v.out == OUT_F16S ? 2 : 4;
+          const int out_bytes = (v.out == OUT_F16S || v.out == OUT_FP8X2) ? 2 : 4;
           split(T, t, 0, gpieces[sd][g], pieces_per_task(256 * v.vec * (nsrc * 4 + G.Rg * out_bytes)));
         }
         stack.push_back({fr, true});

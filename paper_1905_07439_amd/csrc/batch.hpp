@@ -55,7 +55,7 @@ struct LeafDesc {
   const int32_t* eT;
 };
 
-// f16s operand scale of one item side: a maxabs piece is one row of the
+// f16s / fp8c operand scale of one item side: a maxabs piece is one row of the
 // operand (pieces = rows); the exponent task writes every leaf's exponent.
 struct ScaleDesc {
   const float* X;
@@ -65,6 +65,8 @@ struct ScaleDesc {
   int32_t* e;
   int64_t n_leaves;
   int64_t pieces;
+  float target;  // bound of the scaled operand (2^15 for f16, 448 for e4m3)
+  int32_t pad_;
 };
 
 struct CombVariant {
@@ -82,6 +84,8 @@ constexpr CombVariant kGathers[] = {
     {OUT_SAME, 1, 1, 2, 2, 7},  {OUT_SAME, 4, 2, 2, 2, 7},  {OUT_SAME, 1, 2, 2, 2, 7},
     {OUT_F16S, 4, 1, 3, 3, 23}, {OUT_F16S, 1, 1, 3, 3, 23}, {OUT_F16S, 4, 1, 2, 2, 7},
     {OUT_F16S, 1, 1, 2, 2, 7},  {OUT_F16S, 4, 2, 2, 2, 7},  {OUT_F16S, 1, 2, 2, 2, 7},
+    {OUT_FP8X2, 4, 1, 3, 3, 23}, {OUT_FP8X2, 1, 1, 3, 3, 23}, {OUT_FP8X2, 4, 1, 2, 2, 7},
+    {OUT_FP8X2, 1, 1, 2, 2, 7},  {OUT_FP8X2, 4, 2, 2, 2, 7},  {OUT_FP8X2, 1, 2, 2, 2, 7},
 };
 // Compiled scatter variants (float products, accumulation and output).  Two
 // fused levels keep 16 accumulators per position, so they run with at most
@@ -92,11 +96,12 @@ constexpr CombVariant kScatters[] = {
 };
 // Compiled leaf variants: (precision, square tile, K slab).  The tile edge
 // does not change any output element's summation order (that is fixed by the
-// K slab), so f32 leaves run with 64 x 64 tiles in the batch kernel whatever
-// the plan's tile, which keeps the kernel's register budget.
+// K slab), so f32 leaves run with 64 x 64 tiles and fp8c leaves of a 128-tile
+// plan with 64 x 64 tiles in the batch kernel, which keeps its register budget.
 constexpr LeafVariant kLeaves[] = {
     {RBC_PREC_F32, 64, 32}, {RBC_PREC_F32, 64, 16},
     {RBC_PREC_F16S, 128, 32}, {RBC_PREC_F16S, 96, 32}, {RBC_PREC_F16S, 64, 32}, {RBC_PREC_F16S, 32, 32},
+    {RBC_PREC_FP8C, 96, 64},  {RBC_PREC_FP8C, 64, 64}, {RBC_PREC_FP8C, 32, 64},
 };
 constexpr int kNumGathers = sizeof(kGathers) / sizeof(kGathers[0]);
 constexpr int kNumScatters = sizeof(kScatters) / sizeof(kScatters[0]);
@@ -118,8 +123,8 @@ struct KernelArgs {
   uint64_t* trace;         // null, or 4 words per task (taken, ready, done, workgroup)
 };
 
-// Host side of the kernel (batch.hip).  prec selects the kernel instance:
-// RBC_PREC_F32 or RBC_PREC_F16S.
+// Host side of the kernel (batch_*.hip).  prec selects the kernel instance:
+// RBC_PREC_F32, RBC_PREC_F16S or RBC_PREC_FP8C.
 hipError_t batch_occupancy(int prec, int* blocks_per_cu);
 hipError_t launch_batch(int prec, const KernelArgs& a, int grid, hipStream_t stream);
 

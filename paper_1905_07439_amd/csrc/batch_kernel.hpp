@@ -1,9 +1,10 @@
 // The persistent batch kernel (see batch.hpp for the task model).
 //
-// Synchronisation: after a task, a barrier (which waits until every
-// wavefront's stores have completed) is followed by thread 0's agent-scope
-// release fence and the atomic add of the task's piece count to its
-// completion counter.  A waiting task's thread 0 polls its counters with
+// Synchronisation: after a task, every wavefront waits until its own memory
+// operations have completed (s_waitcnt 0: the stores have reached the L2; the
+// workgroup barrier alone does not wait for global stores), then a barrier,
+// then thread 0's agent-scope release fence and the atomic add of the task's
+// piece count to its completion counter.  A waiting task's thread 0 polls its counters with
 // agent-scope atomic loads (sleeping between polls) and then takes an
 // agent-scope acquire fence before the barrier that releases the other
 // wavefronts.  On this hardware those fences act on caches that the whole
@@ -26,8 +27,9 @@ namespace batch {
 template <int PREC>
 struct Smem {
   static constexpr size_t bytes =
-      PREC == RBC_PREC_F32 ? sizeof(float) * tiles::F32Tile<64, 64, 32>::SMEM
-                           : sizeof(uint16_t) * tiles::LowpTile<tiles::LOWP_F16S, 128, 128>::SMEM_HALVES;
+      PREC == RBC_PREC_F32    ? sizeof(float) * tiles::F32Tile<64, 64, 32>::SMEM
+      : PREC == RBC_PREC_F16S ? sizeof(uint16_t) * tiles::LowpTile<tiles::LOWP_F16S, 128, 128>::SMEM_HALVES
+                              : tiles::Fp8Tile<96, 96>::SMEM_BYTES;
 };
 
 // Most outputs per top block among the compiled gathers (f16s exponents in LDS).
@@ -44,13 +46,14 @@ constexpr int kMaxGatherOutputs = max_gather_outputs();
 
 template <int PREC>
 constexpr bool gather_in(const CombVariant& v) {
-  return v.out == OUT_SAME || (PREC == RBC_PREC_F16S && v.out == OUT_F16S);
+  return v.out == OUT_SAME || (PREC == RBC_PREC_F16S && v.out == OUT_F16S) ||
+         (PREC == RBC_PREC_FP8C && v.out == OUT_FP8X2);
 }
 
 template <int OUTF, int V, int NL, int BR, int BC, int R>
 __device__ __forceinline__ void gather_task(const GatherParams& p, int64_t first, int count, int64_t in,
                                             int32_t* exps) {
-  if constexpr (OUTF == OUT_F16S) comb::load_exponents<NL, R>(p, in, exps);
+  if constexpr (OUTF == OUT_F16S || OUTF == OUT_FP8X2) comb::load_exponents<NL, R>(p, in, exps);
   for (int c = 0; c < count; ++c) comb::gather_block<float, OUTF, V, NL, BR, BC, R>(p, first + c, in, exps);
 }
 
@@ -67,6 +70,10 @@ __device__ __forceinline__ void leaf_task(const LeafDesc& d, int64_t first, int 
       tiles::gemm_f32_tile<TILE, TILE, BK>(static_cast<const float*>(d.S), static_cast<const float*>(d.T),
                                            d.P, d.m, d.n, d.k, d.tiles_n, d.tiles_per_leaf, first + c,
                                            static_cast<float*>(smem));
+    else if constexpr (PREC == RBC_PREC_FP8C)
+      tiles::gemm_fp8c_tile<TILE, TILE>(static_cast<const uint8_t*>(d.S), static_cast<const uint8_t*>(d.T), d.P,
+                                        d.m, d.n, d.k, d.plane_s, d.plane_t, d.eS, d.eT, d.tiles_n,
+                                        d.tiles_per_leaf, first + c, static_cast<uint8_t*>(smem));
     else
       tiles::gemm_lowp_tile<tiles::LOWP_F16S, TILE, TILE>(
           static_cast<const uint16_t*>(d.S), static_cast<const uint16_t*>(d.T), d.P, d.m, d.n, d.k,
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
         const float mx = __uint_as_float(__hip_atomic_load(d.maxbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         const gbl<const float>* G = global_ptr(d.G);
         gbl<int32_t>* e = global_ptr(d.e);
-        for (int64_t l = threadIdx.x; l < d.n_leaves; l += 256) e[l] = scale::leaf_exponent(mx, G[l]);
+        for (int64_t l = threadIdx.x; l < d.n_leaves; l += 256) e[l] = scale::leaf_exponent(mx, G[l], d.target);
         break;
       }
       case TK_GATHER:
@@ -224,6 +231,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
       default:
         break;
     }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     leader_signal(ctl, t, task.signal, task.count, trace);
   }

@@ -79,6 +79,26 @@ __device__ __forceinline__ void vstore(gbl<T>* p, VecT<T, V> v) {
 #endif
 }
 
+// Round to the nearest OCP e4m3 value (ties to even) and encode: bias 7,
+// 3 fraction bits, subnormal spacing 2^-9, largest finite 448.  The caller
+// keeps |f| <= 448; larger magnitudes saturate to 448.
+__device__ __forceinline__ uint32_t e4m3_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const float a = fminf(fabsf(f), 448.0f);
+  uint32_t code;
+  if (a < 0.015625f) {  // below 2^-6: subnormal grid of 2^-9 (rintf: ties to even)
+    code = (uint32_t)rintf(a * 512.0f);  // 0 .. 8 (8 is the smallest normal, 2^-6)
+  } else {
+    const uint32_t b = __float_as_uint(a);
+    // keep 3 fraction bits: round the f32 mantissa at bit 20, ties to even
+    const uint32_t r = b + 0x7FFFFu + ((b >> 20) & 1u);
+    const uint32_t e = (r >> 23) - 127 + 7;  // rebias (carry may raise the exponent)
+    code = (e << 3) | ((r >> 20) & 7u);
+  }
+  return sign | code;
+}
+
 template <typename T, int OUTF, int V>
 struct GatherEmit {
   void* dst;
@@ -89,6 +109,31 @@ struct GatherEmit {
     if constexpr (OUTF == OUT_SAME) {
       // streaming store: the leaf operands are read once, by the next kernel
       vstore<T, V>(global_ptr(static_cast<T*>(dst)) + idx * dst_batch + off, v);
+    } else if constexpr (OUTF == OUT_FP8X2) {
+      // scaled split: y = 2^e v, hi = rn_e4m3(y), lo = rn_e4m3(16 (y - hi)) (y - hi is exact)
+      const int ex = exps[idx - exp_base];
+      uint32_t hi = 0, lo = 0;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const float y = ldexpf((float)v[e], ex);
+        const uint32_t h = e4m3_rne(y);
+        const float hv = ldexpf((float)(h & 7u) + ((h & 0x78u) ? 8.f : 0.f),
+                                (h & 0x78u) ? (int)((h >> 3) & 15u) - 10 : -9);
+        const float hs = (h & 0x80u) ? -hv : hv;
+        hi |= h << (8 * e);
+        lo |= e4m3_rne(16.0f * (y - hs)) << (8 * e);
+      }
+      gbl<uint8_t>* d = global_ptr(static_cast<uint8_t*>(dst)) + idx * dst_batch + off;
+      if constexpr (V == 4) {
+        *reinterpret_cast<gbl<uint32_t>*>(d) = hi;
+        *reinterpret_cast<gbl<uint32_t>*>(d + plane) = lo;
+      } else if constexpr (V == 2) {
+        *reinterpret_cast<gbl<uint16_t>*>(d) = (uint16_t)hi;
+        *reinterpret_cast<gbl<uint16_t>*>(d + plane) = (uint16_t)lo;
+      } else {
+        d[0] = (uint8_t)hi;
+        d[plane] = (uint8_t)lo;
+      }
     } else if constexpr (OUTF == OUT_F16S) {
       // scaled leaf operand: rn_f16(2^e v), e chosen per leaf so nothing overflows
       const int ex = exps[idx - exp_base];
@@ -215,7 +260,7 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, 
 
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
 __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
-  if constexpr (OUTF == OUT_F16S) {
+  if constexpr (OUTF == OUT_F16S || OUTF == OUT_FP8X2) {
     __shared__ int32_t exps[group_outputs<NL, R>()];
     for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
       if (in != blockIdx.y) __syncthreads();  // the previous block's readers are done
@@ -392,7 +437,7 @@ hipError_t scatter_dispatch(int vec, int nl, int br, int bc, int R, const Scatte
 }
 
 #define RBC_GATHER_COMBOS(X) \
-  X(double, OUT_SAME) X(float, OUT_SAME) X(float, OUT_BF16X2) X(float, OUT_F16S)
+  X(double, OUT_SAME) X(float, OUT_SAME) X(float, OUT_BF16X2) X(float, OUT_F16S) X(float, OUT_FP8X2)
 #define RBC_SCATTER_COMBOS(X)                                                          \
   X(double, double, double) X(float, float, float) X(float, double, double)            \
   X(float, double, float) X(double, double, float)

@@ -1,0 +1,8 @@
+// Instantiation of the fused gather for element type float, output OUT_FP8X2.
+#include "combine.hpp"
+
+namespace rbc {
+namespace comb {
+template hipError_t gather_dispatch<float, OUT_FP8X2>(int, int, int, int, int, const GatherParams&, hipStream_t);
+}  // namespace comb
+}  // namespace rbc

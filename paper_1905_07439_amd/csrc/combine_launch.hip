@@ -17,6 +17,8 @@ hipError_t launch_gather(Elt elt, GatherOut out, int vec, int nl, int br, int bc
     return comb::gather_dispatch<float, OUT_BF16X2>(vec, nl, br, bc, R, p, s);
   if (elt == ELT_F32 && out == OUT_F16S)
     return comb::gather_dispatch<float, OUT_F16S>(vec, nl, br, bc, R, p, s);
+  if (elt == ELT_F32 && out == OUT_FP8X2)
+    return comb::gather_dispatch<float, OUT_FP8X2>(vec, nl, br, bc, R, p, s);
   return hipErrorInvalidValue;
 }
 

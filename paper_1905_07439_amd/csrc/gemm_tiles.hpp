@@ -324,5 +324,157 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
       }
 }
 
+// ---- fp8 (OCP e4m3) leaves with one correction pass ------------------------
+//
+// S and T hold a hi plane and a lo plane of bytes (lo scaled by 16).  Per
+// output: acc = sum hi_S hi_T and cor = sum (hi_S lo_T + lo_S hi_T), both f32,
+// on v_mfma_f32_16x16x32_fp8_fp8; P = 2^-(eS + eT) (acc + cor / 16).  K
+// advances in slabs of 64 bytes; S slabs keep their k-contiguous rows in LDS,
+// T slabs are transposed on the way in (8 k rows x 16 columns per group, each
+// column's 8 k bytes one 8-byte LDS store), so every MFMA operand is one
+// 8-byte LDS read.
+template <int BM, int BN>
+struct Fp8Tile {
+  static constexpr int BK = 64, LDK = BK + 8;
+  static constexpr int SMEM_BYTES = 2 * 2 * (BM + BN) * LDK;  // two buffers, two planes
+};
+
+__device__ __forceinline__ floatx4 mfma_fp8(u32x2 a, u32x2 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c,
+                                                     0, 0, 0);
+}
+
+template <int BM, int BN>
+__device__ __forceinline__ void gemm_fp8c_tile(const uint8_t* __restrict__ S, const uint8_t* __restrict__ T,
+                                               float* __restrict__ P, int m, int n, int k, int64_t plane_s,
+                                               int64_t plane_t, const int32_t* __restrict__ eS,
+                                               const int32_t* __restrict__ eT, int tiles_n, int tiles_per_leaf,
+                                               int64_t bid, uint8_t* smem) {
+  constexpr int BK = Fp8Tile<BM, BN>::BK, LDK = Fp8Tile<BM, BN>::LDK;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  constexpr int A_TOTAL = 2 * BM * (BK / 16);        // 16-byte chunks of an S slab (both planes)
+  constexpr int A_ITER = (A_TOTAL + 255) / 256;
+  constexpr int B_TOTAL = 2 * (BK / 8) * (BN / 16);  // 8k x 16n groups of a T slab (both planes)
+  constexpr int B_ITER = (B_TOTAL + 255) / 256;
+  uint8_t(*As)[2][BM][LDK] = reinterpret_cast<uint8_t(*)[2][BM][LDK]>(smem);  // [buf][plane][row][k]
+  uint8_t(*Bs)[2][BN][LDK] = reinterpret_cast<uint8_t(*)[2][BN][LDK]>(smem + 2 * 2 * BM * LDK);
+  const int64_t leaf = bid / tiles_per_leaf;
+  const int t = (int)(bid - leaf * tiles_per_leaf);
+  const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
+  const gbl<const uint8_t>* Sl = global_ptr(S) + leaf * (int64_t)m * k + (int64_t)tm * BM * k;
+  const gbl<const uint8_t>* Tl = global_ptr(T) + leaf * (int64_t)k * n + (int64_t)tn * BN;
+  gbl<float>* Pl = global_ptr(P) + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // Per-thread slab sources (threads past a total mirror a valid chunk and do not store).
+  const gbl<const uint8_t>* a_src[A_ITER];
+#pragma unroll
+  for (int i = 0; i < A_ITER; ++i) {
+    const int idx = (tid + 256 * i) % A_TOTAL;
+    const int pl = idx / (BM * (BK / 16)), rem = idx % (BM * (BK / 16));
+    a_src[i] = Sl + pl * plane_s + (int64_t)(rem / (BK / 16)) * k + (rem % (BK / 16)) * 16;
+  }
+  const gbl<const uint8_t>* b_src[B_ITER];
+#pragma unroll
+  for (int i = 0; i < B_ITER; ++i) {
+    const int idx = (tid + 256 * i) % B_TOTAL;
+    const int pl = idx / ((BK / 8) * (BN / 16)), rem = idx % ((BK / 8) * (BN / 16));
+    b_src[i] = Tl + pl * plane_t + (int64_t)((rem / (BN / 16)) * 8) * n + (rem % (BN / 16)) * 16;
+  }
+
+  u32x4 ra[A_ITER];
+  u32x4 rb[B_ITER][8];
+#pragma unroll
+  for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i]);
+#pragma unroll
+  for (int i = 0; i < B_ITER; ++i)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)r * n);
+
+  floatx4 acc[FM][FN], cor[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = cor[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = k / BK;
+  const int lr = lane & 15, lg = lane >> 4;
+  int cur = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int i = 0; i < A_ITER; ++i) {
+      const int idx = tid + 256 * i;
+      if (A_TOTAL % 256 && idx >= A_TOTAL) break;
+      const int pl = idx / (BM * (BK / 16)), rem = idx % (BM * (BK / 16));
+      *reinterpret_cast<u32x4*>(&As[cur][pl][rem / (BK / 16)][(rem % (BK / 16)) * 16]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_ITER; ++i) {
+      const int idx = tid + 256 * i;
+      if (B_TOTAL % 256 && idx >= B_TOTAL) break;
+      const int pl = idx / ((BK / 8) * (BN / 16)), rem = idx % ((BK / 8) * (BN / 16));
+      const int kg = rem / (BN / 16), cg = rem % (BN / 16);
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        // byte c of each of the 8 k rows: byte c % 4 of 32-bit word c / 4
+        const int w = c >> 2, sh = (c & 3) * 8;
+        u32x2 v;
+        v[0] = ((rb[i][0][w] >> sh) & 0xFFu) | (((rb[i][1][w] >> sh) & 0xFFu) << 8) |
+               (((rb[i][2][w] >> sh) & 0xFFu) << 16) | (((rb[i][3][w] >> sh) & 0xFFu) << 24);
+        v[1] = ((rb[i][4][w] >> sh) & 0xFFu) | (((rb[i][5][w] >> sh) & 0xFFu) << 8) |
+               (((rb[i][6][w] >> sh) & 0xFFu) << 16) | (((rb[i][7][w] >> sh) & 0xFFu) << 24);
+        *reinterpret_cast<u32x2*>(&Bs[cur][pl][cg * 16 + c][kg * 8]) = v;
+      }
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      const int k1 = (kt + 1) * BK;
+#pragma unroll
+      for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i] + k1);
+#pragma unroll
+      for (int i = 0; i < B_ITER; ++i)
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)(k1 + r) * n);
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK / 32; ++kk) {
+      u32x2 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        ah[i] = *reinterpret_cast<const u32x2*>(&As[cur][0][wm * WM + i * 16 + lr][kk * 32 + lg * 8]);
+        al[i] = *reinterpret_cast<const u32x2*>(&As[cur][1][wm * WM + i * 16 + lr][kk * 32 + lg * 8]);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        bh[j] = *reinterpret_cast<const u32x2*>(&Bs[cur][0][wn * WN + j * 16 + lr][kk * 32 + lg * 8]);
+        bl[j] = *reinterpret_cast<const u32x2*>(&Bs[cur][1][wn * WN + j * 16 + lr][kk * 32 + lg * 8]);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = mfma_fp8(ah[i], bh[j], acc[i][j]);
+          cor[i][j] = mfma_fp8(ah[i], bl[j], cor[i][j]);
+          cor[i][j] = mfma_fp8(al[i], bh[j], cor[i][j]);
+        }
+    }
+    cur ^= 1;
+  }
+
+  const int unscale = -(global_ptr(eS)[leaf] + global_ptr(eT)[leaf]);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wm * WM + i * 16 + lg * 4 + v, col = wn * WN + j * 16 + lr;
+        Pl[(int64_t)row * n + col] = ldexpf(acc[i][j][v] + cor[i][j][v] * 0.0625f, unscale);
+      }
+}
+
 }  // namespace tiles
 }  // namespace rbc

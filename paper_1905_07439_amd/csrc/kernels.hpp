@@ -12,7 +12,7 @@ namespace rbc {
 constexpr int kMaxGroupLevels = 3;
 
 // Output formats of a gather.
-enum GatherOut { OUT_SAME = 0, OUT_BF16X2 = 1, OUT_F16S = 2 };
+enum GatherOut { OUT_SAME = 0, OUT_BF16X2 = 1, OUT_F16S = 2, OUT_FP8X2 = 3 };
 
 // Gather of one group: every top block (n_in of them) becomes Rg bottom blocks,
 // S = sum over (k, l) of the folded coefficient times block (k, l), level by
@@ -25,8 +25,8 @@ struct GatherParams {
   void* dst;
   int64_t rows_bot, cols_bot;  // bottom block size
   int64_t dst_batch;   // elements between consecutive bottom blocks
-  int64_t plane;       // bf16x2 output: elements between the hi and lo planes
-  const int32_t* scale_exp;  // f16s output: power-of-two exponent per bottom block
+  int64_t plane;       // bf16x2 / fp8x2 output: elements between the hi and lo planes
+  const int32_t* scale_exp;  // f16s / fp8 output: power-of-two exponent per bottom block
   int64_t n_in;
   SideLevel lev[kMaxGroupLevels];
 };
@@ -68,8 +68,12 @@ hipError_t launch_gemm_bf16x3(const uint16_t* S, const uint16_t* T, float* P, in
 hipError_t launch_gemm_f16s(const uint16_t* S, const uint16_t* T, float* P, int64_t m, int64_t n,
                             int64_t k, int64_t batch, int tile, const int32_t* eS, const int32_t* eT,
                             hipStream_t stream);
-// max |X| into *maxbits, then e[l] = floor(log2(2^15 / (G[l] max|X|))) for every leaf.
+// fp8c: S and T hold e4m3 hi planes followed (plane bytes later) by lo planes,
+// scaled by 2^eS[l], 2^eT[l]; P = 2^-(eS+eT) (hi hi + (hi lo + lo hi) / 16).
+hipError_t launch_gemm_fp8c(const uint8_t* S, const uint8_t* T, float* P, int64_t m, int64_t n, int64_t k,
+                            int64_t batch, int tile, const int32_t* eS, const int32_t* eT, hipStream_t stream);
+// max |X| into *maxbits, then e[l] = floor(log2(target / (G[l] max|X|))) for every leaf.
 hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, uint32_t* maxbits,
-                              const float* G, int32_t* e, int64_t n_leaves, hipStream_t s);
+                              const float* G, int32_t* e, int64_t n_leaves, float target, hipStream_t s);
 
 }  // namespace rbc

@@ -160,9 +160,9 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
                   std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out) {
   scale.clear(), out.clear();
   const bool f64 = p.prec == RBC_PREC_F64;
-  const bool f16s = p.prec == RBC_PREC_F16S;
+  const bool scaled = p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C;
   int32_t* exps = nullptr;
-  if (f16s) {
+  if (scaled) {
     ScaleLaunch sl;
     sl.X = static_cast<const float*>(X), sl.ld = ldx;
     sl.rows = which == 0 ? p.M : p.K, sl.cols = which == 0 ? p.K : p.N;
@@ -170,6 +170,7 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     exps = reinterpret_cast<int32_t*>(ws + p.off_aux + 256) + (size_t)which * p.n_leaves;
     sl.G = reinterpret_cast<const float*>(static_cast<const char*>(p.dev_tables) + p.g_off[which]);
     sl.e = exps, sl.n_leaves = p.n_leaves;
+    sl.target = p.prec == RBC_PREC_FP8C ? 448.0f : 32768.0f;
     scale.push_back(sl);
   }
   for (size_t gi = 0; gi < p.groups.size(); ++gi) {
@@ -196,9 +197,10 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     gp.dst_batch = gp.rows_bot * gp.cols_bot;
     gp.n_in = g.n_in;
     const bool bf16_out = last && p.prec == RBC_PREC_BF16X3;
-    const bool f16_out = last && f16s;
-    gp.plane = bf16_out ? (int64_t)p.n_leaves * gp.rows_bot * gp.cols_bot : 0;
-    gp.scale_exp = f16_out ? exps : nullptr;
+    const bool f16_out = last && p.prec == RBC_PREC_F16S;
+    const bool fp8_out = last && p.prec == RBC_PREC_FP8C;
+    gp.plane = (bf16_out || fp8_out) ? (int64_t)p.n_leaves * gp.rows_bot * gp.cols_bot : 0;
+    gp.scale_exp = (f16_out || fp8_out) ? exps : nullptr;
     for (int d = g.d0; d < g.d1; ++d)
       fill_side(p, dr, d, which == 0 ? SIDE_A : SIDE_B, f64, false, gp.lev[d - g.d0]);
     L.br = which == 0 ? g.b1 : g.b2, L.bc = which == 0 ? g.b2 : g.b3;
@@ -207,7 +209,7 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     L.vec = pick_vec(f64 ? 8 : 4, gp.cols_bot, {gp.ld_src, gp.src_batch, gp.dst_batch, gp.plane},
                      {gp.src, gp.dst}, f64, L.nl);
     L.elt = f64 ? ELT_F64 : ELT_F32;
-    L.out = bf16_out ? OUT_BF16X2 : (f16_out ? OUT_F16S : OUT_SAME);
+    L.out = bf16_out ? OUT_BF16X2 : (f16_out ? OUT_F16S : (fp8_out ? OUT_FP8X2 : OUT_SAME));
     out.push_back(L);
   }
 }
@@ -218,7 +220,7 @@ LeafLaunch build_leaf(const Plan& p, char* ws) {
   L.S = ws + p.off_S, L.T = ws + p.off_T, L.P = ws + p.off_P;
   L.m = p.mM, L.n = p.mN, L.k = p.mK, L.batch = p.n_leaves, L.tile = p.tile_m;
   L.eS = L.eT = nullptr;
-  if (p.prec == RBC_PREC_F16S) {
+  if (p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C) {
     L.eS = reinterpret_cast<const int32_t*>(ws + p.off_aux + 256);
     L.eT = L.eS + p.n_leaves;
   }
@@ -249,7 +251,8 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
     sp.n_out = g.n_in;
     for (int d = g.d0; d < g.d1; ++d) fill_side(p, dr, d, SIDE_C, f64_tabs, kappa_scale, sp.lev[d - g.d0]);
     if (p.prec == RBC_PREC_F64) L.tp = L.ta = L.to = ELT_F64;
-    else if (p.prec == RBC_PREC_F32 || p.prec == RBC_PREC_F16S) L.tp = L.ta = L.to = ELT_F32;
+    else if (p.prec == RBC_PREC_F32 || p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C)
+      L.tp = L.ta = L.to = ELT_F32;
     else L.tp = last ? ELT_F32 : ELT_F64, L.ta = ELT_F64, L.to = gi == 0 ? ELT_F32 : ELT_F64;
     L.R = p.Q ? p.levels[g.d0].R : 1;
     L.nl = g.d1 - g.d0;
@@ -261,7 +264,7 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
 }
 
 hipError_t launch(const ScaleLaunch& l, hipStream_t s) {
-  return launch_leaf_scales(l.X, l.ld, l.rows, l.cols, l.maxbits, l.G, l.e, l.n_leaves, s);
+  return launch_leaf_scales(l.X, l.ld, l.rows, l.cols, l.maxbits, l.G, l.e, l.n_leaves, l.target, s);
 }
 
 hipError_t launch(const GatherLaunch& l, hipStream_t s) {
@@ -278,6 +281,9 @@ hipError_t launch(const LeafLaunch& l, hipStream_t s) {
                              static_cast<float*>(l.P), l.m, l.n, l.k, l.batch, l.tile, s);
     case RBC_PREC_F16S:
       return launch_gemm_f16s(static_cast<const uint16_t*>(l.S), static_cast<const uint16_t*>(l.T),
+                              static_cast<float*>(l.P), l.m, l.n, l.k, l.batch, l.tile, l.eS, l.eT, s);
+    case RBC_PREC_FP8C:
+      return launch_gemm_fp8c(static_cast<const uint8_t*>(l.S), static_cast<const uint8_t*>(l.T),
                               static_cast<float*>(l.P), l.m, l.n, l.k, l.batch, l.tile, l.eS, l.eT, s);
     case RBC_PREC_BF16X3:
       return launch_gemm_bf16x3(static_cast<const uint16_t*>(l.S), static_cast<const uint16_t*>(l.T),

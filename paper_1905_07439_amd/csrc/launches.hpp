@@ -23,13 +23,14 @@ rbc_status check_ws(const Plan& p, void* ws, size_t bytes);
 // Upload the coefficient tables of every level on first use on a device.
 rbc_status ensure_device(Plan& p);
 
-struct ScaleLaunch {  // f16s: max|X| and the per-leaf exponents of one operand
+struct ScaleLaunch {  // f16s, fp8c: max|X| and the per-leaf exponents of one operand
   const float* X;
   int64_t ld, rows, cols;
   uint32_t* maxbits;
   const float* G;
   int32_t* e;
   int64_t n_leaves;
+  float target;  // bound of the scaled operand: 2^15 (f16), 448 (e4m3)
 };
 
 struct GatherLaunch {
@@ -56,7 +57,7 @@ struct ScatterLaunch {
   int vec, nl, br, bc, R;
 };
 
-// which = 0: A (M x K), 1: B (K x N).  `scale` is filled for f16s plans.
+// which = 0: A (M x K), 1: B (K x N).  `scale` is filled for f16s and fp8c plans.
 void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int64_t ldx, char* ws,
                   std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out);
 LeafLaunch build_leaf(const Plan& p, char* ws);

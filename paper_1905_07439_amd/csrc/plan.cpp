@@ -50,7 +50,8 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   if (M < 1 || K < 1 || N < 1) return fail(RBC_EINVAL, "empty product %lldx%lldx%lld", (long long)M,
                                           (long long)K, (long long)N);
   if ((int)levels.size() > kMaxLevels) return fail(RBC_EINVAL, "at most %d levels", kMaxLevels);
-  if (prec != RBC_PREC_F64 && prec != RBC_PREC_F32 && prec != RBC_PREC_BF16X3 && prec != RBC_PREC_F16S)
+  if (prec != RBC_PREC_F64 && prec != RBC_PREC_F32 && prec != RBC_PREC_BF16X3 && prec != RBC_PREC_F16S &&
+      prec != RBC_PREC_FP8C)
     return fail(RBC_EUNSUPPORTED, "precision %d not implemented", (int)prec);
   Plan p;
   p.M = M, p.K = K, p.N = N;
@@ -71,7 +72,7 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     if (leaf_tile == 0) leaf_tile = 16;
     if (leaf_tile != 16) return fail(RBC_EUNSUPPORTED, "f64 leaf tile must be 16");
     p.tile_m = p.tile_n = 16, p.tile_k = 4;
-  } else if (prec == RBC_PREC_F16S) {
+  } else if (prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) {
     if (leaf_tile == 0) {
       // the tile with the least padded leaf area (ties: the larger tile)
       int64_t best = -1;
@@ -81,9 +82,9 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
       }
     }
     if (leaf_tile != 32 && leaf_tile != 64 && leaf_tile != 96 && leaf_tile != 128)
-      return fail(RBC_EUNSUPPORTED, "f16s leaf tile must be 32, 64, 96 or 128");
+      return fail(RBC_EUNSUPPORTED, "f16s / fp8c leaf tile must be 32, 64, 96 or 128");
     p.tile_m = p.tile_n = leaf_tile;
-    p.tile_k = 32;
+    p.tile_k = prec == RBC_PREC_FP8C ? 64 : 32;
   } else {
     if (leaf_tile == 0) {
       // 128 unless it pads the leaf by more than 1/8
@@ -103,7 +104,8 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   p.comb_bytes = prec == RBC_PREC_F64 ? 8 : 4;
   p.recomb_bytes = (prec == RBC_PREC_F64 || prec == RBC_PREC_BF16X3) ? 8 : 4;
   // bf16x3: hi + lo planes of 2 bytes; f16s: one plane of 2 bytes
-  const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : (prec == RBC_PREC_F16S ? 2 : 4);
+  // fp8c: hi + lo planes of 1 byte
+  const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : ((prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) ? 2 : 4);
   const int prod_bytes = prec == RBC_PREC_F64 ? 8 : 4;
 
   // Fused groups, formed from the deepest level upwards so that the
@@ -169,7 +171,7 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     g.off_b_bot = off, off = align256(off + nb * g.b_rows_bot * g.b_cols_bot * p.comb_bytes);
     g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * p.recomb_bytes);
   }
-  if (prec == RBC_PREC_F16S) {
+  if (prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) {
     p.off_aux = off;
     p.bytes_aux = 256 + 2 * (size_t)p.n_leaves * 4;
     off = align256(off + p.bytes_aux);

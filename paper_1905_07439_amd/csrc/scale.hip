@@ -1,5 +1,5 @@
-// Per-leaf power-of-two scales of the f16 leaf operands (the bound is
-// explained in scale.hpp): max|X|, then one exponent per leaf.
+// Per-leaf power-of-two scales of the reduced-precision leaf operands (the
+// bound is explained in scale.hpp): max|X|, then one exponent per leaf.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -22,16 +22,16 @@ __global__ __launch_bounds__(256) void k_maxabs(const float* __restrict__ X, int
 }
 
 __global__ void k_leaf_scales(const uint32_t* maxbits, const float* __restrict__ G, int32_t* e,
-                              int64_t n) {
+                              int64_t n, float target) {
   const float mx = __uint_as_float(*maxbits);
   for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x)
-    e[l] = scale::leaf_exponent(mx, G[l]);
+    e[l] = scale::leaf_exponent(mx, G[l], target);
 }
 
 }  // namespace
 
 hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, uint32_t* maxbits,
-                              const float* G, int32_t* e, int64_t n_leaves, hipStream_t s) {
+                              const float* G, int32_t* e, int64_t n_leaves, float target, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, maxbits, (int64_t)1, 0u);
   int64_t blocks = rows < 4096 ? rows : 4096;
   if (blocks < 1) blocks = 1;
@@ -39,7 +39,7 @@ hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t 
   int64_t lb = (n_leaves + 255) / 256;
   if (lb > 1024) lb = 1024;
   hipLaunchKernelGGL(k_leaf_scales, dim3((unsigned)(lb < 1 ? 1 : lb)), dim3(256), 0, s, maxbits, G, e,
-                     n_leaves);
+                     n_leaves, target);
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
-// Device parts of the per-leaf power-of-two scales of f16 leaf operands,
-// shared by the stand-alone kernels and the batch engine.
+// Device parts of the per-leaf power-of-two scales of reduced-precision leaf
+// operands (f16, e4m3), shared by the stand-alone kernels and the batch engine.
 //
 // A leaf operand S_l is a chain of folded combinations of blocks of A, so
 // |S_l| <= G_l max|A| with G_l the product over levels of the 1-norm of the
@@ -7,6 +7,7 @@
 // norm unchanged).  The gather writes rn_f16(2^e_l S_l) with
 // e_l = floor(log2(2^15 / (G_l max|A|))): no value can exceed 2^15 < 65504,
 // and the leaf kernel multiplies its f32 result by 2^-(eS_l + eT_l), exactly.
+// e4m3 operands use the bound 448 (the largest finite e4m3) in place of 2^15.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -37,12 +38,14 @@ __device__ __forceinline__ void maxabs_fold(float m, uint32_t* out) {
   if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
-__device__ __forceinline__ int32_t leaf_exponent(float mx, float G) {
+// e = floor(log2(target / (G mx))), clamped to [-120, 120]; 0 when the bound is 0.
+// target: 2^15 for f16 operands, 448 for e4m3.
+__device__ __forceinline__ int32_t leaf_exponent(float mx, float G, float target) {
   const float bound = G * mx;
   int ex = 0;
   if (bound > 0.f && isfinite(bound)) {
     int x;
-    frexpf(32768.0f / bound, &x);  // 32768 / bound = m 2^x, m in [0.5, 1)
+    frexpf(target / bound, &x);  // target / bound = m 2^x, m in [0.5, 1)
     ex = x - 1;
     ex = ex < -120 ? -120 : (ex > 120 ? 120 : ex);
   }

@@ -34,10 +34,17 @@ def _say(*a):
 _PLANS = {}
 
 
+def _scheme(name):
+    if name.startswith("pert:"):  # perturbed Strassen, pert:<sigma>:<seed>
+        _, sigma, seed = name.split(":")
+        return rbc.Scheme.perturbed(rbc.Scheme.builtin("strassen"), float(sigma), int(seed))
+    return rbc.Scheme.builtin(name)
+
+
 def _plan(n, names, prec):
     key = (n, tuple(names), prec)
     if key not in _PLANS:
-        _PLANS[key] = rbc.Plan(n, n, n, [rbc.Scheme.builtin(s) for s in names], prec)
+        _PLANS[key] = rbc.Plan(n, n, n, [_scheme(s) for s in names], prec)
     return _PLANS[key]
 
 
@@ -57,6 +64,9 @@ F32_SPECS = [(("strassen", "strassen"), 256), (("laderman",), 192), (("laderman"
 F16S_SPECS = [(("laderman",), 192), (("laderman",), 288), (("laderman", "strassen"), 480),
               (("laderman", "strassen", "strassen"), 768), (("laderman", "strassen", "strassen"), 864),
               (("laderman", "strassen", "strassen", "strassen"), 1536)]
+FP8C_SPECS = [(("strassen",), 128), (("laderman",), 192), (("pert:0.001:42", "pert:0.001:42"), 512),
+              (("laderman", "strassen"), 480), (("strassen", "strassen", "strassen"), 1024),
+              (("strassen", "strassen"), 320)]
 MODES = ["full", "signs", "perms", "none"]
 
 
@@ -82,7 +92,7 @@ def _alone(items):
     return out
 
 
-@pytest.mark.parametrize("prec,specs", [("f32", F32_SPECS), ("f16s", F16S_SPECS)])
+@pytest.mark.parametrize("prec,specs", [("f32", F32_SPECS), ("f16s", F16S_SPECS), ("fp8c", FP8C_SPECS)])
 def test_batch_equals_alone_bitwise(prec, specs):
     b, items = _build(prec, specs, "gauss")
     _say("batch", prec, b.info())

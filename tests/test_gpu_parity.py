@@ -364,6 +364,68 @@ def test_f16s_scaled_leaves(case):
     assert e <= 1.1 * e_emu + 1e-6 and e < 2e-2
 
 
+FP8C_CASES = [(["strassen", "strassen"], 256, 256, 256, 0), (["laderman"], 192, 192, 192, 0),
+              (["laderman", "strassen"], 480, 480, 480, 0), (["strassen"], 200, 190, 180, 96),
+              (["pert:0.001:42", "pert:0.001:42"], 512, 512, 512, 0), (["strassen"] * 3, 1024, 1024, 1024, 128)]
+
+
+@pytest.mark.parametrize("case", range(len(FP8C_CASES)))
+def test_fp8c_split_leaves(case):
+    # fp8 leaves: exponents and both e4m3 planes are bit-identical to the oracle's scaled
+    # split; the product is within the emulation's error (the device accumulates in f32).
+    names, M, K, N, tile = FP8C_CASES[case]
+    _say("fp8c", names, M, K, N)
+    lib_s, ref_s = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec="fp8c", leaf_tile=tile)
+    info = plan.info
+    A = workloads.scaled_gaussian((M, K), 4200 + case).astype(np.float32)
+    B = workloads.scaled_gaussian((K, N), 4300 + case).astype(np.float32)
+    s, p, dr = _level_draws(plan, ref_s, 11, "full")
+    ws = torch.zeros(info["workspace_bytes"], dtype=torch.uint8, device=DEV)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    plan.stage_gather(0, Ad, s, p, ws)
+    plan.stage_gather(1, Bd, s, p, ws)
+    torch.cuda.synchronize()
+    L, mM, mK, mN = info["n_leaves"], info["mM"], info["mK"], info["mN"]
+    Sg = _region(ws, info["off_S"], info["bytes_S"], torch.uint8, (2, L, mM, mK))
+    Tg = _region(ws, info["off_T"], info["bytes_T"], torch.uint8, (2, L, mK, mN))
+    ex = _region(ws, info["off_aux"] + 256, 2 * L * 4, torch.int32, (2, L))
+    dims = (mM, mK, mN)
+    ops = recursion.leaf_operands(A, B, ref_s, dr, arith="f32", leaf_dims=dims)
+    gA, gB = precision.path_norms(ref_s, "A"), precision.path_norms(ref_s, "B")
+    mA, mB = float(np.max(np.abs(A))), float(np.max(np.abs(B)))
+    prods = []
+    for l, (S, T) in enumerate(ops):
+        eA = precision.leaf_exponent(mA, gA[l], target=448.0)
+        eB = precision.leaf_exponent(mB, gB[l], target=448.0)
+        assert (ex[0, l], ex[1, l]) == (eA, eB), l
+        sh, sl = precision.split_e4m3_scaled(np.ldexp(S.astype(np.float64), eA))
+        th, tl = precision.split_e4m3_scaled(np.ldexp(T.astype(np.float64), eB))
+        np.testing.assert_array_equal(precision.decode_e4m3(Sg[0, l]), sh)
+        np.testing.assert_array_equal(precision.decode_e4m3(Sg[1, l]), sl)
+        np.testing.assert_array_equal(precision.decode_e4m3(Tg[0, l]), th)
+        np.testing.assert_array_equal(precision.decode_e4m3(Tg[1, l]), tl)
+        prods.append(np.ldexp(sh @ th + (sh @ tl + sl @ th) / 16.0, -(eA + eB)).astype(np.float32))
+    plan.stage_leaf(ws)
+    Pg = _region(ws, info["off_P"], info["bytes_P"], torch.float32, (L, mM, mN))
+    for l in range(0, L, max(1, L // 7)):
+        # The fp8 MFMA's internal accumulation is not the sequential f32 sum (its errors reach
+        # about 2^-18 of the sum of |terms| at K = 64); a wrong lane layout or byte order would
+        # give errors of the order of the values themselves.
+        eA, eB = ex[0, l], ex[1, l]
+        sh, sl = precision.split_e4m3_scaled(np.ldexp(ops[l][0].astype(np.float64), eA))
+        th, tl = precision.split_e4m3_scaled(np.ldexp(ops[l][1].astype(np.float64), eB))
+        bound = np.ldexp(np.abs(sh) @ np.abs(th) + (np.abs(sh) @ np.abs(tl) + np.abs(sl) @ np.abs(th)) / 16.0,
+                         -(eA + eB)) * (mK + 2) * 2.0 ** -20
+        assert (np.abs(Pg[l] - prods[l]) <= bound + 1e-30).all(), l
+    emu = recursion.combine(prods, M, N, K, ref_s, dr, arith="f32", leaf_dims=dims)
+    C = plan.matmul(Ad, Bd, seed=11).cpu().numpy()
+    AB = A.astype(np.float64) @ B.astype(np.float64)
+    e, e_emu = recursion.rel_err(C, AB), recursion.rel_err(emu, AB)
+    _say("fp8c rel err %.3g, emulation %.3g" % (e, e_emu))
+    assert e <= 1.1 * e_emu + 1e-6 and e < 5e-2
+
+
 def test_results_are_deterministic_and_stream_ordered():
     _say("determinism")
     lib_s, _ = _schemes(["strassen"] * 3)

@@ -158,6 +158,19 @@ def test_f16s_plan_geometry():
     assert q.info["tile_m"] == 128 and q.info["mM"] == 128
 
 
+def test_fp8c_plan_geometry():
+    S = rbc.Scheme.builtin("strassen")
+    p = rbc.Plan(300, 260, 200, [S, S], prec="fp8c")
+    i = p.info
+    # leaves 75 x 65 x 50: M, N to the tile with the least padded area (32), K to the
+    # 64-byte slab; two one-byte planes per operand element
+    assert (i["mM"], i["mK"], i["mN"], i["tile_m"], i["tile_k"]) == (96, 128, 64, 32, 64)
+    assert i["bytes_S"] == 49 * 96 * 128 * 2 and i["bytes_T"] == 49 * 128 * 64 * 2
+    assert i["bytes_aux"] == 256 + 2 * 49 * 4
+    t = p.traffic()
+    assert t["leaf"] == 49 * (96 * 128 * 2 + 128 * 64 * 2 + 96 * 64 * 4)
+
+
 def test_plan_errors():
     S = rbc.Scheme.builtin("strassen")
     with pytest.raises(rbc.RbcError) as e:
