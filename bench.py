@@ -10,6 +10,7 @@ in HBM.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload approx3072     # approximate scheme, bf16 hi+lo leaves
     python bench.py --workload batch512       # 512 products of mixed N in one persistent launch
+    python bench.py --workload serve          # Poisson request stream, fp8 leaves, p50/p99 latency
     python bench.py --copy-calibration BYTES  # plain copy of known size (counter scale)
 """
 
@@ -248,6 +249,69 @@ def batch512(args):
     print(json.dumps(out), flush=True)
 
 
+def serve_stream(args):
+    """Requests C = A B arriving as a Poisson process at 2000 per second (seed 5000) for
+    --serve-seconds, N log-uniform in [128, 4096] (multiples of 32), scheme uniform over
+    Strassen, Laderman and the approximate (perturbed Strassen, lambda = 1e-3) scheme, one
+    algorithm seed per request, A and B N(0,1) generated on the device; fp8 leaves with
+    per-leaf power-of-two scales and one correction pass; admission under a 200 GB HBM
+    budget, 4 slots, continuous batching (the products admitted together launch their stages
+    on one slot's stream; batches on different slots overlap).  The same request stream is
+    also served through the persistent batch engine and with the plain f32 recursive form."""
+    import numpy as np
+    import torch
+
+    from paper_1905_07439_amd import serve
+
+    torch.cuda.set_device(0)
+    budget = 200e9
+
+    def run(prec, mode, duration, seed, keep=None):
+        reqs = serve.make_requests(2000, duration, seed)
+        ex = serve.GpuExecutor(prec=prec, mode=mode, keep=keep)
+        sch = serve.Scheduler(budget, max_batch=64)
+        # warm up: plans and kernels of every size class, outside the measured stream
+        warm = serve.make_requests(2000, 0.05, seed + 100)
+        serve.serve(warm, ex, serve.Scheduler(budget, 64), slots=4)
+        stats = serve.serve(reqs, ex, sch, slots=4)
+        return stats, reqs, ex
+
+    keep = {}
+    out_rows = {}
+    for prec, mode in (("fp8c", "direct"), ("fp8c", "batch"), ("f32", "direct")):
+        reqs_probe = serve.make_requests(2000, args.serve_seconds, 5000)
+        k = {r.rid: None for r in reqs_probe[::97]}
+        stats, reqs, ex = run(prec, mode, args.serve_seconds, 5000, keep=k)
+        errs = {}
+        for rid, val in k.items():
+            if val is None:
+                continue
+            A, B, C = val
+            ref = A.double() @ B.double()
+            e = float(torch.linalg.norm(C.double() - ref) / torch.linalg.norm(ref))
+            errs.setdefault(reqs[rid].scheme, []).append(e)
+        stats["rel_err_vs_fp64"] = {s: {"median": float(np.median(v)), "max": float(np.max(v))}
+                                    for s, v in errs.items()}
+        out_rows["%s_%s" % (prec, mode)] = stats
+        del ex
+        torch.cuda.empty_cache()
+    head = out_rows["fp8c_direct"]
+    out = {
+        "metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
+        "value": round(head["effective_tflops"], 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp8 e4m3 leaves + 1 correction pass (f32 accumulate)", "data": "synthetic",
+        "config": {"workload": "serving: Poisson 2000 req/s for %.1f s, N log-uniform [128, 4096], "
+                               "scheme uniform {strassen, laderman, approx lambda=1e-3}, fp8c leaves, "
+                               "200 GB admission budget, 4 slots, continuous batching; headline: each "
+                               "admitted product's stages launched on its slot's stream" % args.serve_seconds,
+                   "parallelism": "single GPU"},
+        "p50_ms": round(head["latency_ms"]["p50"], 3), "p99_ms": round(head["latency_ms"]["p99"], 3),
+        "runs": out_rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes):
     """A plain device copy of nbytes (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
     import torch
@@ -266,7 +330,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="strassen4096", choices=["strassen4096", "approx3072", "batch512"])
+    ap.add_argument("--workload", default="strassen4096",
+                    choices=["strassen4096", "approx3072", "batch512", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-budget-gb", type=int, default=24)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
@@ -281,6 +347,8 @@ def main():
         return approx3072(args)
     if args.workload == "batch512":
         return batch512(args)
+    if args.workload == "serve":
+        return serve_stream(args)
 
     import numpy as np
     import torch

@@ -285,8 +285,9 @@ rbc_status rbc_batch_add(rbc_batch b, rbc_plan p, const void* A, int64_t lda, co
                          void* C, int64_t ldc, uint64_t seed, rbc_mode mode, int kappa_scale,
                          int64_t* index);
 rbc_status rbc_batch_workspace(rbc_batch b, size_t* bytes);
-/* Build the task table for this workspace and upload it (synchronously on
- * stream).  Call again after adding products or to use another workspace. */
+/* Build the task table for this workspace and upload it (asynchronously on
+ * stream; the batch keeps its host copy unchanged until the upload is done).
+ * Call again after adding products or to use another workspace. */
 rbc_status rbc_batch_prepare(rbc_batch b, void* workspace, size_t ws_bytes, void* stream);
 /* Enqueue one run on stream: a counter reset and the persistent kernel.
  * use_graph != 0 captures both into a HIP graph on first use (stream must
@@ -295,6 +296,10 @@ rbc_status rbc_batch_launch(rbc_batch b, void* stream, int use_graph);
 /* Wait for stream, then report RBC_EHIP if a dependency wait timed out. */
 rbc_status rbc_batch_check(rbc_batch b, void* stream);
 rbc_status rbc_batch_get_info(rbc_batch b, rbc_batch_info* info);
+/* Workgroups of the persistent kernel for later launches (0: the resident
+ * maximum; larger values are clamped to it).  A smaller grid leaves room for
+ * kernels on other streams, e.g. other batches of a serving loop. */
+rbc_status rbc_batch_set_grid(rbc_batch b, int grid);
 /* Where a product's stage buffers live in the workspace (byte offset and
  * size), the queue index of its first task, and its two counters: the one
  * its first tasks wait on (previous users of its bytes) and the one its last

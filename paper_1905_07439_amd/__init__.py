@@ -343,6 +343,10 @@ class Batch:
                                          ctypes.byref(n)))
         return out
 
+    def set_grid(self, grid):
+        """Workgroups of the persistent kernel (0: the resident maximum)."""
+        check(lib().rbc_batch_set_grid(self._h, int(grid)))
+
     def trace(self):
         """Per-task (taken, ready, done) times in microseconds from the first task taken, and
         the workgroup, of the last completed run (needs ``trace=True``)."""

@@ -94,6 +94,7 @@ SIGNATURES = {
     "rbc_batch_check": (ctypes.c_int, [c_vp, c_vp]),
     "rbc_batch_get_info": (ctypes.c_int, [c_vp, ctypes.POINTER(BatchInfo)]),
     "rbc_batch_trace": (ctypes.c_int, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64), c_dbl_p]),
+    "rbc_batch_set_grid": (ctypes.c_int, [c_vp, ctypes.c_int]),
     "rbc_batch_get_item": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(BatchItem)]),
     "rbc_batch_task_table": (ctypes.c_int, [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]),
     "rbc_batch_destroy": (None, [c_vp]),

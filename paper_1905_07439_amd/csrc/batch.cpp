@@ -70,7 +70,22 @@ struct rbc_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t graph_stream = nullptr;
+  // The task table's upload reads the host vectors: they must not change
+  // until this event (recorded after the copies) has completed.
+  hipEvent_t uploaded = nullptr;
+  bool upload_pending = false;
 };
+
+namespace {
+rbc_status wait_upload(rbc_batch_s& b) {
+  if (b.upload_pending) {
+    hipError_t e = hipEventSynchronize(b.uploaded);
+    if (e != hipSuccess) return fail(RBC_EHIP, "hipEventSynchronize: %s", hipGetErrorString(e));
+    b.upload_pending = false;
+  }
+  return RBC_OK;
+}
+}  // namespace
 
 namespace {
 
@@ -540,6 +555,8 @@ rbc_status rbc_batch_add(rbc_batch b, rbc_plan plan, const void* A, int64_t lda,
                          int64_t* index) {
   try {
     if (!b || !plan) return fail(RBC_EINVAL, "null batch or plan");
+    rbc_status ws = wait_upload(*b);
+    if (ws != RBC_OK) return ws;
     Plan& p = plan->p;
     if (!A || !B || !C) return fail(RBC_EINVAL, "null matrix pointer");
     if (lda < p.K || ldb < p.N || ldc < p.N) return fail(RBC_EINVAL, "leading dimension too small");
@@ -561,7 +578,9 @@ rbc_status rbc_batch_add(rbc_batch b, rbc_plan plan, const void* A, int64_t lda,
 rbc_status rbc_batch_workspace(rbc_batch b, size_t* bytes) {
   try {
     if (!b || !bytes) return fail(RBC_EINVAL, "null argument");
-    rbc_status st = build(*b, nullptr);
+    rbc_status st = wait_upload(*b);
+    if (st != RBC_OK) return st;
+    st = build(*b, nullptr);
     if (st != RBC_OK) return st;
     *bytes = b->lay.total;
     return RBC_OK;
@@ -576,11 +595,13 @@ rbc_status rbc_batch_prepare(rbc_batch b, void* workspace, size_t ws_bytes, void
     if (b->items.empty()) return fail(RBC_EINVAL, "empty batch");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign)
       return fail(RBC_EINVAL, "workspace must be non-null and 256-byte aligned");
+    rbc_status st = wait_upload(*b);
+    if (st != RBC_OK) return st;
     for (Item& it : b->items) {
-      rbc_status st = ensure_device(*it.plan);
+      st = ensure_device(*it.plan);
       if (st != RBC_OK) return st;
     }
-    rbc_status st = build(*b, static_cast<char*>(workspace));
+    st = build(*b, static_cast<char*>(workspace));
     if (st != RBC_OK) return st;
     if (ws_bytes < b->lay.total)
       return fail(RBC_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, b->lay.total);
@@ -590,7 +611,7 @@ rbc_status rbc_batch_prepare(rbc_batch b, void* workspace, size_t ws_bytes, void
     HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
     HIP_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device));
     if (bpc < 1) return fail(RBC_EHIP, "batch kernel cannot be resident");
-    b->grid = b->opt.grid > 0 ? b->opt.grid : bpc * cus;
+    b->grid = b->opt.grid > 0 ? std::min(b->opt.grid, bpc * cus) : bpc * cus;
     b->timeout_ticks = (int64_t)b->opt.timeout_ms * (rate_khz > 0 ? rate_khz : 100000);
     hipStream_t s = (hipStream_t)stream;
     char* ws = static_cast<char*>(workspace);
@@ -609,8 +630,10 @@ rbc_status rbc_batch_prepare(rbc_batch b, void* workspace, size_t ws_bytes, void
     if (!b->cparams.empty())
       HIP_CHECK(hipMemcpyAsync(ws + L.scale, b->cparams.data(), b->cparams.size() * sizeof(ScaleDesc),
                                hipMemcpyHostToDevice, s));
-    // the host vectors stay alive in the batch until the copies are done
-    HIP_CHECK(hipStreamSynchronize(s));
+    // the host vectors stay unchanged in the batch until the copies are done
+    if (!b->uploaded) HIP_CHECK(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
+    HIP_CHECK(hipEventRecord(b->uploaded, s));
+    b->upload_pending = true;
     if (b->exec) (void)hipGraphExecDestroy(b->exec), b->exec = nullptr;
     if (b->graph) (void)hipGraphDestroy(b->graph), b->graph = nullptr;
     b->prepared = true;
@@ -747,8 +770,25 @@ rbc_status rbc_batch_get_item(rbc_batch b, int64_t index, rbc_batch_item* out) {
   return RBC_OK;
 }
 
+rbc_status rbc_batch_set_grid(rbc_batch b, int grid) {
+  if (!b) return fail(RBC_EINVAL, "null batch");
+  if (grid < 0) return fail(RBC_EINVAL, "grid must be >= 0");
+  b->opt.grid = grid;
+  if (b->prepared) {
+    int bpc = 0, cus = 0;
+    HIP_CHECK(batch_occupancy(b->prec, &bpc));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    b->grid = grid > 0 ? std::min(grid, bpc * cus) : bpc * cus;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec), b->exec = nullptr;
+    if (b->graph) (void)hipGraphDestroy(b->graph), b->graph = nullptr;
+  }
+  return RBC_OK;
+}
+
 void rbc_batch_destroy(rbc_batch b) {
   if (!b) return;
+  (void)wait_upload(*b);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   delete b;
