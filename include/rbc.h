@@ -190,6 +190,23 @@ rbc_status rbc_matmul_draws(rbc_plan p, const void* A, int64_t lda, const void* 
                             void* C, int64_t ldc, const int32_t* signs, const int32_t* perms,
                             int kappa_scale, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- averages of several products (Section 3, error of average) -----------
+ * Cavg = (1/K) sum_k F-hat_k(A, B), F-hat_k with the draws of (seeds[k], mode),
+ * accumulated elementwise in f64 in the order k = 0, 1, ..., K-1 (Cavg: device,
+ * M x N contiguous f64; seeds: host array of K).  The workspace holds the plan's
+ * workspace and one product (rbc_average_workspace bytes). */
+rbc_status rbc_average_workspace(rbc_plan p, size_t* bytes);
+rbc_status rbc_matmul_average(rbc_plan p, const void* A, int64_t lda, const void* B, int64_t ldb, double* Cavg,
+                              const uint64_t* seeds, int64_t K, rbc_mode mode, int kappa_scale, void* workspace,
+                              size_t ws_bytes, void* stream);
+/* acc (rows x cols, contiguous f64, device) = (first ? 0 : acc) + X elementwise;
+ * X is f64 (x_is_f64) or f32 with row stride ldx.  Building block for averages
+ * over explicit draws. */
+rbc_status rbc_accumulate(double* acc, const void* X, int x_is_f64, int64_t rows, int64_t cols, int64_t ldx,
+                          int first, void* stream);
+/* x[i] *= s for i < n (device f64). */
+rbc_status rbc_scale_f64(double* x, int64_t n, double s, void* stream);
+
 /* ---- stages of rbc_matmul, for composition and testing --------------------
  * gather:  which = 0 forms every leaf S (from A), which = 1 every leaf T
  *          (from B), into the workspace at info.off_S / info.off_T, as

@@ -201,6 +201,43 @@ class Plan:
                                      C.stride(0), sp, pp, int(bool(kappa_scale)), _ptr(ws), ws.numel(), st))
         return C
 
+    def matmul_average(self, A, B, seeds, mode="full", kappa_scale=None, stream=None):
+        """(1/K) sum_k F-hat_k(A, B) over the draws of seeds[k], accumulated in f64 (a new
+        float64 tensor)."""
+        import torch
+        if kappa_scale is None:
+            kappa_scale = mode != "none"
+        M, N = self.info["M"], self.info["N"]
+        for name, X, shape in (("A", A, (M, self.info["K"])), ("B", B, (self.info["K"], N))):
+            if tuple(X.shape) != shape or X.dtype != self.dtype or not X.is_cuda or X.stride(1) != 1:
+                raise ValueError("%s must be a row-major %s CUDA tensor of shape %s" % (name, self.dtype, shape))
+        n = ctypes.c_size_t()
+        check(lib().rbc_average_workspace(self._h, ctypes.byref(n)))
+        ws = torch.empty(n.value, dtype=torch.uint8, device=A.device)
+        out = torch.empty((M, N), dtype=torch.float64, device=A.device)
+        sd = (ctypes.c_uint64 * len(seeds))(*[int(x) & 0xFFFFFFFFFFFFFFFF for x in seeds])
+        st = stream if stream is not None else torch.cuda.current_stream(A.device)
+        check(lib().rbc_matmul_average(self._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(out), sd,
+                                       len(seeds), MODES[mode], int(bool(kappa_scale)), _ptr(ws), ws.numel(),
+                                       ctypes.c_void_p(st.cuda_stream)))
+        return out
+
+    def average_over_draws(self, A, B, draws, kappa_scale=True, stream=None):
+        """(1/K) sum over explicit draws [(signs, perms), ...] (as rbc_matmul_draws takes them),
+        accumulated in f64 on the device."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(A.device)
+        M, N = self.info["M"], self.info["N"]
+        out = torch.empty((M, N), dtype=torch.float64, device=A.device)
+        C = torch.empty((M, N), dtype=self.dtype, device=A.device)
+        ws = self.workspace(A.device)
+        for k, (signs, perms) in enumerate(draws):
+            self.matmul_draws(A, B, signs, perms, C=C, kappa_scale=kappa_scale, workspace=ws, stream=st)
+            check(lib().rbc_accumulate(_ptr(out), _ptr(C), int(self.prec == "f64"), M, N, C.stride(0),
+                                       int(k == 0), ctypes.c_void_p(st.cuda_stream)))
+        check(lib().rbc_scale_f64(_ptr(out), M * N, 1.0 / len(draws), ctypes.c_void_p(st.cuda_stream)))
+        return out
+
     def draws(self, seed, mode="full"):
         """Concatenated per-level draws of (seed, mode), as rbc_matmul computes them."""
         ss, ps = [], []

@@ -78,6 +78,11 @@ SIGNATURES = {
                                   ctypes.c_int, ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]),
     "rbc_matmul_draws": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_i32_p, c_i32_p,
                                         ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]),
+    "rbc_average_workspace": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "rbc_matmul_average": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, ctypes.POINTER(ctypes.c_uint64),
+                                          c_i64, ctypes.c_int, ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]),
+    "rbc_accumulate": (ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_i64, c_i64, c_i64, ctypes.c_int, c_vp]),
+    "rbc_scale_f64": (ctypes.c_int, [c_vp, c_i64, ctypes.c_double, c_vp]),
     "rbc_stage_gather": (ctypes.c_int, [c_vp, ctypes.c_int, c_vp, c_i64, c_i32_p, c_i32_p, c_vp,
                                         ctypes.c_size_t, c_vp]),
     "rbc_stage_leaf": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, c_vp]),

@@ -316,6 +316,56 @@ rbc_status rbc_matmul_draws(rbc_plan h, const void* A, int64_t lda, const void* 
   RBC_GUARD_END
 }
 
+rbc_status rbc_accumulate(double* acc, const void* X, int x_is_f64, int64_t rows, int64_t cols, int64_t ldx,
+                          int first, void* stream) {
+  if (!acc || !X) return fail(RBC_EINVAL, "null pointer");
+  if (rows < 0 || cols < 0 || ldx < cols) return fail(RBC_EINVAL, "bad shape");
+  HIP_CHECK(launch_accumulate(acc, X, x_is_f64 ? ELT_F64 : ELT_F32, rows, cols, ldx, first != 0,
+                              (hipStream_t)stream));
+  return RBC_OK;
+}
+
+rbc_status rbc_scale_f64(double* x, int64_t n, double s, void* stream) {
+  if (!x || n < 0) return fail(RBC_EINVAL, "bad argument");
+  HIP_CHECK(launch_scale_f64(x, n, s, (hipStream_t)stream));
+  return RBC_OK;
+}
+
+rbc_status rbc_average_workspace(rbc_plan h, size_t* bytes) {
+  if (!h || !bytes) return fail(RBC_EINVAL, "null argument");
+  const Plan& p = h->p;
+  const size_t elt = p.prec == RBC_PREC_F64 ? 8 : 4;
+  *bytes = (p.ws_bytes + 255) / 256 * 256 + (size_t)p.M * p.N * elt;
+  return RBC_OK;
+}
+
+rbc_status rbc_matmul_average(rbc_plan h, const void* A, int64_t lda, const void* B, int64_t ldb, double* Cavg,
+                              const uint64_t* seeds, int64_t K, rbc_mode mode, int kappa_scale, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  RBC_GUARD_BEGIN
+  if (!h || !Cavg || !seeds) return fail(RBC_EINVAL, "null argument");
+  if (K < 1) return fail(RBC_EINVAL, "K must be at least 1");
+  if (mode < RBC_MODE_FULL || mode > RBC_MODE_NONE) return fail(RBC_EINVAL, "bad mode %d", (int)mode);
+  Plan& p = h->p;
+  size_t need = 0;
+  rbc_status st = rbc_average_workspace(h, &need);
+  if (st != RBC_OK) return st;
+  if (!workspace || ws_bytes < need) return fail(RBC_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  const size_t plan_ws = (p.ws_bytes + 255) / 256 * 256;
+  void* prod = static_cast<char*>(workspace) + plan_ws;
+  const Elt elt = p.prec == RBC_PREC_F64 ? ELT_F64 : ELT_F32;
+  std::vector<int32_t> s, pm;
+  for (int64_t k = 0; k < K; ++k) {
+    seeded_draws(p, seeds[k], mode, s, pm);
+    st = matmul_impl(p, A, lda, B, ldb, prod, p.N, s.data(), pm.data(), kappa_scale, workspace, plan_ws, stream);
+    if (st != RBC_OK) return st;
+    HIP_CHECK(launch_accumulate(Cavg, prod, elt, p.M, p.N, p.N, k == 0, (hipStream_t)stream));
+  }
+  HIP_CHECK(launch_scale_f64(Cavg, p.M * p.N, 1.0 / (double)K, (hipStream_t)stream));
+  return RBC_OK;
+  RBC_GUARD_END
+}
+
 rbc_status rbc_stage_gather(rbc_plan h, int which, const void* X, int64_t ldx, const int32_t* signs,
                             const int32_t* perms, void* workspace, size_t ws_bytes, void* stream) {
   RBC_GUARD_BEGIN

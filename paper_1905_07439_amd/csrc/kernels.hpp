@@ -72,6 +72,10 @@ hipError_t launch_gemm_f16s(const uint16_t* S, const uint16_t* T, float* P, int6
 // scaled by 2^eS[l], 2^eT[l]; P = 2^-(eS+eT) (hi hi + (hi lo + lo hi) / 16).
 hipError_t launch_gemm_fp8c(const uint8_t* S, const uint8_t* T, float* P, int64_t m, int64_t n, int64_t k,
                             int64_t batch, int tile, const int32_t* eS, const int32_t* eT, hipStream_t stream);
+// acc (rows x cols, contiguous f64) = (first ? 0 : acc) + x (row stride ldx), elementwise.
+hipError_t launch_accumulate(double* acc, const void* x, Elt elt, int64_t rows, int64_t cols, int64_t ldx,
+                             int first, hipStream_t s);
+hipError_t launch_scale_f64(double* acc, int64_t n, double scale, hipStream_t s);
 // max |X| into *maxbits, then e[l] = floor(log2(target / (G[l] max|X|))) for every leaf.
 hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, uint32_t* maxbits,
                               const float* G, int32_t* e, int64_t n_leaves, float target, hipStream_t s);
