@@ -197,6 +197,27 @@ def batch512(args):
     ms = float(np.mean(per))
     value = flops / (ms * 1e-3) / 1e12
 
+    # the same batch through the level-synchronous executor (grouped launches in one graph)
+    lb = rbc.Batch(item_budget=args.batch_budget_gb << 30, mode="levels")
+    Cl = [torch.empty_like(c) for c in Cs]
+    for i, n in enumerate(sizes):
+        lb.add(plans16[n], As[i], Bs[i], C=Cl[i], seed=i, mode="full")
+    with torch.cuda.stream(stream):
+        lb.prepare(stream=stream)
+    for _ in range(args.warmup):
+        lb.launch(graph=True, stream=stream)
+    lb.check(stream=stream)
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev2[0].record(stream)
+    for k in range(args.steps):
+        lb.launch(graph=True, stream=stream)
+        ev2[k + 1].record(stream)
+    lb.check(stream=stream)
+    ms_levels = float(np.mean([ev2[k].elapsed_time(ev2[k + 1]) for k in range(args.steps)]))
+    same_bits = all(torch.equal(a, b) for a, b in zip(Cs, Cl))
+    linfo = lb.info()
+    del lb, Cl
+
     # accuracy of every product against the float64 product of the same operands
     errs = []
     for i in range(count):
@@ -240,6 +261,9 @@ def batch512(args):
         "batch": {k: info[k] for k in ("n_tasks", "gather_tasks", "leaf_tasks", "scatter_tasks", "gate_tasks",
                                        "grid", "workspace_bytes")},
         "prepare_s": round(prep_s, 3),
+        "levels_mode": {"ms_per_step": round(ms_levels, 4), "tflops": round(flops / ms_levels / 1e9, 3),
+                        "launches": linfo["launches"], "levels": linfo["levels"],
+                        "bitwise_equal_to_persistent": same_bits},
         "same_gpu": {"f16s_one_by_one_ms": round(seq16, 3), "f32_recursive_one_by_one_ms": round(seq32, 3),
                      "f32_recursive_rel_err_max": max(errs32),
                      "standard_f32_gemm_one_by_one_ms": round(std32, 3)},

@@ -268,11 +268,22 @@ typedef struct {
                         * With a budget the regions form a ring: a product reuses the
                         * bytes of earlier ones and its first tasks wait until those
                         * have finished.  Must hold the largest product's buffers. */
+  int32_t mode;        /* RBC_BATCH_PERSISTENT (0) or RBC_BATCH_LEVELS (1), below */
+  int32_t reserved;
 } rbc_batch_options;
+
+/* Execution modes of a batch.  PERSISTENT: one persistent kernel takes the tasks
+ * from a queue and waits on dependency counters.  LEVELS: the tasks are grouped by
+ * their depth in the dependency graph and by type, and every group runs as one
+ * grid of one-piece workgroups (a few tens of launches per batch, ordered by the
+ * stream); timeout_ms, trace and grid do not apply.  Both give every product the
+ * same bits. */
+enum { RBC_BATCH_PERSISTENT = 0, RBC_BATCH_LEVELS = 1 };
 
 typedef struct {
   int64_t n_items, n_tasks, n_counters;
   int64_t scale_tasks, gather_tasks, leaf_tasks, scatter_tasks, gate_tasks;
+  int64_t levels, launches;  /* RBC_BATCH_LEVELS: dependency depths and grouped launches */
   size_t workspace_bytes; /* total, as rbc_batch_workspace */
   size_t control_bytes;   /* task table, parameters and counters (the rest is stage buffers) */
   int32_t grid, prec;
@@ -306,7 +317,8 @@ rbc_status rbc_batch_workspace(rbc_batch b, size_t* bytes);
  * stream; the batch keeps its host copy unchanged until the upload is done).
  * Call again after adding products or to use another workspace. */
 rbc_status rbc_batch_prepare(rbc_batch b, void* workspace, size_t ws_bytes, void* stream);
-/* Enqueue one run on stream: a counter reset and the persistent kernel.
+/* Enqueue one run on stream: a counter reset and the persistent kernel (or the
+ * grouped launches of RBC_BATCH_LEVELS).
  * use_graph != 0 captures both into a HIP graph on first use (stream must
  * not be the default stream) and replays it afterwards. */
 rbc_status rbc_batch_launch(rbc_batch b, void* stream, int use_graph);

@@ -309,9 +309,11 @@ class Batch:
     batch is in use.
     """
 
-    def __init__(self, window=0, grid=0, timeout_ms=0, task_bytes=0, item_budget=0, trace=False):
+    def __init__(self, window=0, grid=0, timeout_ms=0, task_bytes=0, item_budget=0, trace=False,
+                 mode="persistent"):
+        modes = {"persistent": 0, "levels": 1}
         opt = BatchOptions(window=window, grid=grid, timeout_ms=timeout_ms, task_bytes=task_bytes,
-                           item_budget=item_budget, trace=int(bool(trace)))
+                           item_budget=item_budget, trace=int(bool(trace)), mode=modes[mode])
         h = ctypes.c_void_p()
         check(lib().rbc_batch_create(ctypes.byref(opt), ctypes.byref(h)))
         self._h = h

@@ -34,13 +34,15 @@ class PlanInfo(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("grid", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
-                ("trace", ctypes.c_int32), ("task_bytes", c_i64), ("item_budget", c_i64)]
+                ("trace", ctypes.c_int32), ("task_bytes", c_i64), ("item_budget", c_i64),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_items", c_i64), ("n_tasks", c_i64), ("n_counters", c_i64),
                 ("scale_tasks", c_i64), ("gather_tasks", c_i64), ("leaf_tasks", c_i64),
-                ("scatter_tasks", c_i64), ("gate_tasks", c_i64), ("workspace_bytes", ctypes.c_size_t),
+                ("scatter_tasks", c_i64), ("gate_tasks", c_i64), ("levels", c_i64), ("launches", c_i64),
+                ("workspace_bytes", ctypes.c_size_t),
                 ("control_bytes", ctypes.c_size_t), ("grid", ctypes.c_int32), ("prec", ctypes.c_int32)]
 
     def as_dict(self):

@@ -41,7 +41,8 @@ struct Item {
 };
 
 struct Layout {  // byte offsets inside the batch workspace
-  size_t tasks = 0, gather = 0, scatter = 0, leaf = 0, scale = 0, ctl = 0, trace = 0, items = 0, total = 0;
+  size_t tasks = 0, gather = 0, scatter = 0, leaf = 0, scale = 0, ctl = 0, trace = 0, pieces = 0, items = 0,
+         total = 0;
   std::vector<size_t> item_ws;
 };
 
@@ -60,6 +61,14 @@ struct rbc_batch_s {
   std::vector<int32_t> cslots;  // per scale descriptor: counter word holding max|X| bits
   int64_t n_counters = 0;
   Layout lay;
+  // RBC_BATCH_LEVELS: launches in order, each a range of (task, piece) entries
+  struct GroupLaunch {
+    int32_t level, kind, variant;
+    int64_t begin, n;
+  };
+  std::vector<GroupLaunch> launches;
+  std::vector<int32_t> piece_table;  // pairs (task, piece)
+  int64_t n_levels = 0;
   std::vector<int32_t> item_gate, item_done;  // per item: counters, from the last build
   std::vector<int64_t> item_first;            // per item: queue index of its first task
   char* ws = nullptr;
@@ -494,6 +503,47 @@ void assemble(rbc_batch_s& b, std::vector<ItemTasks>& per, const Schedule& sc) {
   }
 }
 
+// RBC_BATCH_LEVELS: the depth of every task in the dependency graph (0 for a
+// task without waits, else one more than the deepest task that signals a
+// counter it waits on; signals precede waits in the queue), then one launch
+// per (depth, kind, variant) listing every piece of its tasks.
+void make_levels(rbc_batch_s& b) {
+  const size_t n = b.tasks.size();
+  std::vector<int32_t> clevel((size_t)b.n_counters, -1), level(n, 0);
+  int32_t top = 0;
+  for (size_t t = 0; t < n; ++t) {
+    const Task& k = b.tasks[t];
+    int32_t lv = 0;
+    for (int i = 0; i < 2; ++i)
+      if (k.wait[i] >= 0) lv = std::max(lv, clevel[(size_t)k.wait[i]] + 1);
+    level[t] = lv;
+    top = std::max(top, lv);
+    if (k.signal >= 0) clevel[(size_t)k.signal] = std::max(clevel[(size_t)k.signal], lv);
+  }
+  std::vector<int32_t> order(n);
+  for (size_t t = 0; t < n; ++t) order[t] = (int32_t)t;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const Task &a = b.tasks[(size_t)x], &c = b.tasks[(size_t)y];
+    if (level[(size_t)x] != level[(size_t)y]) return level[(size_t)x] < level[(size_t)y];
+    if (a.kind != c.kind) return a.kind < c.kind;
+    return a.variant < c.variant;
+  });
+  b.launches.clear(), b.piece_table.clear();
+  for (int32_t t : order) {
+    const Task& k = b.tasks[(size_t)t];
+    if (k.kind == TK_GATE) continue;  // ordering only
+    if (b.launches.empty() || b.launches.back().level != level[(size_t)t] || b.launches.back().kind != k.kind ||
+        b.launches.back().variant != k.variant)
+      b.launches.push_back({level[(size_t)t], k.kind, k.variant, (int64_t)b.piece_table.size() / 2, 0});
+    for (int32_t c = 0; c < k.count; ++c) {
+      b.piece_table.push_back(t);
+      b.piece_table.push_back((int32_t)(k.first + c));
+    }
+    b.launches.back().n += k.count;
+  }
+  b.n_levels = n ? top + 1 : 0;
+}
+
 // Build tasks, parameter blocks and the workspace layout for workspace base
 // `ws` (nullptr: sizes only).
 rbc_status build(rbc_batch_s& b, char* ws) {
@@ -511,6 +561,8 @@ rbc_status build(rbc_batch_s& b, char* ws) {
   if ((st = make_schedule(b, order, per, sc)) != RBC_OK) return st;
   assemble(b, per, sc);
   if (b.tasks.size() > 0x7fffffff) return fail(RBC_EINVAL, "batch: too many tasks");
+  const bool levels = b.opt.mode == RBC_BATCH_LEVELS;
+  if (levels) make_levels(b);
   Layout& L = b.lay;
   L.tasks = 0;
   L.gather = align_up(L.tasks + b.tasks.size() * sizeof(Task));
@@ -519,13 +571,15 @@ rbc_status build(rbc_batch_s& b, char* ws) {
   L.scale = align_up(L.leaf + b.lparams.size() * sizeof(LeafDesc));
   L.ctl = align_up(L.scale + b.cparams.size() * sizeof(ScaleDesc));
   L.trace = align_up(L.ctl + (CTL_WORDS + b.n_counters) * sizeof(int32_t));
-  L.items = align_up(L.trace + (b.opt.trace ? b.tasks.size() * 4 * sizeof(uint64_t) : 0));
+  L.pieces = align_up(L.trace + (b.opt.trace && !levels ? b.tasks.size() * 4 * sizeof(uint64_t) : 0));
+  L.items = align_up(L.pieces + (levels ? b.piece_table.size() * sizeof(int32_t) : 0));
   L.total = L.items + sc.region_bytes;
   L.item_ws = sc.offs;
   b.ws = ws;
   if (!ws) return RBC_OK;
   if ((st = build_items(b, ws + L.items, sc.offs, order, per)) != RBC_OK) return st;
   assemble(b, per, sc);
+  if (levels) make_levels(b);
   int32_t* words = reinterpret_cast<int32_t*>(ws + L.ctl) + CTL_WORDS;
   for (size_t i = 0; i < b.cparams.size(); ++i) b.cparams[i].maxbits = reinterpret_cast<uint32_t*>(words + b.cslots[i]);
   return RBC_OK;
@@ -543,6 +597,11 @@ rbc_status rbc_batch_create(const rbc_batch_options* opt, rbc_batch* out) {
     std::memset(&b->opt, 0, sizeof b->opt);
     if (opt) b->opt = *opt;
     if (b->opt.timeout_ms <= 0) b->opt.timeout_ms = 5000;
+    if (b->opt.mode != RBC_BATCH_PERSISTENT && b->opt.mode != RBC_BATCH_LEVELS) {
+      const int mode = b->opt.mode;
+      delete b;
+      return fail(RBC_EINVAL, "bad batch mode %d", mode);
+    }
     *out = b;
     return RBC_OK;
   } catch (const std::bad_alloc&) {
@@ -630,6 +689,9 @@ rbc_status rbc_batch_prepare(rbc_batch b, void* workspace, size_t ws_bytes, void
     if (!b->cparams.empty())
       HIP_CHECK(hipMemcpyAsync(ws + L.scale, b->cparams.data(), b->cparams.size() * sizeof(ScaleDesc),
                                hipMemcpyHostToDevice, s));
+    if (b->opt.mode == RBC_BATCH_LEVELS && !b->piece_table.empty())
+      HIP_CHECK(hipMemcpyAsync(ws + L.pieces, b->piece_table.data(), b->piece_table.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
     // the host vectors stay unchanged in the batch until the copies are done
     if (!b->uploaded) HIP_CHECK(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
     HIP_CHECK(hipEventRecord(b->uploaded, s));
@@ -650,6 +712,18 @@ namespace {
 rbc_status enqueue(rbc_batch_s& b, hipStream_t s) {
   KernelArgs a;
   const Layout& L = b.lay;
+  if (b.opt.mode == RBC_BATCH_LEVELS) {
+    HIP_CHECK(launch_zero_words(reinterpret_cast<int32_t*>(b.ws + L.ctl), CTL_WORDS + b.n_counters, s));
+    const Task* tasks = reinterpret_cast<const Task*>(b.ws + L.tasks);
+    const int32_t* pieces = reinterpret_cast<const int32_t*>(b.ws + L.pieces);
+    for (const auto& g : b.launches)
+      HIP_CHECK(launch_group(b.prec, g.kind, g.variant, tasks, pieces + 2 * g.begin,
+                             reinterpret_cast<const GatherParams*>(b.ws + L.gather),
+                             reinterpret_cast<const ScatterParams*>(b.ws + L.scatter),
+                             reinterpret_cast<const LeafDesc*>(b.ws + L.leaf),
+                             reinterpret_cast<const ScaleDesc*>(b.ws + L.scale), g.n, s));
+    return RBC_OK;
+  }
   a.tasks = reinterpret_cast<const Task*>(b.ws + L.tasks);
   a.n_tasks = (int64_t)b.tasks.size();
   a.gather = reinterpret_cast<const GatherParams*>(b.ws + L.gather);
@@ -722,6 +796,8 @@ rbc_status rbc_batch_get_info(rbc_batch b, rbc_batch_info* info) {
   info->grid = b->grid;
   info->prec = b->prec;
   info->workspace_bytes = b->lay.total;
+  info->levels = b->n_levels;
+  info->launches = (int64_t)b->launches.size();
   info->control_bytes = b->lay.items;
   for (const Task& t : b->tasks) {
     if (t.kind == TK_GATHER) info->gather_tasks++;
@@ -745,7 +821,8 @@ rbc_status rbc_batch_task_table(rbc_batch b, rbc_batch_task* out, int64_t cap, i
 
 rbc_status rbc_batch_trace(rbc_batch b, uint64_t* out, int64_t cap, int64_t* n, double* ticks_per_us) {
   if (!b || !n) return fail(RBC_EINVAL, "null argument");
-  if (!b->opt.trace || !b->prepared) return fail(RBC_EINVAL, "batch has no trace (options.trace, then prepare)");
+  if (!b->opt.trace || !b->prepared || b->opt.mode != RBC_BATCH_PERSISTENT)
+    return fail(RBC_EINVAL, "batch has no trace (persistent mode, options.trace, then prepare)");
   *n = (int64_t)b->tasks.size();
   if (ticks_per_us) {
     int rate_khz = 0;

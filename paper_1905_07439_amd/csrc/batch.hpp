@@ -127,6 +127,14 @@ struct KernelArgs {
 // RBC_PREC_F32, RBC_PREC_F16S or RBC_PREC_FP8C.
 hipError_t batch_occupancy(int prec, int* blocks_per_cu);
 hipError_t launch_batch(int prec, const KernelArgs& a, int grid, hipStream_t stream);
+// Level-synchronous groups (batch_group.hpp): one workgroup per entry.
+struct PieceRef;
+struct GroupArgs;
+hipError_t launch_group(int prec, int kind, int variant, const Task* tasks, const void* pieces,
+                        const GatherParams* gather, const ScatterParams* scatter, const LeafDesc* leaf,
+                        const ScaleDesc* scale, int64_t grid, hipStream_t stream);
+// Zero n control words (the counters, and the f16s/fp8c max|X| words).
+hipError_t launch_zero_words(int32_t* p, int64_t n, hipStream_t stream);
 
 }  // namespace batch
 }  // namespace rbc

@@ -17,6 +17,14 @@ hipError_t batch_occupancy(int prec, int* b) {
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_zero_words(int32_t* p, int64_t n, hipStream_t s) {
+  int64_t zb = (n + 255) / 256;
+  if (zb > 1024) zb = 1024;
+  if (zb < 1) zb = 1;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)zb), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch(int prec, const KernelArgs& a, int grid, hipStream_t s) {
   if (prec == RBC_PREC_F32) return launch_f32(a, grid, s);
   if (prec == RBC_PREC_F16S) return launch<RBC_PREC_F16S>(a, grid, s);

@@ -79,26 +79,6 @@ __device__ __forceinline__ void vstore(gbl<T>* p, VecT<T, V> v) {
 #endif
 }
 
-// Round to the nearest OCP e4m3 value (ties to even) and encode: bias 7,
-// 3 fraction bits, subnormal spacing 2^-9, largest finite 448.  The caller
-// keeps |f| <= 448; larger magnitudes saturate to 448.
-__device__ __forceinline__ uint32_t e4m3_rne(float f) {
-  const uint32_t u = __float_as_uint(f);
-  const uint32_t sign = (u >> 24) & 0x80u;
-  const float a = fminf(fabsf(f), 448.0f);
-  uint32_t code;
-  if (a < 0.015625f) {  // below 2^-6: subnormal grid of 2^-9 (rintf: ties to even)
-    code = (uint32_t)rintf(a * 512.0f);  // 0 .. 8 (8 is the smallest normal, 2^-6)
-  } else {
-    const uint32_t b = __float_as_uint(a);
-    // keep 3 fraction bits: round the f32 mantissa at bit 20, ties to even
-    const uint32_t r = b + 0x7FFFFu + ((b >> 20) & 1u);
-    const uint32_t e = (r >> 23) - 127 + 7;  // rebias (carry may raise the exponent)
-    code = (e << 3) | ((r >> 20) & 7u);
-  }
-  return sign | code;
-}
-
 template <typename T, int OUTF, int V>
 struct GatherEmit {
   void* dst;
@@ -110,23 +90,24 @@ struct GatherEmit {
       // streaming store: the leaf operands are read once, by the next kernel
       vstore<T, V>(global_ptr(static_cast<T*>(dst)) + idx * dst_batch + off, v);
     } else if constexpr (OUTF == OUT_FP8X2) {
-      // scaled split: y = 2^e v, hi = rn_e4m3(y), lo = rn_e4m3(16 (y - hi)) (y - hi is exact)
+      // scaled split: y = 2^e v, hi = rn_e4m3(y), lo = rn_e4m3(16 (y - hi)) (y - hi is exact);
+      // the conversions are the hardware's OCP e4m3 round-to-nearest-even ones
       const int ex = exps[idx - exp_base];
-      uint32_t hi = 0, lo = 0;
+      float y[4], r[4];
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const float y = ldexpf((float)v[e], ex);
-        const uint32_t h = e4m3_rne(y);
-        const float hv = ldexpf((float)(h & 7u) + ((h & 0x78u) ? 8.f : 0.f),
-                                (h & 0x78u) ? (int)((h >> 3) & 15u) - 10 : -9);
-        const float hs = (h & 0x80u) ? -hv : hv;
-        hi |= h << (8 * e);
-        lo |= e4m3_rne(16.0f * (y - hs)) << (8 * e);
-      }
+      for (int e = 0; e < 4; ++e) y[e] = e < V ? ldexpf((float)v[e < V ? e : 0], ex) : 0.f;
+      int hi = __builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+      if constexpr (V == 4) hi = __builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], hi, true);
+      r[0] = 16.0f * (y[0] - __builtin_amdgcn_cvt_f32_fp8(hi, 0));
+      r[1] = 16.0f * (y[1] - __builtin_amdgcn_cvt_f32_fp8(hi, 1));
+      r[2] = 16.0f * (y[2] - __builtin_amdgcn_cvt_f32_fp8(hi, 2));
+      r[3] = 16.0f * (y[3] - __builtin_amdgcn_cvt_f32_fp8(hi, 3));
+      int lo = __builtin_amdgcn_cvt_pk_fp8_f32(r[0], r[1], 0, false);
+      if constexpr (V == 4) lo = __builtin_amdgcn_cvt_pk_fp8_f32(r[2], r[3], lo, true);
       gbl<uint8_t>* d = global_ptr(static_cast<uint8_t*>(dst)) + idx * dst_batch + off;
       if constexpr (V == 4) {
-        *reinterpret_cast<gbl<uint32_t>*>(d) = hi;
-        *reinterpret_cast<gbl<uint32_t>*>(d + plane) = lo;
+        *reinterpret_cast<gbl<uint32_t>*>(d) = (uint32_t)hi;
+        *reinterpret_cast<gbl<uint32_t>*>(d + plane) = (uint32_t)lo;
       } else if constexpr (V == 2) {
         *reinterpret_cast<gbl<uint16_t>*>(d) = (uint16_t)hi;
         *reinterpret_cast<gbl<uint16_t>*>(d + plane) = (uint16_t)lo;

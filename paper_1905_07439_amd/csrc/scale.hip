@@ -15,10 +15,11 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 
 __global__ __launch_bounds__(256) void k_maxabs(const float* __restrict__ X, int64_t ld, int64_t rows,
                                                 int64_t cols, uint32_t* out) {
-  // rows blockIdx.x, blockIdx.x + gridDim.x, ...
-  float m = 0.f;
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) m = fmaxf(m, scale::maxabs_rows(X, ld, cols, r, 1));
-  scale::maxabs_fold(m, out);
+  // a contiguous range of rows per block
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t nr = r0 < rows ? (rows - r0 < per ? rows - r0 : per) : 0;
+  scale::maxabs_fold(scale::maxabs_rows(X, ld, cols, r0, nr), out);
 }
 
 __global__ void k_leaf_scales(const uint32_t* maxbits, const float* __restrict__ G, int32_t* e,
@@ -33,7 +34,10 @@ __global__ void k_leaf_scales(const uint32_t* maxbits, const float* __restrict__
 hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, uint32_t* maxbits,
                               const float* G, int32_t* e, int64_t n_leaves, float target, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, maxbits, (int64_t)1, 0u);
-  int64_t blocks = rows < 4096 ? rows : 4096;
+  // about 16 KB of X per block, at most 2048 blocks
+  int64_t blocks = (rows * cols + 4095) / 4096;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks > rows) blocks = rows;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_maxabs, dim3((unsigned)blocks), dim3(256), 0, s, X, ld, rows, cols, maxbits);
   int64_t lb = (n_leaves + 255) / 256;

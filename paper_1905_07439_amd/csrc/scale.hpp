@@ -19,15 +19,41 @@ namespace rbc {
 namespace scale {
 
 // max |X| over rows [row0, row0 + nrows) of a row-major matrix with cols
-// columns and row stride ld: this thread's share (256 threads stride along
-// each row).
+// columns and row stride ld: this thread's share.  The 256 threads walk the
+// rows' elements in 16-byte chunks when the layout allows (cols and ld
+// multiples of 4, X 16-byte aligned), four independent loads per step so that
+// several are in flight.
 __device__ __forceinline__ float maxabs_rows(const float* __restrict__ X, int64_t ld, int64_t cols,
                                              int64_t row0, int64_t nrows) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
   const gbl<const float>* Xg = global_ptr(X);
-  float m = 0.f;
-  for (int64_t r = row0; r < row0 + nrows; ++r)
-    for (int64_t c = threadIdx.x; c < cols; c += 256) m = fmaxf(m, fabsf(Xg[r * ld + c]));
-  return m;
+  float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+  if (cols % 4 == 0 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+    const int64_t c4 = cols / 4, n = nrows * c4;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+      f4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = i + 256 * u < n ? i + 256 * u : i;
+        const int64_t r = j / c4, c = j - r * c4;
+        v[u] = *reinterpret_cast<const gbl<const f4>*>(Xg + (row0 + r) * ld + 4 * c);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        m0 = fmaxf(m0, fabsf(v[u][0]));
+        m1 = fmaxf(m1, fabsf(v[u][1]));
+        m2 = fmaxf(m2, fabsf(v[u][2]));
+        m3 = fmaxf(m3, fabsf(v[u][3]));
+      }
+    }
+  } else {
+    const int64_t n = nrows * cols;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      const int64_t r = i / cols, c = i - r * cols;
+      m0 = fmaxf(m0, fabsf(Xg[(row0 + r) * ld + c]));
+    }
+  }
+  return fmaxf(fmaxf(m0, m1), fmaxf(m2, m3));
 }
 
 // Fold the threads' maxima into *out as the bits of a non-negative float
