@@ -282,7 +282,8 @@ def serve_stream(args):
     per-leaf power-of-two scales and one correction pass; admission under a 200 GB HBM
     budget, 4 slots, continuous batching (the products admitted together launch their stages
     on one slot's stream; batches on different slots overlap).  The same request stream is
-    also served through the persistent batch engine and with the plain f32 recursive form."""
+    also served through the batch engine (level-synchronous launches, one batch per admission)
+    and with the plain f32 recursive form."""
     import numpy as np
     import torch
 
@@ -293,7 +294,7 @@ def serve_stream(args):
 
     def run(prec, mode, duration, seed, keep=None):
         reqs = serve.make_requests(2000, duration, seed)
-        ex = serve.GpuExecutor(prec=prec, mode=mode, keep=keep)
+        ex = serve.GpuExecutor(prec=prec, mode=mode, keep=keep, engine="levels")
         sch = serve.Scheduler(budget, max_batch=64)
         # warm up: plans and kernels of every size class, outside the measured stream
         warm = serve.make_requests(2000, 0.05, seed + 100)

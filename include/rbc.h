@@ -100,9 +100,9 @@ typedef struct {
   size_t workspace_bytes;   /* minimum workspace for rbc_matmul */
   size_t off_S, off_T, off_P;      /* byte offsets of the leaf operands and products */
   size_t bytes_S, bytes_T, bytes_P;
-  size_t off_aux, bytes_aux;       /* RBC_PREC_F16S, RBC_PREC_FP8C: max|A|, max|B| bits (2 x u32),
-                                      then the per-leaf exponents of S and of T (n_leaves int32
-                                      each) */
+  size_t off_aux, bytes_aux;       /* RBC_PREC_F16S, RBC_PREC_FP8C: partial maxima of |A| and of
+                                      |B| (1024 f32 each, scratch), then at off_aux + 8192 the
+                                      per-leaf exponents of S and of T (n_leaves int32 each) */
 } rbc_plan_info;
 
 const char* rbc_status_str(rbc_status s);

@@ -100,11 +100,11 @@ class Scheme:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
+            self._h = None  # at interpreter exit module globals may already be gone
             try:
                 lib().rbc_scheme_destroy(h)
             except Exception:
                 pass
-            self._h = ctypes.c_void_p()
 
 
 def draw(seed, depth, b1, b2, b3, mode="full"):
@@ -286,11 +286,11 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
+            self._h = None  # at interpreter exit module globals may already be gone
             try:
                 lib().rbc_plan_destroy(h)
             except Exception:
                 pass
-            self._h = ctypes.c_void_p()
 
 
 # Layout of rbc_batch_task (include/rbc.h).
@@ -413,8 +413,8 @@ class Batch:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
+            self._h = None  # at interpreter exit module globals may already be gone
             try:
                 lib().rbc_batch_destroy(h)
             except Exception:
                 pass
-            self._h = ctypes.c_void_p()

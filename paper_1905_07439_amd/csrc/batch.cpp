@@ -273,7 +273,8 @@ struct Builder {
         b.cslots.push_back(cbits[sd]);
         d.G = l.G, d.e = l.e, d.n_leaves = l.n_leaves;
         d.pieces = l.rows;  // one piece per row
-        d.target = l.target, d.pad_ = 0;
+        d.target = l.target;
+        d.level_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(1 << 16, (64 << 10) / std::max<int64_t>(4 * d.cols, 1)));
         max_pieces[sd] = d.pieces;
         b.cparams.push_back(d);
       }
@@ -535,11 +536,14 @@ void make_levels(rbc_batch_s& b) {
     if (b.launches.empty() || b.launches.back().level != level[(size_t)t] || b.launches.back().kind != k.kind ||
         b.launches.back().variant != k.variant)
       b.launches.push_back({level[(size_t)t], k.kind, k.variant, (int64_t)b.piece_table.size() / 2, 0});
-    for (int32_t c = 0; c < k.count; ++c) {
+    // max|X| pieces cover level_rows rows each; every other piece is one workgroup's unit
+    const int32_t step = k.kind == TK_MAXABS ? b.cparams[(size_t)k.param].level_rows : 1;
+    int64_t np = 0;
+    for (int32_t c = 0; c < k.count; c += step, ++np) {
       b.piece_table.push_back(t);
       b.piece_table.push_back((int32_t)(k.first + c));
     }
-    b.launches.back().n += k.count;
+    b.launches.back().n += np;
   }
   b.n_levels = n ? top + 1 : 0;
 }

@@ -65,8 +65,8 @@ struct ScaleDesc {
   int32_t* e;
   int64_t n_leaves;
   int64_t pieces;
-  float target;  // bound of the scaled operand (2^15 for f16, 448 for e4m3)
-  int32_t pad_;
+  float target;        // bound of the scaled operand (2^15 for f16, 448 for e4m3)
+  int32_t level_rows;  // rows per workgroup in the level-synchronous mode
 };
 
 struct CombVariant {

@@ -83,12 +83,15 @@ __global__ __launch_bounds__(256) void k_group_leaf(GroupArgs a) {
   }
 }
 
-// Scale tasks: max|X| pieces are rows; the exponent task is one piece.
+// Scale tasks: a max|X| piece is a run of level_rows rows of its task (the
+// last one shorter); the exponent task is one piece.
 static __global__ __launch_bounds__(256) void k_group_maxabs(GroupArgs a) {
   int32_t piece;
   const Task& task = group_task(a, &piece);
   const ScaleDesc& d = a.scale[task.param];
-  scale::maxabs_fold(scale::maxabs_rows(d.X, d.ld, d.cols, piece, 1), d.maxbits);
+  const int64_t end = task.first + task.count;
+  const int64_t nr = end - piece < d.level_rows ? end - piece : d.level_rows;
+  scale::maxabs_fold(scale::maxabs_rows(d.X, d.ld, d.cols, piece, nr), d.maxbits);
 }
 
 static __global__ __launch_bounds__(256) void k_group_exponents(GroupArgs a) {

@@ -82,6 +82,10 @@ struct LevelTables {  // host copies, uploaded once per device
   std::vector<float> Uf, Vf, Wf, Wkf;
 };
 
+// Byte offset of the per-leaf exponents in the auxiliary workspace: after
+// 1024 partial maxima for each of A and B.
+constexpr size_t kAuxExpOffset = 2 * 1024 * sizeof(float);
+
 struct Plan {
   int64_t M = 0, K = 0, N = 0, Mp = 0, Kp = 0, Np = 0, mM = 0, mK = 0, mN = 0;
   int64_t n_leaves = 1;
@@ -92,8 +96,9 @@ struct Plan {
   std::vector<LevelTables> tables;
   std::vector<Group> groups;
   size_t ws_bytes = 0, off_S = 0, off_T = 0, off_P = 0, bytes_S = 0, bytes_T = 0, bytes_P = 0;
-  // f16s: auxiliary workspace (max bits, per-leaf exponents) and the per-leaf
-  // path norms G of the A and B sides (product over levels of coefficient 1-norms)
+  // f16s, fp8c: auxiliary workspace (partial maxima of |A| and |B|, then the
+  // per-leaf exponents at kAuxExpOffset) and the per-leaf path norms G of the A
+  // and B sides (product over levels of coefficient 1-norms)
   size_t off_aux = 0, bytes_aux = 0;
   std::vector<float> gA, gB;
   size_t g_off[2] = {0, 0};

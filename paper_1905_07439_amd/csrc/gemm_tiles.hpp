@@ -172,11 +172,25 @@ __device__ __forceinline__ floatx4 mfma16(u32x4 a, u32x4 b, floatx4 c) {
                                                    c, 0, 0, 0);
 }
 
+// 16-bit leaf operands: S slabs keep their k-contiguous rows in LDS; T slabs
+// keep their n-contiguous rows and every T operand (8 k values of one column)
+// is two transposing LDS reads (ds_read_b64_tr_b16): in each group of 16
+// lanes, lane s reads 4 halves of k row s / 4 at column offset 4 (s % 4), and
+// lane t receives half t % 4 of the reads of lanes 4j + t / 4, j = 0..3, which
+// is column t over the 4 k rows.
 template <int KIND, int BM, int BN>
 struct LowpTile {
-  static constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1, BK = 32, LDK = BK + 8;
-  static constexpr int SMEM_HALVES = 2 * NP * (BM + BN) * LDK;  // two buffers of S and T slabs
+  static constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1, BK = 32, LDK = BK + 8, LDB = BN + 16;
+  static constexpr int A_HALVES = NP * BM * LDK, B_HALVES = NP * BK * LDB;  // one buffer
+  static constexpr int SMEM_HALVES = 2 * (A_HALVES + B_HALVES);             // two buffers
 };
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+
+__device__ __forceinline__ u32x2 lds_read_tr16(const uint16_t* p) {
+  return __builtin_bit_cast(u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)(p)));
+}
 
 // Output tile `bid` of the batched reduced-precision leaf product.
 template <int KIND, int BM, int BN>
@@ -186,18 +200,18 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
                                                const int32_t* __restrict__ eS,
                                                const int32_t* __restrict__ eT, int tiles_n,
                                                int tiles_per_leaf, int64_t bid, uint16_t* smem) {
-  constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1;  // operand planes (hi, lo)
-  constexpr int BK = 32;
-  constexpr int LDK = BK + 8;  // padded row of 40 halves (80 bytes)
+  using Tile = LowpTile<KIND, BM, BN>;
+  constexpr int NP = Tile::NP;  // operand planes (hi, lo)
+  constexpr int BK = Tile::BK, LDK = Tile::LDK, LDB = Tile::LDB;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int A_TOTAL = NP * BM * BK / 8;          // 16-byte chunks of an S slab
+  constexpr int A_TOTAL = NP * BM * BK / 8;  // 16-byte chunks of an S slab
   constexpr int A_ITER = (A_TOTAL + 255) / 256;
-  constexpr int B_TOTAL = NP * (BK / 4) * (BN / 8);  // 4k x 8n groups of a T slab
+  constexpr int B_TOTAL = NP * BK * BN / 8;  // 16-byte chunks of a T slab
   constexpr int B_ITER = (B_TOTAL + 255) / 256;
   uint16_t(*As)[NP][BM][LDK] = reinterpret_cast<uint16_t(*)[NP][BM][LDK]>(smem);  // [buf][plane][row][k]
-  uint16_t(*Bs)[NP][BN][LDK] =
-      reinterpret_cast<uint16_t(*)[NP][BN][LDK]>(smem + 2 * NP * BM * LDK);        // [buf][plane][col][k]
+  uint16_t(*Bs)[NP][BK][LDB] =
+      reinterpret_cast<uint16_t(*)[NP][BK][LDB]>(smem + 2 * Tile::A_HALVES);      // [buf][plane][k][col]
   const int64_t leaf = bid / tiles_per_leaf;
   const int t = (int)(bid - leaf * tiles_per_leaf);
   const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
@@ -220,19 +234,16 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
 #pragma unroll
   for (int i = 0; i < B_ITER; ++i) {
     const int idx = (tid + 256 * i) % B_TOTAL;
-    const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
-    b_src[i] = Tl + pl * plane_t + (int64_t)((rem / (BN / 8)) * 4) * n + (rem % (BN / 8)) * 8;
+    const int pl = idx / (BK * BN / 8), rem = idx % (BK * BN / 8);
+    b_src[i] = Tl + pl * plane_t + (int64_t)(rem / (BN / 8)) * n + (rem % (BN / 8)) * 8;
   }
 
   // clang vector types (not HIP's uint4 struct) so the staging stays in registers
-  u32x4 ra[A_ITER];
-  u32x4 rb[B_ITER][4];
+  u32x4 ra[A_ITER], rb[B_ITER];
 #pragma unroll
   for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i]);
 #pragma unroll
-  for (int i = 0; i < B_ITER; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)r * n);
+  for (int i = 0; i < B_ITER; ++i) rb[i] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i]);
 
   floatx4 acc[FM][FN];
 #pragma unroll
@@ -242,9 +253,10 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
 
   const int nk = k / BK;
   const int lr = lane & 15, lg = lane >> 4;
+  // this lane's part of the transposing T reads: k rows lg * 8 + lr / 4 (+ 4), column offset 4 (lr % 4)
+  const int tr_row = lg * 8 + (lr >> 2), tr_col = wn * WN + (lr & 3) * 4;
   int cur = 0;
   for (int kt = 0; kt < nk; ++kt) {
-    // registers -> LDS buffer `cur`; T is transposed so that k is contiguous
 #pragma unroll
     for (int i = 0; i < A_ITER; ++i) {
       const int idx = tid + 256 * i;
@@ -256,17 +268,8 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
     for (int i = 0; i < B_ITER; ++i) {
       const int idx = tid + 256 * i;
       if (B_TOTAL % 256 && idx >= B_TOTAL) break;
-      const int pl = idx / ((BK / 4) * (BN / 8)), rem = idx % ((BK / 4) * (BN / 8));
-      const int kg = rem / (BN / 8), cg = rem % (BN / 8);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        // element c of each of the 4 rows: 16-bit halves of 32-bit word c / 2
-        const int w = c >> 1, sh = (c & 1) * 16;
-        u32x2 v;
-        v[0] = ((rb[i][0][w] >> sh) & 0xFFFFu) | (((rb[i][1][w] >> sh) & 0xFFFFu) << 16);
-        v[1] = ((rb[i][2][w] >> sh) & 0xFFFFu) | (((rb[i][3][w] >> sh) & 0xFFFFu) << 16);
-        *reinterpret_cast<u32x2*>(&Bs[cur][pl][cg * 8 + c][kg * 4]) = v;
-      }
+      const int pl = idx / (BK * BN / 8), rem = idx % (BK * BN / 8);
+      *reinterpret_cast<u32x4*>(&Bs[cur][pl][rem / (BN / 8)][(rem % (BN / 8)) * 8]) = rb[i];
     }
     __syncthreads();
     if (kt + 1 < nk) {
@@ -275,25 +278,29 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
       for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i] + k1);
 #pragma unroll
       for (int i = 0; i < B_ITER; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)(k1 + r) * n);
+        rb[i] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)k1 * n);
     }
     u32x4 ah[FM], bh[FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
       ah[i] = *reinterpret_cast<const u32x4*>(&As[cur][0][wm * WM + i * 16 + lr][lg * 8]);
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
-      bh[j] = *reinterpret_cast<const u32x4*>(&Bs[cur][0][wn * WN + j * 16 + lr][lg * 8]);
+    for (int j = 0; j < FN; ++j) {
+      const u32x2 lo = lds_read_tr16(&Bs[cur][0][tr_row][tr_col + j * 16]);
+      const u32x2 hi = lds_read_tr16(&Bs[cur][0][tr_row + 4][tr_col + j * 16]);
+      bh[j] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+    }
     if constexpr (NP == 2) {
       u32x4 al[FM], bl[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
         al[i] = *reinterpret_cast<const u32x4*>(&As[cur][NP - 1][wm * WM + i * 16 + lr][lg * 8]);
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        bl[j] = *reinterpret_cast<const u32x4*>(&Bs[cur][NP - 1][wn * WN + j * 16 + lr][lg * 8]);
+      for (int j = 0; j < FN; ++j) {
+        const u32x2 lo = lds_read_tr16(&Bs[cur][NP - 1][tr_row][tr_col + j * 16]);
+        const u32x2 hi = lds_read_tr16(&Bs[cur][NP - 1][tr_row + 4][tr_col + j * 16]);
+        bl[j] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+      }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -329,19 +336,29 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
 // S and T hold a hi plane and a lo plane of bytes (lo scaled by 16).  Per
 // output: acc = sum hi_S hi_T and cor = sum (hi_S lo_T + lo_S hi_T), both f32,
 // on v_mfma_f32_16x16x32_fp8_fp8; P = 2^-(eS + eT) (acc + cor / 16).  K
-// advances in slabs of 64 bytes; S slabs keep their k-contiguous rows in LDS,
-// T slabs are transposed on the way in (8 k rows x 16 columns per group, each
-// column's 8 k bytes one 8-byte LDS store), so every MFMA operand is one
-// 8-byte LDS read.
+// advances in slabs of 64 bytes.  Both slabs are copied to LDS as they lie in
+// memory (S rows k-contiguous, T rows n-contiguous), in 16-byte chunks.  An S
+// operand is one 8-byte LDS read; a T operand is one transposing LDS read
+// (ds_read_b64_tr_b8): in each group of 16 lanes, lane s reads 8 bytes of
+// k row s / 2 at column offset 8 (s % 2), and lane t receives byte t % 8 of
+// the reads of lanes 2j + t / 8, j = 0..7, which is column t over the 8 k rows.
 template <int BM, int BN>
 struct Fp8Tile {
-  static constexpr int BK = 64, LDK = BK + 8;
-  static constexpr int SMEM_BYTES = 2 * 2 * (BM + BN) * LDK;  // two buffers, two planes
+  static constexpr int BK = 64, LDK = BK + 8, LDB = BN + 16;
+  static constexpr int A_BYTES = 2 * BM * LDK, B_BYTES = 2 * BK * LDB;  // one buffer, both planes
+  static constexpr int SMEM_BYTES = 2 * (A_BYTES + B_BYTES);            // two buffers
 };
 
 __device__ __forceinline__ floatx4 mfma_fp8(u32x2 a, u32x2 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c,
                                                      0, 0, 0);
+}
+
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) i32x2 lds_i32x2;
+
+__device__ __forceinline__ u32x2 lds_read_tr8(const uint8_t* p) {
+  return __builtin_bit_cast(u32x2, __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_i32x2*)(p)));
 }
 
 template <int BM, int BN>
@@ -350,14 +367,16 @@ __device__ __forceinline__ void gemm_fp8c_tile(const uint8_t* __restrict__ S, co
                                                int64_t plane_t, const int32_t* __restrict__ eS,
                                                const int32_t* __restrict__ eT, int tiles_n, int tiles_per_leaf,
                                                int64_t bid, uint8_t* smem) {
-  constexpr int BK = Fp8Tile<BM, BN>::BK, LDK = Fp8Tile<BM, BN>::LDK;
+  using Tile = Fp8Tile<BM, BN>;
+  constexpr int BK = Tile::BK, LDK = Tile::LDK, LDB = Tile::LDB;
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
-  constexpr int A_TOTAL = 2 * BM * (BK / 16);        // 16-byte chunks of an S slab (both planes)
+  constexpr int A_TOTAL = 2 * BM * (BK / 16);  // 16-byte chunks of an S slab (both planes)
   constexpr int A_ITER = (A_TOTAL + 255) / 256;
-  constexpr int B_TOTAL = 2 * (BK / 8) * (BN / 16);  // 8k x 16n groups of a T slab (both planes)
+  constexpr int B_TOTAL = 2 * BK * (BN / 16);  // 16-byte chunks of a T slab (both planes)
   constexpr int B_ITER = (B_TOTAL + 255) / 256;
-  uint8_t(*As)[2][BM][LDK] = reinterpret_cast<uint8_t(*)[2][BM][LDK]>(smem);  // [buf][plane][row][k]
-  uint8_t(*Bs)[2][BN][LDK] = reinterpret_cast<uint8_t(*)[2][BN][LDK]>(smem + 2 * 2 * BM * LDK);
+  // [buf][plane][row][k] and [buf][plane][k][col]
+  uint8_t(*As)[2][BM][LDK] = reinterpret_cast<uint8_t(*)[2][BM][LDK]>(smem);
+  uint8_t(*Bs)[2][BK][LDB] = reinterpret_cast<uint8_t(*)[2][BK][LDB]>(smem + 2 * Tile::A_BYTES);
   const int64_t leaf = bid / tiles_per_leaf;
   const int t = (int)(bid - leaf * tiles_per_leaf);
   const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
@@ -380,18 +399,15 @@ __device__ __forceinline__ void gemm_fp8c_tile(const uint8_t* __restrict__ S, co
 #pragma unroll
   for (int i = 0; i < B_ITER; ++i) {
     const int idx = (tid + 256 * i) % B_TOTAL;
-    const int pl = idx / ((BK / 8) * (BN / 16)), rem = idx % ((BK / 8) * (BN / 16));
-    b_src[i] = Tl + pl * plane_t + (int64_t)((rem / (BN / 16)) * 8) * n + (rem % (BN / 16)) * 16;
+    const int pl = idx / (BK * (BN / 16)), rem = idx % (BK * (BN / 16));
+    b_src[i] = Tl + pl * plane_t + (int64_t)(rem / (BN / 16)) * n + (rem % (BN / 16)) * 16;
   }
 
-  u32x4 ra[A_ITER];
-  u32x4 rb[B_ITER][8];
+  u32x4 ra[A_ITER], rb[B_ITER];
 #pragma unroll
   for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i]);
 #pragma unroll
-  for (int i = 0; i < B_ITER; ++i)
-#pragma unroll
-    for (int r = 0; r < 8; ++r) rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)r * n);
+  for (int i = 0; i < B_ITER; ++i) rb[i] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i]);
 
   floatx4 acc[FM][FN], cor[FM][FN];
 #pragma unroll
@@ -401,6 +417,8 @@ __device__ __forceinline__ void gemm_fp8c_tile(const uint8_t* __restrict__ S, co
 
   const int nk = k / BK;
   const int lr = lane & 15, lg = lane >> 4;
+  // this lane's part of a transposing T read: k row lg * 8 + lr / 2, column offset 8 (lr % 2)
+  const int tr_row = lg * 8 + (lr >> 1), tr_col = wn * WN + (lr & 1) * 8;
   int cur = 0;
   for (int kt = 0; kt < nk; ++kt) {
 #pragma unroll
@@ -414,19 +432,8 @@ __device__ __forceinline__ void gemm_fp8c_tile(const uint8_t* __restrict__ S, co
     for (int i = 0; i < B_ITER; ++i) {
       const int idx = tid + 256 * i;
       if (B_TOTAL % 256 && idx >= B_TOTAL) break;
-      const int pl = idx / ((BK / 8) * (BN / 16)), rem = idx % ((BK / 8) * (BN / 16));
-      const int kg = rem / (BN / 16), cg = rem % (BN / 16);
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        // byte c of each of the 8 k rows: byte c % 4 of 32-bit word c / 4
-        const int w = c >> 2, sh = (c & 3) * 8;
-        u32x2 v;
-        v[0] = ((rb[i][0][w] >> sh) & 0xFFu) | (((rb[i][1][w] >> sh) & 0xFFu) << 8) |
-               (((rb[i][2][w] >> sh) & 0xFFu) << 16) | (((rb[i][3][w] >> sh) & 0xFFu) << 24);
-        v[1] = ((rb[i][4][w] >> sh) & 0xFFu) | (((rb[i][5][w] >> sh) & 0xFFu) << 8) |
-               (((rb[i][6][w] >> sh) & 0xFFu) << 16) | (((rb[i][7][w] >> sh) & 0xFFu) << 24);
-        *reinterpret_cast<u32x2*>(&Bs[cur][pl][cg * 16 + c][kg * 8]) = v;
-      }
+      const int pl = idx / (BK * (BN / 16)), rem = idx % (BK * (BN / 16));
+      *reinterpret_cast<u32x4*>(&Bs[cur][pl][rem / (BN / 16)][(rem % (BN / 16)) * 16]) = rb[i];
     }
     __syncthreads();
     if (kt + 1 < nk) {
@@ -435,9 +442,7 @@ __device__ __forceinline__ void gemm_fp8c_tile(const uint8_t* __restrict__ S, co
       for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i] + k1);
 #pragma unroll
       for (int i = 0; i < B_ITER; ++i)
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-          rb[i][r] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)(k1 + r) * n);
+        rb[i] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)k1 * n);
     }
 #pragma unroll
     for (int kk = 0; kk < BK / 32; ++kk) {
@@ -449,8 +454,8 @@ __device__ __forceinline__ void gemm_fp8c_tile(const uint8_t* __restrict__ S, co
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        bh[j] = *reinterpret_cast<const u32x2*>(&Bs[cur][0][wn * WN + j * 16 + lr][kk * 32 + lg * 8]);
-        bl[j] = *reinterpret_cast<const u32x2*>(&Bs[cur][1][wn * WN + j * 16 + lr][kk * 32 + lg * 8]);
+        bh[j] = lds_read_tr8(&Bs[cur][0][kk * 32 + tr_row][tr_col + j * 16]);
+        bl[j] = lds_read_tr8(&Bs[cur][1][kk * 32 + tr_row][tr_col + j * 16]);
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)

@@ -76,8 +76,10 @@ hipError_t launch_gemm_fp8c(const uint8_t* S, const uint8_t* T, float* P, int64_
 hipError_t launch_accumulate(double* acc, const void* x, Elt elt, int64_t rows, int64_t cols, int64_t ldx,
                              int first, hipStream_t s);
 hipError_t launch_scale_f64(double* acc, int64_t n, double scale, hipStream_t s);
-// max |X| into *maxbits, then e[l] = floor(log2(target / (G[l] max|X|))) for every leaf.
-hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, uint32_t* maxbits,
+// Partial maxima of |X| (at most kScalePartials floats at `partial`, overwritten),
+// then e[l] = floor(log2(target / (G[l] max|X|))) for every leaf.
+constexpr int kScalePartials = 1024;
+hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, float* partial,
                               const float* G, int32_t* e, int64_t n_leaves, float target, hipStream_t s);
 
 }  // namespace rbc

@@ -16,6 +16,9 @@
 
 namespace rbc {
 
+static_assert(kAuxExpOffset == 2 * kScalePartials * sizeof(float), "aux layout");
+
+
 rbc_status ensure_device(Plan& p) {
   int dev = -1;
   HIP_CHECK(hipGetDevice(&dev));
@@ -166,8 +169,8 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     ScaleLaunch sl;
     sl.X = static_cast<const float*>(X), sl.ld = ldx;
     sl.rows = which == 0 ? p.M : p.K, sl.cols = which == 0 ? p.K : p.N;
-    sl.maxbits = reinterpret_cast<uint32_t*>(ws + p.off_aux) + which;
-    exps = reinterpret_cast<int32_t*>(ws + p.off_aux + 256) + (size_t)which * p.n_leaves;
+    sl.partial = reinterpret_cast<float*>(ws + p.off_aux) + (size_t)which * kScalePartials;
+    exps = reinterpret_cast<int32_t*>(ws + p.off_aux + kAuxExpOffset) + (size_t)which * p.n_leaves;
     sl.G = reinterpret_cast<const float*>(static_cast<const char*>(p.dev_tables) + p.g_off[which]);
     sl.e = exps, sl.n_leaves = p.n_leaves;
     sl.target = p.prec == RBC_PREC_FP8C ? 448.0f : 32768.0f;
@@ -221,7 +224,7 @@ LeafLaunch build_leaf(const Plan& p, char* ws) {
   L.m = p.mM, L.n = p.mN, L.k = p.mK, L.batch = p.n_leaves, L.tile = p.tile_m;
   L.eS = L.eT = nullptr;
   if (p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C) {
-    L.eS = reinterpret_cast<const int32_t*>(ws + p.off_aux + 256);
+    L.eS = reinterpret_cast<const int32_t*>(ws + p.off_aux + kAuxExpOffset);
     L.eT = L.eS + p.n_leaves;
   }
   return L;
@@ -264,7 +267,7 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
 }
 
 hipError_t launch(const ScaleLaunch& l, hipStream_t s) {
-  return launch_leaf_scales(l.X, l.ld, l.rows, l.cols, l.maxbits, l.G, l.e, l.n_leaves, l.target, s);
+  return launch_leaf_scales(l.X, l.ld, l.rows, l.cols, l.partial, l.G, l.e, l.n_leaves, l.target, s);
 }
 
 hipError_t launch(const GatherLaunch& l, hipStream_t s) {

@@ -26,7 +26,7 @@ rbc_status ensure_device(Plan& p);
 struct ScaleLaunch {  // f16s, fp8c: max|X| and the per-leaf exponents of one operand
   const float* X;
   int64_t ld, rows, cols;
-  uint32_t* maxbits;
+  float* partial;  // kScalePartials partial maxima
   const float* G;
   int32_t* e;
   int64_t n_leaves;

@@ -173,7 +173,7 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   }
   if (prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) {
     p.off_aux = off;
-    p.bytes_aux = 256 + 2 * (size_t)p.n_leaves * 4;
+    p.bytes_aux = kAuxExpOffset + 2 * (size_t)p.n_leaves * 4;
     off = align256(off + p.bytes_aux);
     // per-leaf path norms: leaf l = (r_0, ..., r_{Q-1}), r_{Q-1} fastest
     p.gA.assign(p.n_leaves, 1.0f), p.gB.assign(p.n_leaves, 1.0f);

@@ -4,8 +4,9 @@ Requests arrive over time (a Poisson process in the load generator).  The
 scheduler admits waiting requests in arrival order while their HBM footprint
 (A, B, C and the plan's workspace) fits the budget and an execution slot (a
 HIP stream) is free, and launches everything it admitted at that moment as
-one batch: one persistent launch of the batch engine (``Batch``), or, in
-``direct`` mode, the per-stage launches of each product.  Requests that arrive
+one batch: one launch of the batch engine (``Batch``, persistent or
+level-synchronous), or, in ``direct`` mode, the per-stage launches of each
+product.  Requests that arrive
 while earlier batches run are admitted as soon as memory and a slot free up;
 batches on different slots overlap on the device.  A request's latency is
 its completion time (from a HIP event on its slot, on the device clock) minus
@@ -173,11 +174,13 @@ class GpuExecutor:
     """Runs admitted requests on the GPU: operands N(0,1) generated on the device from the
     request seed (A from 2 rid + 1, B from 2 rid + 2), plans cached per (N, scheme)."""
 
-    def __init__(self, prec="fp8c", mode="batch", device="cuda:0", keep=None):
+    def __init__(self, prec="fp8c", mode="batch", device="cuda:0", keep=None, engine="levels"):
         import torch
         import paper_1905_07439_amd as rbc
+        if mode not in ("batch", "direct"):
+            raise ValueError("mode must be 'batch' or 'direct'")
         self.torch, self.rbc = torch, rbc
-        self.prec, self.mode, self.device = prec, mode, device
+        self.prec, self.mode, self.device, self.engine = prec, mode, device, engine
         self.streams = {}
         self.plans = {}
         self.keep = keep  # dict rid -> C (and operands) for requests to keep, or None
@@ -233,15 +236,15 @@ class GpuExecutor:
                     self._keep(r, A, B, C)
                 batch = None
             else:
-                batch = self.rbc.Batch()
+                batch = self.rbc.Batch(mode=self.engine)
                 for r in reqs:
                     A, B = self.operands(r)
                     _, C = batch.add(self.plan(r), A, B, seed=r.seed, mode="full")
                     keepalive.append((A, B, C))
                     self._keep(r, A, B, C)
                 ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device=self.device)
-                info = batch.info()
-                batch.set_grid(min(512, max(32, info["n_tasks"] // 4)))
+                if self.engine == "persistent":
+                    batch.set_grid(min(512, max(32, batch.info()["n_tasks"] // 4)))
                 batch.prepare(ws, stream=s)
                 batch.launch(stream=s)
                 keepalive.append(ws)

@@ -137,19 +137,20 @@ def test_batch_options_ring_and_graph_replays():
         for it, w in zip(its, want):
             assert torch.equal(it[5], w), opt
     s = torch.cuda.Stream()
-    b, its = _build("f16s", F16S_SPECS, "gauss", reps=1, item_budget=int(biggest * 1.6))
-    with torch.cuda.stream(s):
-        b.prepare(stream=s)
-    for rep in range(3):
-        for it in its:
-            it[5].fill_(float("nan"))
-        x = torch.randn(1024, 1024, device=DEV)
-        (x @ x).sum().item()  # unrelated eager work between replays
-        torch.cuda.synchronize()
-        b.launch(graph=True, stream=s)
-        b.check(stream=s)
-        for it, w in zip(its, want):
-            assert torch.equal(it[5], w), rep
+    for engine in ("persistent", "levels"):
+        b, its = _build("f16s", F16S_SPECS, "gauss", reps=1, item_budget=int(biggest * 1.6), mode=engine)
+        with torch.cuda.stream(s):
+            b.prepare(stream=s)
+        for rep in range(3):
+            for it in its:
+                it[5].fill_(float("nan"))
+            x = torch.randn(1024, 1024, device=DEV)
+            (x @ x).sum().item()  # unrelated eager work between replays
+            torch.cuda.synchronize()
+            b.launch(graph=True, stream=s)
+            b.check(stream=s)
+            for it, w in zip(its, want):
+                assert torch.equal(it[5], w), (engine, rep)
 
 
 def test_batch_reruns_and_check():

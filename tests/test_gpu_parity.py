@@ -21,6 +21,7 @@ from oracle import precision, recursion, schemes as osch, tensors as oten
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
+AUX_EXPS = 8192  # byte offset of the per-leaf exponents in the auxiliary region (include/rbc.h)
 
 
 def setup_module(module):
@@ -342,7 +343,7 @@ def test_f16s_scaled_leaves(case):
     L, mM, mK, mN = info["n_leaves"], info["mM"], info["mK"], info["mN"]
     Sg = _region(ws, info["off_S"], info["bytes_S"], torch.int16, (L, mM, mK)).view(np.float16)
     Tg = _region(ws, info["off_T"], info["bytes_T"], torch.int16, (L, mK, mN)).view(np.float16)
-    ex = _region(ws, info["off_aux"] + 256, 2 * L * 4, torch.int32, (2, L))
+    ex = _region(ws, info["off_aux"] + AUX_EXPS, 2 * L * 4, torch.int32, (2, L))
     dims = (mM, mK, mN)
     ops = recursion.leaf_operands(A, B, ref_s, dr, arith="f32", leaf_dims=dims)
     gA, gB = precision.path_norms(ref_s, "A"), precision.path_norms(ref_s, "B")
@@ -389,7 +390,7 @@ def test_fp8c_split_leaves(case):
     L, mM, mK, mN = info["n_leaves"], info["mM"], info["mK"], info["mN"]
     Sg = _region(ws, info["off_S"], info["bytes_S"], torch.uint8, (2, L, mM, mK))
     Tg = _region(ws, info["off_T"], info["bytes_T"], torch.uint8, (2, L, mK, mN))
-    ex = _region(ws, info["off_aux"] + 256, 2 * L * 4, torch.int32, (2, L))
+    ex = _region(ws, info["off_aux"] + AUX_EXPS, 2 * L * 4, torch.int32, (2, L))
     dims = (mM, mK, mN)
     ops = recursion.leaf_operands(A, B, ref_s, dr, arith="f32", leaf_dims=dims)
     gA, gB = precision.path_norms(ref_s, "A"), precision.path_norms(ref_s, "B")

@@ -1,5 +1,5 @@
 """The serving loop on the GPU: every request's result in the mix equals, bit for bit,
-the same product run alone (same plan, operands, seed), in both execution modes; results
+the same product run alone (same plan, operands, seed), in every execution mode; results
 are within the fp8 leaves' error of the float64 product."""
 
 import sys
@@ -18,14 +18,14 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("mode", ["batch", "direct"])
-def test_served_results_equal_alone(mode):
+@pytest.mark.parametrize("mode,engine", [("batch", "persistent"), ("batch", "levels"), ("direct", "levels")])
+def test_served_results_equal_alone(mode, engine):
     reqs = serve.make_requests(4000, 0.03, 11, lo=128, hi=640)
     keep = {r.rid: None for r in reqs}
-    ex = serve.GpuExecutor(prec="fp8c", mode=mode, keep=keep)
+    ex = serve.GpuExecutor(prec="fp8c", mode=mode, keep=keep, engine=engine)
     sch = serve.Scheduler(200e9, max_batch=32)
     stats = serve.serve(reqs, ex, sch, slots=4)
-    _say(mode, {k: stats[k] for k in ("requests", "batches", "mean_batch", "latency_ms")})
+    _say(mode, engine, {k: stats[k] for k in ("requests", "batches", "mean_batch", "latency_ms")})
     assert stats["requests"] == len(reqs) and sch.in_use == 0
     assert all(np.isfinite(r.done) and r.done >= r.arrival for r in reqs)
     if mode == "batch":

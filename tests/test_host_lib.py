@@ -153,7 +153,7 @@ def test_f16s_plan_geometry():
     with pytest.raises(rbc.RbcError):
         rbc.Plan(480, 480, 480, [L, S], prec="f16s", leaf_tile=48)
     assert i["bytes_S"] == 161 * 96 * 96 * 2
-    assert i["bytes_aux"] == 256 + 2 * 161 * 4 and i["off_aux"] >= i["off_P"] + i["bytes_P"]
+    assert i["bytes_aux"] == 2 * 1024 * 4 + 2 * 161 * 4 and i["off_aux"] >= i["off_P"] + i["bytes_P"]
     q = rbc.Plan(768, 768, 768, [L, S], prec="f16s")
     assert q.info["tile_m"] == 128 and q.info["mM"] == 128
 
@@ -166,7 +166,7 @@ def test_fp8c_plan_geometry():
     # 64-byte slab; two one-byte planes per operand element
     assert (i["mM"], i["mK"], i["mN"], i["tile_m"], i["tile_k"]) == (96, 128, 64, 32, 64)
     assert i["bytes_S"] == 49 * 96 * 128 * 2 and i["bytes_T"] == 49 * 128 * 64 * 2
-    assert i["bytes_aux"] == 256 + 2 * 49 * 4
+    assert i["bytes_aux"] == 2 * 1024 * 4 + 2 * 49 * 4
     t = p.traffic()
     assert t["leaf"] == 49 * (96 * 128 * 2 + 128 * 64 * 2 + 96 * 64 * 4)
 
