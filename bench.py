@@ -283,31 +283,42 @@ def serve_stream(args):
     budget, 4 slots, continuous batching (the products admitted together launch their stages
     on one slot's stream; batches on different slots overlap).  The same request stream is
     also served through the batch engine (level-synchronous launches, one batch per admission)
-    and with the plain f32 recursive form."""
+    and with the plain f32 recursive form.  The recursion depth of each (size, scheme) comes
+    from the autotuner (timed trials at five size classes before the stream starts); one more
+    fp8 run uses the fixed depth rule (leaves of about 192) for comparison."""
     import numpy as np
     import torch
 
     from paper_1905_07439_amd import serve
+    from paper_1905_07439_amd.tune import Tuner
 
     torch.cuda.set_device(0)
     budget = 200e9
 
-    def run(prec, mode, duration, seed, keep=None):
+    tuners = {}
+
+    def run(prec, mode, duration, seed, keep=None, tuned=True):
         reqs = serve.make_requests(2000, duration, seed)
-        ex = serve.GpuExecutor(prec=prec, mode=mode, keep=keep, engine="levels")
+        if tuned and prec not in tuners:
+            tuners[prec] = Tuner()
+        ex = serve.GpuExecutor(prec=prec, mode=mode, keep=keep, engine="levels",
+                               tuner=tuners[prec] if tuned else None)
+        depths = ex.tune()  # timed trials per scheme and size class, before the stream starts
         sch = serve.Scheduler(budget, max_batch=64)
         # warm up: plans and kernels of every size class, outside the measured stream
         warm = serve.make_requests(2000, 0.05, seed + 100)
         serve.serve(warm, ex, serve.Scheduler(budget, 64), slots=4)
         stats = serve.serve(reqs, ex, sch, slots=4)
+        stats["tuned_depth"] = depths
         return stats, reqs, ex
 
     keep = {}
     out_rows = {}
-    for prec, mode in (("fp8c", "direct"), ("fp8c", "batch"), ("f32", "direct")):
+    for prec, mode, tuned in (("fp8c", "direct", True), ("fp8c", "batch", True), ("f32", "direct", True),
+                              ("fp8c", "direct", False)):
         reqs_probe = serve.make_requests(2000, args.serve_seconds, 5000)
         k = {r.rid: None for r in reqs_probe[::97]}
-        stats, reqs, ex = run(prec, mode, args.serve_seconds, 5000, keep=k)
+        stats, reqs, ex = run(prec, mode, args.serve_seconds, 5000, keep=k, tuned=tuned)
         errs = {}
         for rid, val in k.items():
             if val is None:
@@ -318,7 +329,20 @@ def serve_stream(args):
             errs.setdefault(reqs[rid].scheme, []).append(e)
         stats["rel_err_vs_fp64"] = {s: {"median": float(np.median(v)), "max": float(np.max(v))}
                                     for s, v in errs.items()}
-        out_rows["%s_%s" % (prec, mode)] = stats
+        out_rows["%s_%s%s" % (prec, mode, "" if tuned else "_fixed_depth")] = stats
+        del ex
+        torch.cuda.empty_cache()
+    # capacity: the same requests all present at time 0 (the loop runs as fast as the device allows)
+    capacity = {}
+    for prec in ("fp8c", "f32"):
+        reqs = serve.make_requests(2000, args.serve_seconds, 5000)
+        for r in reqs:
+            r.arrival = 0.0
+        ex = serve.GpuExecutor(prec=prec, mode="direct", engine="levels", tuner=tuners[prec])
+        ex.tune()
+        st = serve.serve(reqs, ex, serve.Scheduler(budget, max_batch=64), slots=4)
+        capacity[prec] = {"tflops": round(st["effective_tflops"], 3), "span_s": round(st["span_s"], 4),
+                          "requests": st["requests"]}
         del ex
         torch.cuda.empty_cache()
     head = out_rows["fp8c_direct"]
@@ -329,11 +353,13 @@ def serve_stream(args):
         "dtype": "fp8 e4m3 leaves + 1 correction pass (f32 accumulate)", "data": "synthetic",
         "config": {"workload": "serving: Poisson 2000 req/s for %.1f s, N log-uniform [128, 4096], "
                                "scheme uniform {strassen, laderman, approx lambda=1e-3}, fp8c leaves, "
-                               "200 GB admission budget, 4 slots, continuous batching; headline: each "
-                               "admitted product's stages launched on its slot's stream" % args.serve_seconds,
+                               "200 GB admission budget, 4 slots, continuous batching, recursion depth "
+                               "per size class from timed trials; headline: each admitted product's "
+                               "stages launched on its slot's stream" % args.serve_seconds,
                    "parallelism": "single GPU"},
         "p50_ms": round(head["latency_ms"]["p50"], 3), "p99_ms": round(head["latency_ms"]["p99"], 3),
         "runs": out_rows,
+        "capacity_all_arrived_at_0": capacity,
     }
     print(json.dumps(out), flush=True)
 

@@ -12,7 +12,7 @@ namespace {
 using tiles::Fp8Tile;
 
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void k_gemm_fp8c(const uint8_t* __restrict__ S, const uint8_t* __restrict__ T,
+__global__ __launch_bounds__(256, 2) void k_gemm_fp8c(const uint8_t* __restrict__ S, const uint8_t* __restrict__ T,
                                                    float* __restrict__ P, int m, int n, int k, int64_t plane_s,
                                                    int64_t plane_t, const int32_t* __restrict__ eS,
                                                    const int32_t* __restrict__ eT, int tiles_n,

@@ -172,15 +172,17 @@ def summarize(reqs, scheduler, n_batches):
 
 class GpuExecutor:
     """Runs admitted requests on the GPU: operands N(0,1) generated on the device from the
-    request seed (A from 2 rid + 1, B from 2 rid + 2), plans cached per (N, scheme)."""
+    request seed (A from 2 rid + 1, B from 2 rid + 2), plans cached per (N, scheme); the
+    recursion depth from ``tuner`` when given, else ``levels_for``."""
 
-    def __init__(self, prec="fp8c", mode="batch", device="cuda:0", keep=None, engine="levels"):
+    def __init__(self, prec="fp8c", mode="batch", device="cuda:0", keep=None, engine="levels", tuner=None):
         import torch
         import paper_1905_07439_amd as rbc
         if mode not in ("batch", "direct"):
             raise ValueError("mode must be 'batch' or 'direct'")
         self.torch, self.rbc = torch, rbc
         self.prec, self.mode, self.device, self.engine = prec, mode, device, engine
+        self.tuner = tuner  # paper_1905_07439_amd.tune.Tuner: depth per size from timed trials
         self.streams = {}
         self.plans = {}
         self.keep = keep  # dict rid -> C (and operands) for requests to keep, or None
@@ -192,9 +194,24 @@ class GpuExecutor:
     def plan(self, r):
         key = (r.n, r.scheme)
         if key not in self.plans:
-            lv = [self.schemes[s] for s in levels_for(r.n, r.scheme)]
+            if self.tuner is not None:
+                q = self.tuner.depth_for(r.n, self.schemes[r.scheme], self.prec, r.scheme)
+                lv = [self.schemes[r.scheme]] * q
+            else:
+                lv = [self.schemes[s] for s in levels_for(r.n, r.scheme)]
             self.plans[key] = self.rbc.Plan(r.n, r.n, r.n, lv, prec=self.prec)
         return self.plans[key]
+
+    def tune(self, schemes=SCHEMES, grid=(256, 512, 1024, 2048, 4096)):
+        """Run the tuner's trials for every scheme and grid size now (before serving)."""
+        if self.tuner is None:
+            return {}
+        out = {}
+        for name in schemes:
+            for g in grid:
+                c = self.tuner.choose(g, g, g, self.schemes[name], self.prec, name, tiles=False)
+                out["%s/%d" % (name, g)] = c["levels"]
+        return out
 
     def footprint(self, r):
         return 3 * r.n * r.n * 4 + self.plan(r).workspace_bytes + (1 << 20)
