@@ -28,14 +28,18 @@ namespace {
 using tiles::doublex4;
 using tiles::F32Tile;
 
-template <int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ S,
-                                                  const float* __restrict__ T, float* __restrict__ P,
-                                                  int m, int n, int k, int tiles_n,
-                                                  int tiles_per_leaf, int64_t nblocks) {
-  __shared__ __attribute__((aligned(16))) float smem[F32Tile<BM, BN, BK>::SMEM];
-  tiles::gemm_f32_tile<BM, BN, BK>(S, T, P, m, n, k, tiles_n, tiles_per_leaf,
-                                   tiles::xcd_remap(blockIdx.x, nblocks), smem);
+// MINB workgroups per CU (register cap), EPI epilogue passes (LDS cap): chosen by
+// timing on 343 leaves of 512^3 -- 128 x 128 x 16 at 3 per CU with a 4-pass
+// epilogue (37 KB of LDS) ran 0.72 ms against 0.88 ms for 128 x 128 x 32 at
+// 1 per CU with a one-pass epilogue (69 KB of LDS: two per CU).
+template <int BM, int BN, int BK, int MINB, int EPI>
+__global__ __launch_bounds__(256, MINB) void k_gemm_f32(const float* __restrict__ S,
+                                                        const float* __restrict__ T, float* __restrict__ P,
+                                                        int m, int n, int k, int tiles_n,
+                                                        int tiles_per_leaf, int64_t nblocks) {
+  __shared__ __attribute__((aligned(16))) float smem[F32Tile<BM, BN, BK, EPI>::SMEM];
+  tiles::gemm_f32_tile<BM, BN, BK, EPI>(S, T, P, m, n, k, tiles_n, tiles_per_leaf,
+                                        tiles::xcd_remap(blockIdx.x, nblocks), smem);
 }
 
 __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ S,
@@ -68,22 +72,19 @@ hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, 
                            int64_t batch, int tile, hipStream_t stream) {
   if (batch == 0 || m == 0 || n == 0) return hipSuccess;
   if (m % tile || n % tile || k % 16 || (tile != 64 && tile != 128)) return hipErrorInvalidValue;
-  const bool deep = k % 32 == 0;  // K slabs of 32 when K allows, else 16
+  const bool deep = k % 32 == 0;  // 64-tiles: K slabs of 32 when K allows, else 16
   const int tiles_n = (int)(n / tile), tiles_per_leaf = (int)((m / tile) * tiles_n);
   const int64_t nblocks = batch * tiles_per_leaf;
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblocks), block(256);
-  if (tile == 128 && deep)
-    hipLaunchKernelGGL((k_gemm_f32<128, 128, 32>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
-                       (int)k, tiles_n, tiles_per_leaf, nblocks);
-  else if (tile == 128)
-    hipLaunchKernelGGL((k_gemm_f32<128, 128, 16>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+  if (tile == 128)
+    hipLaunchKernelGGL((k_gemm_f32<128, 128, 16, 3, 4>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
                        (int)k, tiles_n, tiles_per_leaf, nblocks);
   else if (deep)
-    hipLaunchKernelGGL((k_gemm_f32<64, 64, 32>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+    hipLaunchKernelGGL((k_gemm_f32<64, 64, 32, 4, 2>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
                        (int)k, tiles_n, tiles_per_leaf, nblocks);
   else
-    hipLaunchKernelGGL((k_gemm_f32<64, 64, 16>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
+    hipLaunchKernelGGL((k_gemm_f32<64, 64, 16, 8, 2>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
                        (int)k, tiles_n, tiles_per_leaf, nblocks);
   return hipGetLastError();
 }

@@ -28,29 +28,31 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-template <int BM, int BN, int BK>
+// EPI: the epilogue parks each wavefront's output quarter in LDS in EPI passes
+// of WM / EPI rows, so that the epilogue needs no more LDS than the K loop.
+template <int BM, int BN, int BK, int EPI = 1>
 struct F32Tile {
   static constexpr int LDA = BK + 4, LDB = BN + 4, WM = BM / 2, WN = BN / 2, LDE = WN + 4;
-  static constexpr int A_FLOATS = 2 * BM * LDA, B_FLOATS = 2 * BK * LDB, E_FLOATS = 4 * WM * LDE;
+  static constexpr int A_FLOATS = 2 * BM * LDA, B_FLOATS = 2 * BK * LDB, E_FLOATS = 4 * (WM / EPI) * LDE;
   // LDS floats: two S and two T slab buffers in the K loop, the output quarters in the epilogue
   static constexpr int SMEM = A_FLOATS + B_FLOATS > E_FLOATS ? A_FLOATS + B_FLOATS : E_FLOATS;
 };
 
 // Output tile `bid` (leaf-major, then tile row, then tile column) of the batched leaf product.
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int EPI = 1>
 __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const float* __restrict__ T,
                                               float* __restrict__ P, int m, int n, int k, int tiles_n,
                                               int tiles_per_leaf, int64_t bid, float* smem) {
-  constexpr int LDA = F32Tile<BM, BN, BK>::LDA;  // S slab row: k-contiguous, padded
-  constexpr int LDB = F32Tile<BM, BN, BK>::LDB;  // T slab row: n-contiguous, padded
+  constexpr int LDA = F32Tile<BM, BN, BK, EPI>::LDA;  // S slab row: k-contiguous, padded
+  constexpr int LDB = F32Tile<BM, BN, BK, EPI>::LDB;  // T slab row: n-contiguous, padded
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int KQ = BK / 4;                  // float4 chunks per S row of a slab
   constexpr int A_VEC = BM * KQ / 256;        // float4 loads per thread per slab
   constexpr int B_VEC = BK * (BN / 4) / 256;
-  constexpr int LDE = F32Tile<BM, BN, BK>::LDE;  // epilogue row of a wavefront's quarter
+  constexpr int LDE = F32Tile<BM, BN, BK, EPI>::LDE;  // epilogue row of a wavefront's quarter
   static_assert(A_VEC >= 1 && B_VEC >= 1, "tile too small for 256 threads");
-  constexpr int A_FLOATS = F32Tile<BM, BN, BK>::A_FLOATS;
+  constexpr int A_FLOATS = F32Tile<BM, BN, BK, EPI>::A_FLOATS;
   float(*As)[BM][LDA] = reinterpret_cast<float(*)[BM][LDA]>(smem);
   float(*Bs)[BK][LDB] = reinterpret_cast<float(*)[BK][LDB]>(smem + A_FLOATS);
 
@@ -138,25 +140,30 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
   }
 
   // Epilogue through LDS: each wavefront parks its (BM/2) x (BN/2) quarter (D layout of the
-  // 16x16 MFMA: lane holds column lane & 15, rows 4 (lane >> 4) + v), then writes it back
-  // row by row with 16-byte stores, 16 lanes per row.
-  __syncthreads();  // every wavefront is done reading the operand buffers
-  float* Es = smem + wave * WM * LDE;
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Es[(i * 16 + lg * 4 + v) * LDE + j * 16 + lr] = acc[i][j][v];
-  __syncthreads();
+  // 16x16 MFMA: lane holds column lane & 15, rows 4 (lane >> 4) + v), WM / EPI rows per
+  // pass, then writes them back row by row with 16-byte stores, 16 lanes per row.
+  static_assert(FM % EPI == 0, "epilogue passes must split the fragments evenly");
+  constexpr int FP = FM / EPI, WR = WM / EPI;  // fragments and rows per pass
+  float* Es = smem + wave * WR * LDE;
   constexpr int LPR = WN / 4;            // lanes per row (16-byte chunks)
   constexpr int RPI = 64 / LPR;          // rows per store instruction
   gbl<float>* Pw = Pl + (int64_t)(wm * WM) * n + wn * WN;
   const int er = lane / LPR, ec = (lane % LPR) * 4;
 #pragma unroll
-  for (int r0 = 0; r0 < WM; r0 += RPI) {
-    const floatx4 v = *reinterpret_cast<const floatx4*>(&Es[(r0 + er) * LDE + ec]);
-    *reinterpret_cast<gbl<floatx4>*>(Pw + (int64_t)(r0 + er) * n + ec) = v;
+  for (int ps = 0; ps < EPI; ++ps) {
+    __syncthreads();  // every wavefront is done reading the operand buffers / the previous pass
+#pragma unroll
+    for (int i = 0; i < FP; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Es[(i * 16 + lg * 4 + v) * LDE + j * 16 + lr] = acc[ps * FP + i][j][v];
+    __syncthreads();
+#pragma unroll
+    for (int r0 = 0; r0 < WR; r0 += RPI) {
+      const floatx4 v = *reinterpret_cast<const floatx4*>(&Es[(r0 + er) * LDE + ec]);
+      *reinterpret_cast<gbl<floatx4>*>(Pw + (int64_t)(ps * WR + r0 + er) * n + ec) = v;
+    }
   }
 }
 

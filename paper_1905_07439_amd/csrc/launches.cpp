@@ -78,7 +78,11 @@ enum Side { SIDE_A, SIDE_B, SIDE_C };
 // Positions per thread for a combination launch: the widest of 4, 2, 1 that
 // divides the block width, every leading dimension and block stride, and the
 // element alignment of every pointer.  8-byte accumulators use at most 2, and
-// 1 in two-level groups (register budget).
+// 1 in two-level groups (register budget).  Scatters of two or more levels use
+// at most 2: with 4, each thread's R^2 operand loads run in R dependent rounds
+// and the launch has too few wavefronts to hide them (measured: the bottom
+// scatter of three Strassen levels at N = 4096 in f32 takes 176 us with 4
+// positions per thread, 135 us with 2).
 // RBC_COMBINE_VEC (1, 2 or 4) lowers the cap for tuning.
 int max_vec_override() {
   static const int v = [] {
@@ -90,8 +94,8 @@ int max_vec_override() {
 }
 
 int pick_vec(int elt_bytes, int64_t cols, std::initializer_list<int64_t> strides,
-             std::initializer_list<const void*> ptrs, bool wide_acc, int nl) {
-  const int cap = std::min(wide_acc ? (nl >= 2 ? 1 : 2) : 4, max_vec_override());
+             std::initializer_list<const void*> ptrs, bool wide_acc, int nl, bool scatter) {
+  const int cap = std::min({wide_acc ? (nl >= 2 ? 1 : 2) : 4, scatter && nl >= 2 ? 2 : 4, max_vec_override()});
   for (int v = cap; v > 1; v /= 2) {
     bool ok = cols % v == 0;
     for (int64_t s : strides) ok = ok && s % v == 0;
@@ -210,7 +214,7 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     L.R = p.Q ? p.levels[g.d0].R : 1;
     L.nl = g.d1 - g.d0;
     L.vec = pick_vec(f64 ? 8 : 4, gp.cols_bot, {gp.ld_src, gp.src_batch, gp.dst_batch, gp.plane},
-                     {gp.src, gp.dst}, f64, L.nl);
+                     {gp.src, gp.dst}, f64, L.nl, false);
     L.elt = f64 ? ELT_F64 : ELT_F32;
     L.out = bf16_out ? OUT_BF16X2 : (f16_out ? OUT_F16S : (fp8_out ? OUT_FP8X2 : OUT_SAME));
     out.push_back(L);
@@ -261,7 +265,7 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
     L.nl = g.d1 - g.d0;
     L.br = g.b1, L.bc = g.b3;
     L.vec = pick_vec(L.to == ELT_F64 ? 8 : 4, sp.cols_bot, {sp.ld_dst, sp.dst_batch, sp.src_batch},
-                     {sp.src, sp.dst}, L.ta == ELT_F64, L.nl);
+                     {sp.src, sp.dst}, L.ta == ELT_F64, L.nl, true);
     out.push_back(L);
   }
 }
