@@ -127,6 +127,56 @@ def approx3072(args):
     print(json.dumps(out), flush=True)
 
 
+def small64(args):
+    """The small case: plain randomized Strassen in f64, N = 64, two levels (49 leaves of 16^3),
+    A, B ~ N(0,1) (seeds 1001/1002) and integers in [-4, 4] (seed 1003 for A, 1004 for B),
+    algorithm seed 0, mode full.  Launch-latency bound: per-call latency (HIP events around
+    each call) over --small-reps calls, p50 and p99, and effective TFLOP/s at the p50."""
+    import numpy as np
+    import torch
+
+    import paper_1905_07439_amd as rbc
+    import workloads
+
+    n, dev = 64, "cuda:0"
+    S = rbc.Scheme.builtin("strassen")
+    plan = rbc.Plan(n, n, n, [S, S], prec="f64")
+    A = torch.from_numpy(workloads.gaussian((n, n), 1001)).to(dev)
+    B = torch.from_numpy(workloads.gaussian((n, n), 1002)).to(dev)
+    Ai = torch.from_numpy(workloads.integers((n, n), 1003).astype(np.float64)).to(dev)
+    Bi = torch.from_numpy(workloads.integers((n, n), 1004).astype(np.float64)).to(dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev)
+    ws = plan.workspace(dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.matmul(A, B, C=C, seed=0, workspace=ws)
+    reps = args.small_reps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        plan.matmul(A, B, C=C, seed=0, workspace=ws, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])  # microseconds
+    p50 = float(np.percentile(lat, 50))
+    ref = A @ B
+    err = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
+    Ci = plan.matmul(Ai, Bi, seed=0, workspace=ws)
+    exact = bool(torch.equal(Ci, Ai @ Bi))
+    out = {"metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
+           "value": round(2.0 * n ** 3 / (p50 * 1e-6) / 1e12, 6), "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": reps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "randomized Strassen, f64, N=64, 2 levels (49 leaves of 16^3), N(0,1) and "
+                                  "integers in [-4,4], algorithm seed 0, mode full", "n": n, "levels": 2,
+                      "parallelism": "single GPU"},
+           "latency_us": {"p50": round(p50, 2), "p99": round(float(np.percentile(lat, 99)), 2),
+                          "min": round(float(lat.min()), 2)},
+           "rel_err_vs_fp64": err, "integers_exact": exact}
+    print(json.dumps(out), flush=True)
+
+
 def batch_levels(n):
     """Laderman at the top, then Strassen until the leaf side is at most 128."""
     m, s = n // 3, 0
@@ -383,7 +433,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="strassen4096",
-                    choices=["strassen4096", "approx3072", "batch512", "serve"])
+                    choices=["strassen4096", "approx3072", "batch512", "serve", "small64"])
+    ap.add_argument("--small-reps", type=int, default=1000)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-budget-gb", type=int, default=24)
@@ -401,6 +452,8 @@ def main():
         return batch512(args)
     if args.workload == "serve":
         return serve_stream(args)
+    if args.workload == "small64":
+        return small64(args)
 
     import numpy as np
     import torch

@@ -26,10 +26,14 @@ namespace batch {
 
 template <int PREC>
 struct Smem {
+  // the fp8 leaves the engine runs (96, 64, 32) have two LDS layouts
+  static constexpr size_t fp8_bytes =
+      tiles::Fp8Tile<96, 96>::SMEM_BYTES > tiles::Fp8Tile<64, 64>::SMEM_BYTES ? tiles::Fp8Tile<96, 96>::SMEM_BYTES
+                                                                             : tiles::Fp8Tile<64, 64>::SMEM_BYTES;
   static constexpr size_t bytes =
       PREC == RBC_PREC_F32    ? sizeof(float) * tiles::F32Tile<64, 64, 32>::SMEM
       : PREC == RBC_PREC_F16S ? sizeof(uint16_t) * tiles::LowpTile<tiles::LOWP_F16S, 128, 128>::SMEM_HALVES
-                              : tiles::Fp8Tile<96, 96>::SMEM_BYTES;
+                              : fp8_bytes;
 };
 
 // Most outputs per top block among the compiled gathers (f16s exponents in LDS).
