@@ -15,12 +15,17 @@
 //
 // Workgroups are dispatched round robin over the 8 XCDs; block ids are
 // remapped so that the tiles of one leaf run on the same XCD and share its L2.
+// 128-tile launches run whole rounds of the resident grid as 128-tiles and a
+// partial last round as 64-tiles (split_tail): at N = 4096, Q = 3 (5488 tiles
+// on 768 resident workgroups) that took the leaf stage from 0.86 to 0.78 ms,
+// with bitwise the same products.
 //
 // f64: v_mfma_f64_16x16x4_f64, one wavefront per 16x16 output tile, operands
 // read straight from global memory (small leaves; latency bound).
 #include <hip/hip_runtime.h>
 
 #include "gemm_tiles.hpp"
+#include "occupancy.hpp"
 
 namespace rbc {
 namespace {
@@ -32,6 +37,21 @@ using tiles::F32Tile;
 // timing on 343 leaves of 512^3 -- 128 x 128 x 16 at 3 per CU with a 4-pass
 // epilogue (37 KB of LDS) ran 0.72 ms against 0.88 ms for 128 x 128 x 32 at
 // 1 per CU with a one-pass epilogue (69 KB of LDS: two per CU).
+// 128-tiles with the last partial round as 64-tiles (split_tail).
+constexpr int kSmem128 = F32Tile<128, 128, 16, 4>::SMEM, kSmem64 = F32Tile<64, 64, 32, 2>::SMEM;
+__global__ __launch_bounds__(256, 3) void k_gemm_f32_128(const float* __restrict__ S, const float* __restrict__ T,
+                                                         float* __restrict__ P, int m, int n, int k, int tiles_n,
+                                                         int tiles_per_leaf, int64_t n_big, int64_t n_small) {
+  __shared__ __attribute__((aligned(16))) float smem[kSmem128 > kSmem64 ? kSmem128 : kSmem64];
+  int64_t bid;
+  if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid))
+    tiles::gemm_f32_tile<128, 128, 16, 4>(S, T, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem);
+  else if (k % 32 == 0)
+    tiles::gemm_f32_tile<64, 64, 32, 2>(S, T, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem);
+  else
+    tiles::gemm_f32_tile<64, 64, 16, 2>(S, T, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem);
+}
+
 template <int BM, int BN, int BK, int MINB, int EPI>
 __global__ __launch_bounds__(256, MINB) void k_gemm_f32(const float* __restrict__ S,
                                                         const float* __restrict__ T, float* __restrict__ P,
@@ -77,10 +97,11 @@ hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, 
   const int64_t nblocks = batch * tiles_per_leaf;
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblocks), block(256);
-  if (tile == 128)
-    hipLaunchKernelGGL((k_gemm_f32<128, 128, 16, 3, 4>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
-                       (int)k, tiles_n, tiles_per_leaf, nblocks);
-  else if (deep)
+  if (tile == 128) {
+    const TailSplit sp = tail_split(nblocks, resident_blocks((const void*)k_gemm_f32_128, 256));
+    hipLaunchKernelGGL(k_gemm_f32_128, dim3((unsigned)(sp.n_big + sp.n_small)), block, 0, stream, S, T, P, (int)m,
+                       (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
+  } else if (deep)
     hipLaunchKernelGGL((k_gemm_f32<64, 64, 32, 4, 2>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
                        (int)k, tiles_n, tiles_per_leaf, nblocks);
   else

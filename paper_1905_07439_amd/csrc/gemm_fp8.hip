@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gemm_tiles.hpp"
+#include "occupancy.hpp"
 
 namespace rbc {
 namespace {
@@ -20,6 +21,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm_fp8c(const uint8_t* __restrict_
   __shared__ __attribute__((aligned(16))) uint8_t smem[Fp8Tile<BM, BN>::SMEM_BYTES];
   tiles::gemm_fp8c_tile<BM, BN>(S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf,
                                 tiles::xcd_remap(blockIdx.x, nblocks), smem);
+}
+
+// 128-tiles with the last partial round as 64-tiles (split_tail; both sizes
+// use the same fragment shape, so the products are the same bits).
+constexpr int kSmem128 = Fp8Tile<128, 128>::SMEM_BYTES, kSmem64 = Fp8Tile<64, 64>::SMEM_BYTES;
+__global__ __launch_bounds__(256, 2) void k_gemm_fp8c_128(const uint8_t* __restrict__ S, const uint8_t* __restrict__ T,
+                                                          float* __restrict__ P, int m, int n, int k, int64_t plane_s,
+                                                          int64_t plane_t, const int32_t* __restrict__ eS,
+                                                          const int32_t* __restrict__ eT, int tiles_n,
+                                                          int tiles_per_leaf, int64_t n_big, int64_t n_small) {
+  __shared__ __attribute__((aligned(16))) uint8_t smem[kSmem128 > kSmem64 ? kSmem128 : kSmem64];
+  int64_t bid;
+  if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid))
+    tiles::gemm_fp8c_tile<128, 128>(S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, bid, smem);
+  else
+    tiles::gemm_fp8c_tile<64, 64>(S, T, P, m, n, k, plane_s, plane_t, eS, eT, 2 * tiles_n, 4 * tiles_per_leaf, bid,
+                                  smem);
 }
 
 template <int TILE>
@@ -43,9 +61,12 @@ hipError_t launch_gemm_fp8c(const uint8_t* S, const uint8_t* T, float* P, int64_
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   const int64_t plane_s = batch * m * k, plane_t = batch * k * n;
   const dim3 grid((unsigned)nblocks);
-  if (tile == 128)
-    launch_tile<128>(grid, stream, S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);
-  else if (tile == 96)
+  if (tile == 128) {
+    const TailSplit sp = tail_split(nblocks, resident_blocks((const void*)k_gemm_fp8c_128, 256));
+    hipLaunchKernelGGL(k_gemm_fp8c_128, dim3((unsigned)(sp.n_big + sp.n_small)), dim3(256), 0, stream, S, T, P,
+                       (int)m, (int)n, (int)k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, sp.n_big,
+                       sp.n_small);
+  } else if (tile == 96)
     launch_tile<96>(grid, stream, S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);
   else if (tile == 64)
     launch_tile<64>(grid, stream, S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);

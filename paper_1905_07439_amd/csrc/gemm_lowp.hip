@@ -8,17 +8,17 @@
 //           no value can overflow; v_mfma_f32_16x16x32_f16.  The unscaling is exact.
 //
 // Tile BM x BN (32, 64, 96 or 128) per workgroup of 4 wavefronts, each a
-// (BM/2) x (BN/2) quarter of 16x16 MFMA tiles, K slabs of 32.  Both operands
-// are staged k-contiguous in LDS so that every MFMA operand is one 16-byte LDS
-// read (8 consecutive k of one row or column): S slabs are already k-contiguous
-// in memory; T slabs are transposed on the way into LDS, four k rows at a
-// time, so each LDS store writes 8 bytes.  Two LDS buffers: a slab held in
-// registers is written to one, one barrier, then the next slab's global loads
-// stay in flight while the MFMAs consume the buffer.  Block ids are remapped
-// so that one leaf's tiles run on one XCD.
+// (BM/2) x (BN/2) quarter of 16x16 MFMA tiles, K slabs of 32 (the tile is
+// described in gemm_tiles.hpp: S operands are 16-byte LDS reads, T operands
+// transposing LDS reads).  Two LDS buffers: a slab held in registers is
+// written to one, one barrier, then the next slab's global loads stay in
+// flight while the MFMAs consume the buffer.  Block ids are remapped so that
+// one leaf's tiles run on one XCD.  128- and 64-tile launches run the partial
+// last round of the resident grid as tiles of half the side (split_tail).
 #include <hip/hip_runtime.h>
 
 #include "gemm_tiles.hpp"
+#include "occupancy.hpp"
 
 namespace rbc {
 namespace {
@@ -38,6 +38,36 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const uint16_t* __restrict__ 
                                       tiles_per_leaf, tiles::xcd_remap(blockIdx.x, nblocks), smem);
 }
 
+// Tiles of BM with the last partial round as tiles of BM / 2 (split_tail).
+template <int KIND, int BM>
+__global__ __launch_bounds__(256) void k_gemm_lowp_split(const uint16_t* __restrict__ S,
+                                                         const uint16_t* __restrict__ T, float* __restrict__ P,
+                                                         int m, int n, int k, int64_t plane_s, int64_t plane_t,
+                                                         const int32_t* __restrict__ eS,
+                                                         const int32_t* __restrict__ eT, int tiles_n,
+                                                         int tiles_per_leaf, int64_t n_big, int64_t n_small) {
+  constexpr int H = BM / 2;
+  constexpr int SB = LowpTile<KIND, BM, BM>::SMEM_HALVES, SH = LowpTile<KIND, H, H>::SMEM_HALVES;
+  __shared__ __attribute__((aligned(16))) uint16_t smem[SB > SH ? SB : SH];
+  int64_t bid;
+  if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid))
+    tiles::gemm_lowp_tile<KIND, BM, BM>(S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, bid,
+                                        smem);
+  else
+    tiles::gemm_lowp_tile<KIND, H, H>(S, T, P, m, n, k, plane_s, plane_t, eS, eT, 2 * tiles_n,
+                                      4 * tiles_per_leaf, bid, smem);
+}
+
+template <int KIND, int BM>
+void launch_split(int64_t nblocks, hipStream_t stream, const uint16_t* S, const uint16_t* T, float* P, int64_t m,
+                  int64_t n, int64_t k, int64_t plane_s, int64_t plane_t, const int32_t* eS, const int32_t* eT,
+                  int tiles_n, int tiles_per_leaf) {
+  const TailSplit sp = tail_split(nblocks, resident_blocks((const void*)k_gemm_lowp_split<KIND, BM>, 256));
+  hipLaunchKernelGGL((k_gemm_lowp_split<KIND, BM>), dim3((unsigned)(sp.n_big + sp.n_small)), dim3(256), 0, stream,
+                     S, T, P, (int)m, (int)n, (int)k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, sp.n_big,
+                     sp.n_small);
+}
+
 template <int KIND>
 hipError_t launch_lowp(const uint16_t* S, const uint16_t* T, float* P, int64_t m, int64_t n, int64_t k,
                        int64_t batch, int tile, const int32_t* eS, const int32_t* eT,
@@ -51,13 +81,11 @@ hipError_t launch_lowp(const uint16_t* S, const uint16_t* T, float* P, int64_t m
   const int64_t plane_s = batch * m * k, plane_t = batch * k * n;
   const dim3 grid((unsigned)nblocks), block(256);
   if (tile == 128)
-    hipLaunchKernelGGL((k_gemm_lowp<KIND, 128, 128>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
-                       (int)k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);
+    launch_split<KIND, 128>(nblocks, stream, S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf);
+  else if (tile == 64)
+    launch_split<KIND, 64>(nblocks, stream, S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf);
   else if (tile == 96)
     hipLaunchKernelGGL((k_gemm_lowp<KIND, 96, 96>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
-                       (int)k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);
-  else if (tile == 64)
-    hipLaunchKernelGGL((k_gemm_lowp<KIND, 64, 64>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
                        (int)k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf, nblocks);
   else
     hipLaunchKernelGGL((k_gemm_lowp<KIND, 32, 32>), grid, block, 0, stream, S, T, P, (int)m, (int)n,

@@ -29,6 +29,28 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// Launches whose tiles do not fill whole rounds of the resident grid: the
+// first n_big blocks compute full tiles (ids 0 .. n_big - 1, whole rounds),
+// the remaining blocks the last tiles split in quarters (tiles of half the
+// side), so that the last round is spread over every CU.  Every output gets
+// the same arithmetic in either tile size.  Returns true and the full-size
+// tile id for a full tile, false and the half-size tile id (leaf-major over
+// the half-size tile grid) for a quarter.
+__device__ __forceinline__ bool split_tail(int64_t b, int64_t n_big, int64_t n_small, int tiles_n,
+                                          int tiles_per_leaf, int64_t* bid) {
+  if (b < n_big) {
+    *bid = xcd_remap(b, n_big);
+    return true;
+  }
+  const int64_t sq = xcd_remap(b - n_big, n_small);
+  const int64_t big = n_big + sq / 4;
+  const int q = (int)(sq % 4);
+  const int64_t leaf = big / tiles_per_leaf;
+  const int t = (int)(big - leaf * tiles_per_leaf), tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
+  *bid = leaf * 4 * (int64_t)tiles_per_leaf + (int64_t)(2 * tm + q / 2) * (2 * tiles_n) + 2 * tn + q % 2;
+  return false;
+}
+
 // EPI: the epilogue parks each wavefront's output quarter in LDS in EPI passes
 // of WM / EPI rows, so that the epilogue needs no more LDS than the K loop.
 template <int BM, int BN, int BK, int EPI = 1>
