@@ -208,9 +208,9 @@ __device__ __forceinline__ floatx4 mfma16(u32x4 a, u32x4 b, floatx4 c) {
 // lanes, lane s reads 4 halves of k row s / 4 at column offset 4 (s % 4), and
 // lane t receives half t % 4 of the reads of lanes 4j + t / 4, j = 0..3, which
 // is column t over the 4 k rows.
-template <int KIND, int BM, int BN>
+template <int KIND, int BM, int BN, int BK_ = 32>
 struct LowpTile {
-  static constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1, BK = 32, LDK = BK + 8, LDB = BN + 16;
+  static constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1, BK = BK_, LDK = BK + 8, LDB = BN + 16;
   static constexpr int A_HALVES = NP * BM * LDK, B_HALVES = NP * BK * LDB;  // one buffer
   static constexpr int SMEM_HALVES = 2 * (A_HALVES + B_HALVES);             // two buffers
 };
@@ -222,15 +222,17 @@ __device__ __forceinline__ u32x2 lds_read_tr16(const uint16_t* p) {
   return __builtin_bit_cast(u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)(p)));
 }
 
-// Output tile `bid` of the batched reduced-precision leaf product.
-template <int KIND, int BM, int BN>
+// Output tile `bid` of the batched reduced-precision leaf product; K slabs of
+// BK (32 or 64), one MFMA k-step of 32 per 32 of the slab, in k order.
+template <int KIND, int BM, int BN, int BK_ = 32>
 __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
                                                const uint16_t* __restrict__ T, float* __restrict__ P,
                                                int m, int n, int k, int64_t plane_s, int64_t plane_t,
                                                const int32_t* __restrict__ eS,
                                                const int32_t* __restrict__ eT, int tiles_n,
                                                int tiles_per_leaf, int64_t bid, uint16_t* smem) {
-  using Tile = LowpTile<KIND, BM, BN>;
+  using Tile = LowpTile<KIND, BM, BN, BK_>;
+  static_assert(BK_ % 32 == 0, "slabs of whole MFMA k-steps");
   constexpr int NP = Tile::NP;  // operand planes (hi, lo)
   constexpr int BK = Tile::BK, LDK = Tile::LDK, LDB = Tile::LDB;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -310,39 +312,42 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
       for (int i = 0; i < B_ITER; ++i)
         rb[i] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)k1 * n);
     }
-    u32x4 ah[FM], bh[FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
-      ah[i] = *reinterpret_cast<const u32x4*>(&As[cur][0][wm * WM + i * 16 + lr][lg * 8]);
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const u32x2 lo = lds_read_tr16(&Bs[cur][0][tr_row][tr_col + j * 16]);
-      const u32x2 hi = lds_read_tr16(&Bs[cur][0][tr_row + 4][tr_col + j * 16]);
-      bh[j] = u32x4{lo[0], lo[1], hi[0], hi[1]};
-    }
-    if constexpr (NP == 2) {
-      u32x4 al[FM], bl[FN];
+    for (int kk = 0; kk < BK / 32; ++kk) {
+      u32x4 ah[FM], bh[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
-        al[i] = *reinterpret_cast<const u32x4*>(&As[cur][NP - 1][wm * WM + i * 16 + lr][lg * 8]);
+        ah[i] = *reinterpret_cast<const u32x4*>(&As[cur][0][wm * WM + i * 16 + lr][kk * 32 + lg * 8]);
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const u32x2 lo = lds_read_tr16(&Bs[cur][NP - 1][tr_row][tr_col + j * 16]);
-        const u32x2 hi = lds_read_tr16(&Bs[cur][NP - 1][tr_row + 4][tr_col + j * 16]);
-        bl[j] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        const u32x2 lo = lds_read_tr16(&Bs[cur][0][kk * 32 + tr_row][tr_col + j * 16]);
+        const u32x2 hi = lds_read_tr16(&Bs[cur][0][kk * 32 + tr_row + 4][tr_col + j * 16]);
+        bh[j] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+      }
+      if constexpr (NP == 2) {
+        u32x4 al[FM], bl[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          al[i] = *reinterpret_cast<const u32x4*>(&As[cur][NP - 1][wm * WM + i * 16 + lr][kk * 32 + lg * 8]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const u32x2 lo = lds_read_tr16(&Bs[cur][NP - 1][kk * 32 + tr_row][tr_col + j * 16]);
+          const u32x2 hi = lds_read_tr16(&Bs[cur][NP - 1][kk * 32 + tr_row + 4][tr_col + j * 16]);
+          bl[j] = u32x4{lo[0], lo[1], hi[0], hi[1]};
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc[i][j] = mfma16<KIND>(al[i], bh[j], acc[i][j]);
+            acc[i][j] = mfma16<KIND>(ah[i], bl[j], acc[i][j]);
+          }
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc[i][j] = mfma16<KIND>(al[i], bh[j], acc[i][j]);
-          acc[i][j] = mfma16<KIND>(ah[i], bl[j], acc[i][j]);
-        }
+        for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<KIND>(ah[i], bh[j], acc[i][j]);
     }
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<KIND>(ah[i], bh[j], acc[i][j]);
     cur ^= 1;
   }
 

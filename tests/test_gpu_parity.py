@@ -441,3 +441,24 @@ def test_results_are_deterministic_and_stream_ordered():
     assert torch.equal(C1, C2)
     C3 = plan.matmul(A, B, seed=6)
     assert not torch.equal(C1, C3)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s", "fp8c"])
+def test_tail_split_tiles_give_the_same_bits(prec):
+    # N = 2048, Q = 2: 49 leaves of 512^2, 784 tiles of 128 -- more than one round of the resident
+    # grid and not a whole number of rounds, so the last round runs as 64-tiles; the products must
+    # be bitwise those of the same plan on 64-tiles only (same instruction, same k order).
+    _say("tail split", prec)
+    n = 2048
+    lib_s, _ = _schemes(["strassen"] * 2)
+    big = rbc.Plan(n, n, n, lib_s, prec=prec, leaf_tile=128)
+    small = rbc.Plan(n, n, n, lib_s, prec=prec, leaf_tile=64)
+    assert big.info["tile_m"] == 128 and small.info["tile_m"] == 64
+    g = torch.Generator(device=DEV)
+    g.manual_seed(9)
+    A = torch.randn(n, n, device=DEV, generator=g)
+    B = torch.randn(n, n, device=DEV, generator=g)
+    C1 = big.matmul(A, B, seed=2)
+    C2 = small.matmul(A, B, seed=2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
