@@ -222,7 +222,7 @@ def batch512(args):
     flops = sum(2.0 * n ** 3 for n in sizes)
     traffic = sum(sum(plans16[n].traffic().values()) for n in sizes)
 
-    batch = rbc.Batch(item_budget=args.batch_budget_gb << 30)
+    batch = rbc.Batch(item_budget=args.batch_budget_gb << 30, order="depth")
     for i, n in enumerate(sizes):
         batch.add(plans16[n], As[i], Bs[i], C=Cs[i], seed=i, mode="full")
     stream = torch.cuda.Stream()
@@ -304,7 +304,7 @@ def batch512(args):
         "data": "synthetic",
         "config": {"workload": "batch of %d products, N = 96k, k ~ U{2..24}, Laderman then Strassen to "
                                "leaves 64..128, f16 leaves with per-leaf 2^e scales, one persistent launch "
-                               "in a HIP graph" % count,
+                               "in a HIP graph (queue in dependency-depth order)" % count,
                    "count": count, "effective_tflop": round(flops / 1e12, 4),
                    "item_budget_gb": args.batch_budget_gb, "parallelism": "single GPU"},
         "rel_err_vs_fp64": {"median": float(np.median(errs)), "max": float(errs.max())},

@@ -263,13 +263,13 @@ typedef struct {
   int32_t grid;        /* workgroups of the persistent kernel (0: resident maximum) */
   int32_t timeout_ms;  /* limit of one dependency wait (0: 5000) */
   int32_t trace;       /* nonzero: record per-task timestamps (rbc_batch_trace) */
-  int64_t task_bytes;  /* HBM bytes one task aims to move (0: 256 KiB) */
+  int64_t task_bytes;  /* HBM bytes one task aims to move (0: 2 MiB) */
   int64_t item_budget; /* bytes for the products' stage buffers (0: one region per product).
                         * With a budget the regions form a ring: a product reuses the
                         * bytes of earlier ones and its first tasks wait until those
                         * have finished.  Must hold the largest product's buffers. */
   int32_t mode;        /* RBC_BATCH_PERSISTENT (0) or RBC_BATCH_LEVELS (1), below */
-  int32_t reserved;
+  int32_t order;       /* persistent queue order: RBC_ORDER_PRODUCTS (0) or RBC_ORDER_DEPTH (1) */
 } rbc_batch_options;
 
 /* Execution modes of a batch.  PERSISTENT: one persistent kernel takes the tasks
@@ -279,6 +279,13 @@ typedef struct {
  * stream); timeout_ms, trace and grid do not apply.  Both give every product the
  * same bits. */
 enum { RBC_BATCH_PERSISTENT = 0, RBC_BATCH_LEVELS = 1 };
+
+/* Queue order of the persistent kernel.  PRODUCTS: each product's tasks depth
+ * first (a gather of one top block, the subtree below it, its scatter),
+ * products interleaved in chunks over `window`.  DEPTH: the same tasks sorted by
+ * their depth in the dependency graph (every stage of every product before the
+ * next stage).  Both orders are topological; results are the same bits. */
+enum { RBC_ORDER_PRODUCTS = 0, RBC_ORDER_DEPTH = 1 };
 
 typedef struct {
   int64_t n_items, n_tasks, n_counters;

@@ -301,7 +301,9 @@ TASK_KINDS = {0: "maxabs", 1: "exponents", 2: "gather", 3: "leaf", 4: "scatter",
 
 
 class Batch:
-    """Independent products run together by one persistent kernel (include/rbc.h, batches).
+    """Independent products run together (include/rbc.h, batches): one persistent kernel
+    (``mode="persistent"``, queue ``order`` "products" or "depth") or one grid per dependency
+    level (``mode="levels"``).
 
     Every product keeps the result ``Plan.matmul`` gives for the same plan,
     operands, seed and mode, bit for bit.  The batch holds references to the
@@ -310,10 +312,12 @@ class Batch:
     """
 
     def __init__(self, window=0, grid=0, timeout_ms=0, task_bytes=0, item_budget=0, trace=False,
-                 mode="persistent"):
+                 mode="persistent", order="products"):
         modes = {"persistent": 0, "levels": 1}
+        orders = {"products": 0, "depth": 1}
         opt = BatchOptions(window=window, grid=grid, timeout_ms=timeout_ms, task_bytes=task_bytes,
-                           item_budget=item_budget, trace=int(bool(trace)), mode=modes[mode])
+                           item_budget=item_budget, trace=int(bool(trace)), mode=modes[mode],
+                           order=orders[order])
         h = ctypes.c_void_p()
         check(lib().rbc_batch_create(ctypes.byref(opt), ctypes.byref(h)))
         self._h = h

@@ -35,7 +35,7 @@ class PlanInfo(ctypes.Structure):
 class BatchOptions(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("grid", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
                 ("trace", ctypes.c_int32), ("task_bytes", c_i64), ("item_budget", c_i64),
-                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):

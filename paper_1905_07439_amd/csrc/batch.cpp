@@ -71,6 +71,7 @@ struct rbc_batch_s {
   int64_t n_levels = 0;
   std::vector<int32_t> item_gate, item_done;  // per item: counters, from the last build
   std::vector<int64_t> item_first;            // per item: queue index of its first task
+  std::vector<int32_t> task_item;             // per task: its item (gates: the gated item)
   char* ws = nullptr;
   int device = -1;
   int grid = 0;
@@ -465,7 +466,7 @@ rbc_status build_items(rbc_batch_s& b, char* items_base, const std::vector<size_
   b.gparams.clear(), b.sparams.clear(), b.lparams.clear(), b.cparams.clear();
   b.cslots.clear();
   b.n_counters = 0;
-  Builder bl{b, b.opt.task_bytes > 0 ? b.opt.task_bytes : (int64_t)256 << 10};
+  Builder bl{b, b.opt.task_bytes > 0 ? b.opt.task_bytes : (int64_t)2 << 20};
   per.assign(b.items.size(), ItemTasks{});
   for (size_t i : order) {
     char* base = items_base ? items_base + offs[i] : nullptr;
@@ -476,7 +477,7 @@ rbc_status build_items(rbc_batch_s& b, char* items_base, const std::vector<size_
 }
 
 void assemble(rbc_batch_s& b, std::vector<ItemTasks>& per, const Schedule& sc) {
-  b.tasks.clear();
+  b.tasks.clear(), b.task_item.clear();
   b.item_gate.assign(per.size(), -1), b.item_done.assign(per.size(), -1), b.item_first.assign(per.size(), -1);
   for (size_t j = 0; j < per.size(); ++j) b.item_gate[j] = per[j].gate, b.item_done[j] = per[j].done;
   for (size_t j = 0; j < per.size(); ++j) {  // entry tasks wait for the previous users of the region
@@ -497,20 +498,22 @@ void assemble(rbc_batch_s& b, std::vector<ItemTasks>& per, const Schedule& sc) {
         t.wait[0] = per[d].done, t.need[0] = per[d].done_need;
         t.wait[1] = -1, t.signal = per[c.item].gate, t.count = 1;
         b.tasks.push_back(t);
+        b.task_item.push_back((int32_t)c.item);
       }
     } else {
       b.tasks.insert(b.tasks.end(), per[c.item].list.begin() + c.begin, per[c.item].list.begin() + c.end);
+      b.task_item.insert(b.task_item.end(), c.end - c.begin, (int32_t)c.item);
     }
   }
 }
 
-// RBC_BATCH_LEVELS: the depth of every task in the dependency graph (0 for a
-// task without waits, else one more than the deepest task that signals a
-// counter it waits on; signals precede waits in the queue), then one launch
-// per (depth, kind, variant) listing every piece of its tasks.
-void make_levels(rbc_batch_s& b) {
+// Depth of every task in the dependency graph: 0 for a task without waits,
+// else one more than the deepest task that signals a counter it waits on
+// (signals precede waits in the queue).  Returns the largest depth.
+int32_t task_depths(const rbc_batch_s& b, std::vector<int32_t>& level) {
   const size_t n = b.tasks.size();
-  std::vector<int32_t> clevel((size_t)b.n_counters, -1), level(n, 0);
+  std::vector<int32_t> clevel((size_t)b.n_counters, -1);
+  level.assign(n, 0);
   int32_t top = 0;
   for (size_t t = 0; t < n; ++t) {
     const Task& k = b.tasks[t];
@@ -521,6 +524,34 @@ void make_levels(rbc_batch_s& b) {
     top = std::max(top, lv);
     if (k.signal >= 0) clevel[(size_t)k.signal] = std::max(clevel[(size_t)k.signal], lv);
   }
+  return top;
+}
+
+// RBC_ORDER_DEPTH: the persistent kernel's queue sorted by dependency depth
+// (stable: queue order within a depth).  Every wait still points backwards.
+void order_by_depth(rbc_batch_s& b) {
+  std::vector<int32_t> level;
+  task_depths(b, level);
+  const size_t n = b.tasks.size();
+  std::vector<int32_t> order(n);
+  for (size_t t = 0; t < n; ++t) order[t] = (int32_t)t;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return level[(size_t)x] < level[(size_t)y]; });
+  std::vector<Task> tasks(n);
+  std::vector<int32_t> items(n);
+  for (size_t i = 0; i < n; ++i) tasks[i] = b.tasks[(size_t)order[i]], items[i] = b.task_item[(size_t)order[i]];
+  b.tasks.swap(tasks), b.task_item.swap(items);
+  b.item_first.assign(b.item_first.size(), -1);
+  for (size_t i = 0; i < n; ++i)
+    if (b.item_first[(size_t)b.task_item[i]] < 0) b.item_first[(size_t)b.task_item[i]] = (int64_t)i;
+}
+
+// RBC_BATCH_LEVELS: one launch per (dependency depth, kind, variant) listing
+// every piece of its tasks.
+void make_levels(rbc_batch_s& b) {
+  const size_t n = b.tasks.size();
+  std::vector<int32_t> level;
+  const int32_t top = task_depths(b, level);
   std::vector<int32_t> order(n);
   for (size_t t = 0; t < n; ++t) order[t] = (int32_t)t;
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
@@ -566,7 +597,9 @@ rbc_status build(rbc_batch_s& b, char* ws) {
   assemble(b, per, sc);
   if (b.tasks.size() > 0x7fffffff) return fail(RBC_EINVAL, "batch: too many tasks");
   const bool levels = b.opt.mode == RBC_BATCH_LEVELS;
+  const bool by_depth = !levels && b.opt.order == RBC_ORDER_DEPTH;
   if (levels) make_levels(b);
+  if (by_depth) order_by_depth(b);
   Layout& L = b.lay;
   L.tasks = 0;
   L.gather = align_up(L.tasks + b.tasks.size() * sizeof(Task));
@@ -584,6 +617,7 @@ rbc_status build(rbc_batch_s& b, char* ws) {
   if ((st = build_items(b, ws + L.items, sc.offs, order, per)) != RBC_OK) return st;
   assemble(b, per, sc);
   if (levels) make_levels(b);
+  if (by_depth) order_by_depth(b);
   int32_t* words = reinterpret_cast<int32_t*>(ws + L.ctl) + CTL_WORDS;
   for (size_t i = 0; i < b.cparams.size(); ++i) b.cparams[i].maxbits = reinterpret_cast<uint32_t*>(words + b.cslots[i]);
   return RBC_OK;
@@ -605,6 +639,11 @@ rbc_status rbc_batch_create(const rbc_batch_options* opt, rbc_batch* out) {
       const int mode = b->opt.mode;
       delete b;
       return fail(RBC_EINVAL, "bad batch mode %d", mode);
+    }
+    if (b->opt.order != RBC_ORDER_PRODUCTS && b->opt.order != RBC_ORDER_DEPTH) {
+      const int order = b->opt.order;
+      delete b;
+      return fail(RBC_EINVAL, "bad batch order %d", order);
     }
     *out = b;
     return RBC_OK;

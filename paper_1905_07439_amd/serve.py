@@ -253,7 +253,7 @@ class GpuExecutor:
                     self._keep(r, A, B, C)
                 batch = None
             else:
-                batch = self.rbc.Batch(mode=self.engine)
+                batch = self.rbc.Batch(mode=self.engine, order="depth")
                 for r in reqs:
                     A, B = self.operands(r)
                     _, C = batch.add(self.plan(r), A, B, seed=r.seed, mode="full")

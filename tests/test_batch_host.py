@@ -249,3 +249,39 @@ def test_batch_rejects_mixed_precision_and_unsupported_plans():
     empty = rbc.Batch()
     assert L.rbc_batch_prepare(empty._h, ctypes.c_void_p(FAKE), 1 << 30, None) == _lib.RBC_EINVAL
     assert L.rbc_batch_launch(empty._h, None, 0) == _lib.RBC_EINVAL
+
+
+@pytest.mark.parametrize("budget_factor", [0, 1.6])
+def test_depth_order_is_topological_and_sorted(budget_factor):
+    plans = [(_plan(n, names, "f16s"), i, "full") for i, (names, n) in enumerate(F16S_ITEMS * 2)]
+    biggest = max(p.workspace_bytes for p, _, _ in plans)
+    ref = _batch(plans, item_budget=int(biggest * budget_factor))
+    ref.workspace_bytes
+    b = _batch(plans, item_budget=int(biggest * budget_factor), order="depth")
+    b.workspace_bytes
+    t0, t1 = ref.task_table(), b.task_table()
+    assert len(t0) == len(t1)
+    # the same tasks, reordered
+    key = lambda t: (int(t["kind"]), int(t["variant"]), int(t["param"]), int(t["signal"]), int(t["first"]),
+                     int(t["count"]), int(t["sub"]), tuple(int(w) for w in t["wait"]))
+    assert sorted(map(key, t0)) == sorted(map(key, t1))
+    _simulate(t1, b.info()["n_counters"])
+    _coverage(t1)
+    depth, clevel = [], {}
+    for t in t1:
+        lv = max([clevel[int(w)] + 1 for w in t["wait"] if w >= 0] + [0])
+        depth.append(lv)
+        if t["signal"] >= 0:
+            clevel[int(t["signal"])] = max(clevel.get(int(t["signal"]), -1), lv)
+    assert depth == sorted(depth)
+    for i in range(len(plans)):
+        first = b.item(i)["first_task"]
+        assert 0 <= first < len(t1)
+
+
+def test_bad_order_rejected():
+    with pytest.raises(rbc.RbcError):
+        L = rbc.lib()
+        opt = _lib.BatchOptions(order=7)
+        h = ctypes.c_void_p()
+        _lib.check(L.rbc_batch_create(ctypes.byref(opt), ctypes.byref(h)))

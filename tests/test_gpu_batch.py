@@ -92,10 +92,11 @@ def _alone(items):
     return out
 
 
-@pytest.mark.parametrize("mode", ["persistent", "levels"])
+@pytest.mark.parametrize("engine", ["persistent", "persistent-depth", "levels"])
 @pytest.mark.parametrize("prec,specs", [("f32", F32_SPECS), ("f16s", F16S_SPECS), ("fp8c", FP8C_SPECS)])
-def test_batch_equals_alone_bitwise(prec, specs, mode):
-    b, items = _build(prec, specs, "gauss", mode=mode)
+def test_batch_equals_alone_bitwise(prec, specs, engine):
+    opt = {"persistent": {}, "persistent-depth": {"order": "depth"}, "levels": {"mode": "levels"}}[engine]
+    b, items = _build(prec, specs, "gauss", **opt)
     _say("batch", prec, b.info())
     b.prepare()
     b.launch()
@@ -128,7 +129,8 @@ def test_batch_options_ring_and_graph_replays():
     biggest = max(it[0].workspace_bytes for it in items)
     for opt in (dict(window=1), dict(window=8, task_bytes=1 << 16),
                 dict(item_budget=int(biggest * 1.6), window=3), dict(mode="levels"),
-                dict(mode="levels", item_budget=int(biggest * 1.6))):
+                dict(mode="levels", item_budget=int(biggest * 1.6)),
+                dict(order="depth", item_budget=int(biggest * 1.6), task_bytes=1 << 18)):
         b, its = _build("f16s", F16S_SPECS, "gauss", reps=2, **opt)
         _say("options", opt, b.info())
         b.prepare()
