@@ -34,7 +34,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 def _kernel_source_hash():
     """Hash of the sources the f32 leaf GEMM is compiled from."""
     h = hashlib.sha256()
-    for f in ("gemm.hip", "gemm_tiles.hpp", "devptr.hpp", "kernels.hpp"):
+    for f in ("gemm.hip", "gemm_tiles.hpp", "occupancy.hpp", "devptr.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_1905_07439_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
