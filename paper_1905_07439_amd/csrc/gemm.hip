@@ -4,14 +4,16 @@
 //
 // f32: v_mfma_f32_16x16x4_f32.  A workgroup of 4 wavefronts computes a BM x BN
 // tile (BM = BN = 64 or 128), each wavefront a (BM/2) x (BN/2) quarter as a
-// grid of 16x16 MFMA tiles.  K advances in slabs of 32 (16 when K is not a
-// multiple of 32) through two LDS buffers: a slab held in registers is
-// written to one buffer, one barrier, then the next slab's global loads are
-// issued and stay in flight while the MFMAs consume the buffer.  Both slabs
-// keep their memory layout in LDS (16-byte stores): the k order inside each
-// group of 16 is permuted identically for both operands so that an S operand
-// is one 16-byte LDS read per four MFMA steps; S rows are padded to 36 words
-// and T rows to BN + 4, which spreads each read over all banks.
+// grid of 16x16 MFMA tiles.  K advances in slabs (16 for 128-tiles; 32 for
+// 64-tiles when K is a multiple of 32, else 16) through two LDS buffers: a
+// slab held in registers is written to one buffer, one barrier, then the next
+// slab's global loads are issued and stay in flight while the MFMAs consume
+// the buffer.  Both slabs keep their memory layout in LDS (16-byte stores):
+// the k order inside each group of 16 is permuted identically for both
+// operands so that an S operand is one 16-byte LDS read per four MFMA steps;
+// S rows are padded to BK + 4 words and T rows to BN + 4, which spreads each
+// read over all banks.  The slab depth does not change any product's bits
+// (the MFMA chain runs over the same k order).
 //
 // Workgroups are dispatched round robin over the 8 XCDs; block ids are
 // remapped so that the tiles of one leaf run on the same XCD and share its L2.
