@@ -42,11 +42,33 @@ __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * i
 
 // Folded coefficient of block (k, l) in product r: table entry at the permuted
 // block times the two signs (eq. randomized-algorithm).
-template <typename T, int BC>
+// A folded coefficient of one level (the same value for every lane).  With
+// UNIFORM the index is made uniform and the read-only table is read through the
+// constant address space, so the coefficients arrive by scalar loads instead
+// of waited vector loads.  Used for every scatter level whose product loop is
+// not unrolled and for a gather's innermost level when its loop is not
+// unrolled (Laderman's 23 products): at N = 4096, Laderman Q = 2, f32, the
+// gathers went from 230 to 202 us and the scatter from 410 to 225 us, and the
+// Strassen scatters from 130 to 118 us (Q = 3) and 223 to 195 us (Q = 4).  A
+// Strassen gather's outer level keeps the vector loads (the scalar form there
+// was 2-3% slower).
+template <typename T, int BC, bool UNIFORM>
 __device__ __forceinline__ T coef(const SideLevel& L, int k, int l, int r, int R) {
-  const gbl<const T>* tab = global_ptr(static_cast<const T*>(L.tab));
-  const T c = tab[(L.pr[k] * BC + L.pc[l]) * R + r];
-  return (L.sr[k] * L.sc[l] < 0) ? -c : c;
+  if constexpr (UNIFORM) {
+    typedef __attribute__((address_space(4))) const T ctab_t;
+    const uint64_t a = reinterpret_cast<uintptr_t>(L.tab);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const ctab_t* tab = (const ctab_t*)(((uint64_t)hi << 32) | lo);
+    const int idx = __builtin_amdgcn_readfirstlane((L.pr[k] * BC + L.pc[l]) * R + r);
+    const int sg = __builtin_amdgcn_readfirstlane(L.sr[k] * L.sc[l]);
+    const T c = tab[idx];
+    return sg < 0 ? -c : c;
+  } else {
+    const gbl<const T>* tab = global_ptr(static_cast<const T*>(L.tab));
+    const T c = tab[(L.pr[k] * BC + L.pc[l]) * R + r];
+    return (L.sr[k] * L.sc[l] < 0) ? -c : c;
+  }
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -165,7 +187,7 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
       bool first = true;
 #pragma unroll
       for (int kl = 0; kl < BB; ++kl) {
-        const T c = coef<T, BC>(L, kl / BC, kl % BC, r, RR);
+        const T c = coef<T, BC, UNR == 1 && LT + 1 == NL>(L, kl / BC, kl % BC, r, RR);
         const bool nz = c != T(0);
 #pragma unroll
         for (int j = 0; j < SUB; ++j) {
@@ -281,7 +303,7 @@ __device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t 
       scatter_level<TP, TA, V, NL, BR, BC, R, LT + 1>(src, src_batch, off, lev, idx * RR + r, sub);
 #pragma unroll
       for (int ij = 0; ij < BB; ++ij) {
-        const TA c = coef<TA, BC>(L, ij / BC, ij % BC, r, RR);
+        const TA c = coef<TA, BC, UNR == 1>(L, ij / BC, ij % BC, r, RR);
         const bool nz = c != TA(0);
 #pragma unroll
         for (int j = 0; j < SUB; ++j) {
