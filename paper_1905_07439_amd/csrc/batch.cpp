@@ -199,6 +199,9 @@ struct Builder {
     std::vector<GatherLaunch> gA, gB;
     build_gather(p, dr, 0, it.A, it.lda, item_ws, scA, gA);
     build_gather(p, dr, 1, it.B, it.ldb, item_ws, scB, gB);
+    // the engine derives the exponents in its own tasks (max|X|, exponents) before the gathers
+    for (GatherLaunch& l : gA) l.p.scale_partial = nullptr;
+    for (GatherLaunch& l : gB) l.p.scale_partial = nullptr;
     const LeafLaunch lf = build_leaf(p, item_ws);
     std::vector<ScatterLaunch> sc;  // deepest group first
     build_scatter(p, dr, it.kappa_scale != 0, it.C, it.ldc, item_ws, sc);

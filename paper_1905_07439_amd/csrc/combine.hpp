@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "devptr.hpp"
+#include "scale.hpp"
 #include "kernels.hpp"
 
 #pragma clang fp contract(off)
@@ -209,14 +210,32 @@ constexpr int group_outputs() {
   return R ? ipow(R, NL) : kMaxR;
 }
 
-// f16s: copy the scale exponents of top block `in`'s outputs into LDS (every
-// thread of the workgroup calls this; it ends with a barrier).  Each output
-// block's exponent is then one LDS read instead of a dependent global load.
+// f16s, fp8: the scale exponents of top block `in`'s outputs into LDS (every
+// thread of the workgroup calls this; it ends with a barrier), so that each
+// output block's exponent is one LDS read.  With p.scale_partial the exponents
+// are derived here, e = floor(log2(target / (G max|X|))) from the partial
+// maxima of |X| and the per-leaf path norms, and the workgroup with `writer`
+// set also stores them for the leaf product; otherwise they are read from
+// p.scale_exp.
 template <int NL, int R>
-__device__ __forceinline__ void load_exponents(const GatherParams& p, int64_t in, int32_t* lds) {
+__device__ __forceinline__ void load_exponents(const GatherParams& p, int64_t in, int32_t* lds,
+                                               bool writer = false) {
   const int n = R ? ipow(R, NL) : p.lev[0].R;
-  const gbl<const int32_t>* e = global_ptr(p.scale_exp) + in * n;
-  for (int j = threadIdx.x; j < n; j += 256) lds[j] = e[j];
+  if (p.scale_partial) {
+    float m = 0.f;
+    for (int i = threadIdx.x; i < p.scale_nparts; i += 256) m = fmaxf(m, global_ptr(p.scale_partial)[i]);
+    const float mx = scale::block_max(m);
+    const gbl<const float>* G = global_ptr(p.scale_G) + in * n;
+    gbl<int32_t>* e = global_ptr(p.scale_exp) + in * n;
+    for (int j = threadIdx.x; j < n; j += 256) {
+      const int32_t x = scale::leaf_exponent(mx, G[j], p.scale_target);
+      lds[j] = x;
+      if (writer) e[j] = x;
+    }
+  } else {
+    const gbl<const int32_t>* e = global_ptr(p.scale_exp) + in * n;
+    for (int j = threadIdx.x; j < n; j += 256) lds[j] = e[j];
+  }
   __syncthreads();
 }
 
@@ -267,7 +286,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherParams p) {
     __shared__ int32_t exps[group_outputs<NL, R>()];
     for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
       if (in != blockIdx.y) __syncthreads();  // the previous block's readers are done
-      load_exponents<NL, R>(p, in, exps);
+      load_exponents<NL, R>(p, in, exps, blockIdx.x == 0);
       gather_block<T, OUTF, V, NL, BR, BC, R>(p, blockIdx.x, in, exps);
     }
   } else {

@@ -26,7 +26,14 @@ struct GatherParams {
   int64_t rows_bot, cols_bot;  // bottom block size
   int64_t dst_batch;   // elements between consecutive bottom blocks
   int64_t plane;       // bf16x2 / fp8x2 output: elements between the hi and lo planes
-  const int32_t* scale_exp;  // f16s / fp8 output: power-of-two exponent per bottom block
+  int32_t* scale_exp;   // f16s / fp8 output: power-of-two exponent per bottom block
+  // Stand-alone path: the gather derives those exponents itself from the
+  // partial maxima of |X| and the per-leaf path norms (writing them to
+  // scale_exp for the leaf product); null when scale_exp is filled beforehand.
+  const float* scale_partial;
+  const float* scale_G;
+  int32_t scale_nparts;
+  float scale_target;
   int64_t n_in;
   SideLevel lev[kMaxGroupLevels];
 };
@@ -76,10 +83,17 @@ hipError_t launch_gemm_fp8c(const uint8_t* S, const uint8_t* T, float* P, int64_
 hipError_t launch_accumulate(double* acc, const void* x, Elt elt, int64_t rows, int64_t cols, int64_t ldx,
                              int first, hipStream_t s);
 hipError_t launch_scale_f64(double* acc, int64_t n, double scale, hipStream_t s);
-// Partial maxima of |X| (at most kScalePartials floats at `partial`, overwritten),
-// then e[l] = floor(log2(target / (G[l] max|X|))) for every leaf.
+// Partial maxima of |X|: maxabs_blocks(rows, cols) floats at `partial`
+// (overwritten), at most kScalePartials.  The gather of the leaf operands
+// reduces them and derives the per-leaf exponents.
 constexpr int kScalePartials = 1024;
-hipError_t launch_leaf_scales(const float* X, int64_t ld, int64_t rows, int64_t cols, float* partial,
-                              const float* G, int32_t* e, int64_t n_leaves, float target, hipStream_t s);
+inline int maxabs_blocks(int64_t rows, int64_t cols) {
+  // at least 32 KB of X per workgroup, at most kScalePartials workgroups
+  int64_t b = (rows * cols + 8191) / 8192;
+  if (b > kScalePartials) b = kScalePartials;
+  if (b > rows) b = rows;
+  return (int)(b < 1 ? 1 : b);
+}
+hipError_t launch_maxabs(const float* X, int64_t ld, int64_t rows, int64_t cols, float* partial, hipStream_t s);
 
 }  // namespace rbc

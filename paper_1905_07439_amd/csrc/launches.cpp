@@ -208,6 +208,12 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     const bool fp8_out = last && p.prec == RBC_PREC_FP8C;
     gp.plane = (bf16_out || fp8_out) ? (int64_t)p.n_leaves * gp.rows_bot * gp.cols_bot : 0;
     gp.scale_exp = (f16_out || fp8_out) ? exps : nullptr;
+    gp.scale_partial = nullptr, gp.scale_G = nullptr, gp.scale_nparts = 0, gp.scale_target = 0.f;
+    if (f16_out || fp8_out) {  // the exponents are derived by this gather (load_exponents)
+      const ScaleLaunch& sl = scale[0];
+      gp.scale_partial = sl.partial, gp.scale_G = sl.G, gp.scale_target = sl.target;
+      gp.scale_nparts = maxabs_blocks(sl.rows, sl.cols);
+    }
     for (int d = g.d0; d < g.d1; ++d)
       fill_side(p, dr, d, which == 0 ? SIDE_A : SIDE_B, f64, false, gp.lev[d - g.d0]);
     L.br = which == 0 ? g.b1 : g.b2, L.bc = which == 0 ? g.b2 : g.b3;
@@ -271,7 +277,7 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
 }
 
 hipError_t launch(const ScaleLaunch& l, hipStream_t s) {
-  return launch_leaf_scales(l.X, l.ld, l.rows, l.cols, l.partial, l.G, l.e, l.n_leaves, l.target, s);
+  return launch_maxabs(l.X, l.ld, l.rows, l.cols, l.partial, s);
 }
 
 hipError_t launch(const GatherLaunch& l, hipStream_t s) {

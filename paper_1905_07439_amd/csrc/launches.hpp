@@ -23,7 +23,7 @@ rbc_status check_ws(const Plan& p, void* ws, size_t bytes);
 // Upload the coefficient tables of every level on first use on a device.
 rbc_status ensure_device(Plan& p);
 
-struct ScaleLaunch {  // f16s, fp8c: max|X| and the per-leaf exponents of one operand
+struct ScaleLaunch {  // f16s, fp8c: partial maxima of |X| (launch), per-leaf exponent inputs
   const float* X;
   int64_t ld, rows, cols;
   float* partial;  // kScalePartials partial maxima
