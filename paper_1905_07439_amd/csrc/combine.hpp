@@ -280,8 +280,11 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, 
   gather_level<T, V, NL, BR, BC, R, 0>(v, p.lev, in, e);
 }
 
+// f16 outputs: held to 128 VGPRs (four workgroups per CU) without spills; at
+// N = 4096, Q = 2 the f16 gather went from 60 to 51 us.  The e4m3 emission
+// spills at that bound, and two positions per thread were slower (71 us).
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
-__global__ __launch_bounds__(256) void k_gather(GatherParams p) {
+__global__ __launch_bounds__(256, OUTF == OUT_F16S ? 4 : 1) void k_gather(GatherParams p) {
   if constexpr (OUTF == OUT_F16S || OUTF == OUT_FP8X2) {
     __shared__ int32_t exps[group_outputs<NL, R>()];
     for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
