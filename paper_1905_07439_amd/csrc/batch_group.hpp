@@ -43,12 +43,14 @@ __global__ __launch_bounds__(256) void k_group_gather(GroupArgs a) {
   int32_t piece;
   const Task& task = group_task(a, &piece);
   const GatherParams& p = a.gather[task.param];
+  __shared__ float ct[comb::gather_coef_entries<float, G.out, G.nl, G.br, G.bc, G.R>()];
+  comb::stage_gather_coefs<float, G.out, G.nl, G.br, G.bc, G.R>(p.lev, ct);
   if constexpr (G.out == OUT_F16S || G.out == OUT_FP8X2) {
     __shared__ int32_t exps[comb::group_outputs<G.nl, G.R>()];
     comb::load_exponents<G.nl, G.R>(p, task.sub, exps);
-    comb::gather_block<float, G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, piece, task.sub, exps);
+    comb::gather_block<float, G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, ct, piece, task.sub, exps);
   } else {
-    comb::gather_block<float, G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, piece, task.sub, nullptr);
+    comb::gather_block<float, G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, ct, piece, task.sub, nullptr);
   }
 }
 
@@ -57,7 +59,10 @@ __global__ __launch_bounds__(256) void k_group_scatter(GroupArgs a) {
   constexpr CombVariant S = kScatters[I];
   int32_t piece;
   const Task& task = group_task(a, &piece);
-  comb::scatter_block<float, float, float, S.vec, S.nl, S.br, S.bc, S.R>(a.scatter[task.param], piece, task.sub);
+  const ScatterParams& p = a.scatter[task.param];
+  __shared__ float ct[comb::scatter_coef_entries<float, S.nl, S.br, S.bc, S.R>()];
+  comb::stage_scatter_coefs<float, S.nl, S.br, S.bc, S.R>(p.lev, ct);
+  comb::scatter_block<float, float, float, S.vec, S.nl, S.br, S.bc, S.R>(p, ct, piece, task.sub);
 }
 
 template <int I>

@@ -48,6 +48,22 @@ constexpr int max_gather_outputs() {
 }
 constexpr int kMaxGatherOutputs = max_gather_outputs();
 
+// Most staged coefficients among the compiled gathers and scatters.
+template <int I>
+constexpr int max_coef_entries() {
+  if constexpr (I < kNumGathers + kNumScatters) {
+    constexpr bool g = I < kNumGathers;
+    constexpr CombVariant v = g ? kGathers[I] : kScatters[I - kNumGathers];
+    constexpr int e = g ? comb::gather_coef_entries<float, v.out, v.nl, v.br, v.bc, v.R>()
+                        : comb::scatter_coef_entries<float, v.nl, v.br, v.bc, v.R>();
+    constexpr int rest = max_coef_entries<I + 1>();
+    return e > rest ? e : rest;
+  } else {
+    return 1;
+  }
+}
+constexpr int kMaxCoefEntries = max_coef_entries<0>();
+
 template <int PREC>
 constexpr bool gather_in(const CombVariant& v) {
   return v.out == OUT_SAME || (PREC == RBC_PREC_F16S && v.out == OUT_F16S) ||
@@ -56,14 +72,20 @@ constexpr bool gather_in(const CombVariant& v) {
 
 template <int OUTF, int V, int NL, int BR, int BC, int R>
 __device__ __forceinline__ void gather_task(const GatherParams& p, int64_t first, int count, int64_t in,
-                                            int32_t* exps) {
+                                            int32_t* exps, float* ct) {
+  static_assert(comb::gather_coef_entries<float, OUTF, NL, BR, BC, R>() <= kMaxCoefEntries, "staging too small");
+  comb::stage_gather_coefs<float, OUTF, NL, BR, BC, R>(p.lev, ct);
   if constexpr (OUTF == OUT_F16S || OUTF == OUT_FP8X2) comb::load_exponents<NL, R>(p, in, exps);
-  for (int c = 0; c < count; ++c) comb::gather_block<float, OUTF, V, NL, BR, BC, R>(p, first + c, in, exps);
+  for (int c = 0; c < count; ++c) comb::gather_block<float, OUTF, V, NL, BR, BC, R>(p, ct, first + c, in, exps);
 }
 
 template <int V, int NL, int BR, int BC, int R>
-__device__ __forceinline__ void scatter_task(const ScatterParams& p, int64_t first, int count, int64_t o) {
-  for (int c = 0; c < count; ++c) comb::scatter_block<float, float, float, V, NL, BR, BC, R>(p, first + c, o);
+__device__ __forceinline__ void scatter_task(const ScatterParams& p, int64_t first, int count, int64_t o,
+                                             float* ct) {
+  static_assert(comb::scatter_coef_entries<float, NL, BR, BC, R>() <= kMaxCoefEntries, "staging too small");
+  comb::stage_scatter_coefs<float, NL, BR, BC, R>(p.lev, ct);
+  for (int c = 0; c < count; ++c)
+    comb::scatter_block<float, float, float, V, NL, BR, BC, R>(p, ct, first + c, o);
 }
 
 template <int PREC, int TILE, int BK>
@@ -88,23 +110,23 @@ __device__ __forceinline__ void leaf_task(const LeafDesc& d, int64_t first, int 
 
 template <int PREC, int I>
 __device__ __forceinline__ void run_gather(int v, const GatherParams& p, int64_t first, int count,
-                                           int64_t in, int32_t* exps) {
+                                           int64_t in, int32_t* exps, float* ct) {
   if constexpr (I < kNumGathers) {
     constexpr CombVariant G = kGathers[I];
     if constexpr (gather_in<PREC>(G)) {
-      if (v == I) return gather_task<G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, first, count, in, exps);
+      if (v == I) return gather_task<G.out, G.vec, G.nl, G.br, G.bc, G.R>(p, first, count, in, exps, ct);
     }
-    run_gather<PREC, I + 1>(v, p, first, count, in, exps);
+    run_gather<PREC, I + 1>(v, p, first, count, in, exps, ct);
   }
 }
 
 template <int I>
 __device__ __forceinline__ void run_scatter(int v, const ScatterParams& p, int64_t first, int count,
-                                            int64_t o) {
+                                            int64_t o, float* ct) {
   if constexpr (I < kNumScatters) {
     constexpr CombVariant S = kScatters[I];
-    if (v == I) return scatter_task<S.vec, S.nl, S.br, S.bc, S.R>(p, first, count, o);
-    run_scatter<I + 1>(v, p, first, count, o);
+    if (v == I) return scatter_task<S.vec, S.nl, S.br, S.bc, S.R>(p, first, count, o, ct);
+    run_scatter<I + 1>(v, p, first, count, o, ct);
   }
 }
 
@@ -198,6 +220,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
   __shared__ int32_t s_task;
   __shared__ int32_t s_ok;
   __shared__ int32_t s_exps[kMaxGatherOutputs];
+  __shared__ float s_coef[kMaxCoefEntries];
   for (;;) {
     leader_pop(ctl, n_tasks, &s_task);
     __syncthreads();
@@ -224,13 +247,13 @@ __global__ __launch_bounds__(256, 2) void k_batch(const Task* __restrict__ tasks
         break;
       }
       case TK_GATHER:
-        run_gather<PREC, 0>(task.variant, gather[task.param], task.first, task.count, task.sub, s_exps);
+        run_gather<PREC, 0>(task.variant, gather[task.param], task.first, task.count, task.sub, s_exps, s_coef);
         break;
       case TK_LEAF:
         run_leaf<PREC, 0>(task.variant, leaf[task.param], task.first, task.count, smem);
         break;
       case TK_SCATTER:
-        run_scatter<0>(task.variant, scatter[task.param], task.first, task.count, task.sub);
+        run_scatter<0>(task.variant, scatter[task.param], task.first, task.count, task.sub, s_coef);
         break;
       default:
         break;

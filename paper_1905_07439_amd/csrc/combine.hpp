@@ -42,18 +42,12 @@ namespace comb {
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 // Folded coefficient of block (k, l) in product r: table entry at the permuted
-// block times the two signs (eq. randomized-algorithm).
-// A folded coefficient of one level (the same value for every lane).  With
-// UNIFORM the index is made uniform and the read-only table is read through the
-// constant address space, so the coefficients arrive by scalar loads instead
-// of waited vector loads.  Used for every scatter level whose product loop is
-// not unrolled and for a gather's innermost level when its loop is not
-// unrolled (Laderman's 23 products): at N = 4096, Laderman Q = 2, f32, the
-// gathers went from 230 to 202 us and the scatter from 410 to 225 us, and the
-// Strassen scatters from 130 to 118 us (Q = 3) and 223 to 195 us (Q = 4).  A
-// Strassen gather's outer level keeps the vector loads (the scalar form there
-// was 2-3% slower).
-template <typename T, int BC, bool UNIFORM>
+// block times the two signs (eq. randomized-algorithm).  With UNIFORM (the
+// same value for every lane) the index is made uniform and the read-only
+// table is read through the constant address space, so the coefficient
+// arrives by a scalar load instead of a waited vector load: the Strassen
+// scatters' looped level went from 130 to 118 us (N = 4096, Q = 3, f32).
+template <typename T, int BC, bool UNIFORM = false>
 __device__ __forceinline__ T coef(const SideLevel& L, int k, int l, int r, int R) {
   if constexpr (UNIFORM) {
     typedef __attribute__((address_space(4))) const T ctab_t;
@@ -70,6 +64,77 @@ __device__ __forceinline__ T coef(const SideLevel& L, int k, int l, int r, int R
     const T c = tab[(L.pr[k] * BC + L.pc[l]) * R + r];
     return (L.sr[k] * L.sc[l] < 0) ? -c : c;
   }
+}
+
+// Levels [0, NS) of a group read their folded coefficients from a table staged
+// in LDS once per workgroup (stage_coefs) instead of from the level's table in
+// global memory.  A level's product loop is unrolled when R is compiled in, at
+// most 8, and the level is the group's last; the rest loop over r.  Measured
+// at N = 4096 unless stated:
+//  - f64 (latency-bound sizes): every level staged; N = 64, two Strassen
+//    levels, the whole product went from 67 to 51 us.
+//  - R not compiled in or above 8 (Laderman's 23): every level staged; f32
+//    Laderman Q = 2 scatter 224 -> 199 us, fp8 gathers 211 -> 188 us, f16
+//    gathers (N = 2048) 79 -> 64 us, a whole fp8 product at N = 384 86 -> 56 us.
+//  - Strassen, gathers to reduced-precision leaf operands: the looped outer
+//    level staged (fp8, Q = 2: 77 -> 73-75 us).
+//  - Strassen f32 gathers and scatters: nothing staged (the outer gather
+//    level staged was 128 -> 131 us at Q = 3, the scatter 117 -> 125 us);
+//    the scatter's looped level reads by scalar loads.
+template <typename T, int NL, int R>
+constexpr bool stage_all() {
+  return sizeof(T) == 8 || R == 0 || R > 8;
+}
+template <typename T, int OUTF, int NL, int R>
+constexpr int gather_staged() {
+  return stage_all<T, NL, R>() ? NL : (OUTF != OUT_SAME && NL > 1 ? NL - 1 : 0);
+}
+template <typename T, int NL, int R>
+constexpr int scatter_staged() {
+  return stage_all<T, NL, R>() ? NL : 0;
+}
+
+// The staged coefficients of levels [0, NS) in LDS as [level][block kl][product
+// r], r < R (kMaxR for a level whose count is not compiled in; entries past the
+// level's count are zero).
+template <int NS, int BB, int R>
+constexpr int coef_entries() {
+  return NS ? NS * BB * (R ? R : kMaxR) : 1;  // one unused entry when nothing is staged
+}
+
+// Every thread of the workgroup calls this; it ends with a barrier when it
+// stages anything.
+template <typename T, int NS, int BR, int BC, int R>
+__device__ __forceinline__ void stage_coefs(const SideLevel* lev, T* lds) {
+  constexpr int BB = BR * BC, RM = R ? R : kMaxR;
+  if constexpr (NS > 0) {
+    for (int i = threadIdx.x; i < NS * BB * RM; i += 256) {
+      const int lt = i / (BB * RM), rem = i - lt * (BB * RM), kl = rem / RM, r = rem - kl * RM;
+      const SideLevel& L = lev[lt];
+      const int RR = R ? R : L.R;
+      lds[i] = r < RR ? coef<T, BC>(L, kl / BC, kl % BC, r, RR) : T(0);
+    }
+    __syncthreads();
+  }
+}
+
+// The staging of one gather or scatter variant (callers declare
+// coef_entries floats of LDS and stage them before the first block).
+template <typename T, int OUTF, int NL, int BR, int BC, int R>
+constexpr int gather_coef_entries() {
+  return coef_entries<gather_staged<T, OUTF, NL, R>(), BR * BC, R>();
+}
+template <typename T, int NL, int BR, int BC, int R>
+constexpr int scatter_coef_entries() {
+  return coef_entries<scatter_staged<T, NL, R>(), BR * BC, R>();
+}
+template <typename T, int OUTF, int NL, int BR, int BC, int R>
+__device__ __forceinline__ void stage_gather_coefs(const SideLevel* lev, T* lds) {
+  stage_coefs<T, gather_staged<T, OUTF, NL, R>(), BR, BC, R>(lev, lds);
+}
+template <typename T, int NL, int BR, int BC, int R>
+__device__ __forceinline__ void stage_scatter_coefs(const SideLevel* lev, T* lds) {
+  stage_coefs<T, scatter_staged<T, NL, R>(), BR, BC, R>(lev, lds);
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -165,8 +230,8 @@ struct GatherEmit {
 // block (k, l) of this level occupying the SUB consecutive values at
 // (k * BC + l) * SUB.  R > 0 is the compiled product count, R == 0 reads it
 // from the level descriptor.
-template <typename T, int V, int NL, int BR, int BC, int R, int LT, typename Emit>
-__device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLevel* lev, int64_t idx,
+template <typename T, int V, int NL, int BR, int BC, int R, int NS, int LT, typename Emit>
+__device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLevel* lev, const T* ct, int64_t idx,
                                              const Emit& emit) {
   if constexpr (LT == NL) {
     emit(idx, v[0]);
@@ -188,7 +253,9 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
       bool first = true;
 #pragma unroll
       for (int kl = 0; kl < BB; ++kl) {
-        const T c = coef<T, BC, UNR == 1 && LT + 1 == NL>(L, kl / BC, kl % BC, r, RR);
+        T c;
+        if constexpr (LT < NS) c = ct[(LT * BB + kl) * (R ? R : kMaxR) + r];
+        else c = coef<T, BC>(L, kl / BC, kl % BC, r, RR);
         const bool nz = c != T(0);
 #pragma unroll
         for (int j = 0; j < SUB; ++j) {
@@ -198,7 +265,7 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
         }
         first = first && !nz;
       }
-      gather_level<T, V, NL, BR, BC, R, LT + 1>(acc, lev, idx * RR + r, emit);
+      gather_level<T, V, NL, BR, BC, R, NS, LT + 1>(acc, lev, ct, idx * RR + r, emit);
     }
   }
 }
@@ -244,7 +311,7 @@ __device__ __forceinline__ void load_exponents(const GatherParams& p, int64_t in
 // engine's persistent kernel.  exps: for f16s outputs, top block `in`'s
 // exponents in LDS (load_exponents).
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
-__device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, int64_t in,
+__device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct, int64_t bx, int64_t in,
                                              const int32_t* exps) {
   constexpr int BB = BR * BC;
   constexpr int NSRC = ipow(BB, NL);
@@ -277,7 +344,7 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, 
   }
   const int64_t n_out = R ? ipow(R, NL) : p.lev[0].R;
   GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, exps, in * n_out};
-  gather_level<T, V, NL, BR, BC, R, 0>(v, p.lev, in, e);
+  gather_level<T, V, NL, BR, BC, R, gather_staged<T, OUTF, NL, R>(), 0>(v, p.lev, ct, in, e);
 }
 
 // f16 outputs: held to 128 VGPRs (four workgroups per CU) without spills; at
@@ -285,24 +352,26 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, int64_t bx, 
 // spills at that bound, and two positions per thread were slower (71 us).
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
 __global__ __launch_bounds__(256, OUTF == OUT_F16S ? 4 : 1) void k_gather(GatherParams p) {
+  __shared__ T ct[gather_coef_entries<T, OUTF, NL, BR, BC, R>()];
+  stage_gather_coefs<T, OUTF, NL, BR, BC, R>(p.lev, ct);
   if constexpr (OUTF == OUT_F16S || OUTF == OUT_FP8X2) {
     __shared__ int32_t exps[group_outputs<NL, R>()];
     for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y) {
       if (in != blockIdx.y) __syncthreads();  // the previous block's readers are done
       load_exponents<NL, R>(p, in, exps, blockIdx.x == 0);
-      gather_block<T, OUTF, V, NL, BR, BC, R>(p, blockIdx.x, in, exps);
+      gather_block<T, OUTF, V, NL, BR, BC, R>(p, ct, blockIdx.x, in, exps);
     }
   } else {
     for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y)
-      gather_block<T, OUTF, V, NL, BR, BC, R>(p, blockIdx.x, in, nullptr);
+      gather_block<T, OUTF, V, NL, BR, BC, R>(p, ct, blockIdx.x, in, nullptr);
   }
 }
 
 // Level LT of a scatter group: returns in `out` the BB^(NL-LT) values of the
 // block at this level for subproblem prefix idx.
-template <typename TP, typename TA, int V, int NL, int BR, int BC, int R, int LT>
+template <typename TP, typename TA, int V, int NL, int BR, int BC, int R, int NS, int LT>
 __device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t src_batch, int64_t off,
-                                              const SideLevel* lev, int64_t idx, VecT<TA, V>* out) {
+                                              const SideLevel* lev, const TA* ct, int64_t idx, VecT<TA, V>* out) {
   if constexpr (LT == NL) {
     const VecT<TP, V> x = vload<TP, V>(src + idx * src_batch + off);
 #pragma unroll
@@ -322,10 +391,14 @@ __device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t 
     for (int r = 0; r < RR; ++r) {
       if constexpr (UNR == 1 && RBC_LEVEL_BARRIER) __asm__ volatile("" ::: "memory");
       VecT<TA, V> sub[SUB];
-      scatter_level<TP, TA, V, NL, BR, BC, R, LT + 1>(src, src_batch, off, lev, idx * RR + r, sub);
+      scatter_level<TP, TA, V, NL, BR, BC, R, NS, LT + 1>(src, src_batch, off, lev, ct, idx * RR + r, sub);
 #pragma unroll
       for (int ij = 0; ij < BB; ++ij) {
-        const TA c = coef<TA, BC, UNR == 1>(L, ij / BC, ij % BC, r, RR);
+        TA c;
+        if constexpr (LT < NS)
+          c = ct[(LT * BB + ij) * (R ? R : kMaxR) + r];
+        else
+          c = coef<TA, BC, UNR == 1>(L, ij / BC, ij % BC, r, RR);
         const bool nz = c != TA(0);
 #pragma unroll
         for (int j = 0; j < SUB; ++j) {
@@ -342,7 +415,7 @@ __device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t 
 // One workgroup's share of a scatter: 256 threads x V positions (block bx)
 // of top block o.
 template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
-__device__ __forceinline__ void scatter_block(const ScatterParams& p, int64_t bx, int64_t o) {
+__device__ __forceinline__ void scatter_block(const ScatterParams& p, const TA* ct, int64_t bx, int64_t o) {
   constexpr int BB = BR * BC;
   constexpr int NOUT = ipow(BB, NL);
   const int64_t npos = p.rows_bot * p.cols_bot;
@@ -351,7 +424,7 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, int64_t bx
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
   const gbl<const TP>* src = global_ptr(static_cast<const TP*>(p.src));
   VecT<TA, V> out[NOUT];
-  scatter_level<TP, TA, V, NL, BR, BC, R, 0>(src, p.src_batch, pos, p.lev, o, out);
+  scatter_level<TP, TA, V, NL, BR, BC, R, scatter_staged<TA, NL, R>(), 0>(src, p.src_batch, pos, p.lev, ct, o, out);
   gbl<TO>* dst = global_ptr(static_cast<TO*>(p.dst)) + o * p.dst_batch;
 #pragma unroll
   for (int s = 0; s < NOUT; ++s) {
@@ -381,8 +454,10 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, int64_t bx
 
 template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
 __global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
+  __shared__ TA ct[scatter_coef_entries<TA, NL, BR, BC, R>()];
+  stage_scatter_coefs<TA, NL, BR, BC, R>(p.lev, ct);
   for (int64_t o = blockIdx.y; o < p.n_out; o += gridDim.y)
-    scatter_block<TP, TA, TO, V, NL, BR, BC, R>(p, blockIdx.x, o);
+    scatter_block<TP, TA, TO, V, NL, BR, BC, R>(p, ct, blockIdx.x, o);
 }
 
 inline dim3 grid_for(int64_t npos, int64_t nbatch) {
