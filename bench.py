@@ -5,7 +5,9 @@ Workload: C = A B with N = 4096, three Strassen levels (343 leaves of
 seeds 2001/2002), algorithm seed = step index mod 16, mode "full".  One step
 is one full pass of the hot path: draws + fold for every level, gather of A
 and B, the batched leaf GEMM, and the scatter into C, with A and B resident
-in HBM.  Prints one JSON line.
+in HBM.  With the plan's leaf gather on (the default at this size) the
+gathers stop one level above the leaves and the leaf GEMM forms its operands
+from those parent blocks while loading them.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload approx3072     # approximate scheme, bf16 hi+lo leaves
@@ -513,8 +515,8 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
                 "traffic": _traffic()}
-    comb_bytes = 4.0 * (2 * (N * N + info["n_leaves"] * info["mM"] * info["mK"])
-                        + info["n_leaves"] * info["mM"] * info["mN"] + N * N)
+    tr = plan.traffic()  # algorithmic bytes of the path the plan takes
+    comb_bytes = tr["gather_A"] + tr["gather_B"] + tr["scatter"]
     comb_ms = stage_ms[0] / calls + stage_ms[1] / calls + stage_ms[3] / calls
 
     out = {
@@ -525,7 +527,7 @@ def main():
         "config": {"workload": "randomized Strassen F-hat^(3), N=4096, 343 leaves of 512^3 on f32 MFMA, "
                                "A,B ~ U[-1,1] (seeds 2001/2002), algorithm seeds 0..15, mode full",
                    "n": N, "levels": LEVELS, "scheme": "strassen", "leaf": info["mM"], "prec": "f32",
-                   "parallelism": "single GPU"},
+                   "leaf_gather": plan.leaf_gather[0], "parallelism": "single GPU"},
         "rel_err_vs_fp64": rel_err,
         "stage_ms": {"gather_A": round(stage_ms[0] / calls, 4), "gather_B": round(stage_ms[1] / calls, 4),
                      "leaf": round(leaf_ms, 4), "scatter": round(stage_ms[3] / calls, 4)},

@@ -165,13 +165,33 @@ rbc_status rbc_fold(rbc_scheme s, const int32_t* signs, const int32_t* perms, in
 rbc_status rbc_plan_create(int64_t M, int64_t K, int64_t N, int levels, const rbc_scheme* schemes,
                            rbc_prec prec, int leaf_tile, rbc_plan* out);
 rbc_status rbc_plan_get_info(rbc_plan p, rbc_plan_info* info);
-/* Algorithmic HBM bytes of one product, per stage: bytes[0] gathers of A,
+/* Algorithmic HBM bytes of one rbc_matmul, per stage: bytes[0] gathers of A,
  * bytes[1] gathers of B (with the max|X| pass of f16s), bytes[2] leaf
- * products (S and T read once, P written once), bytes[3] scatters.  Every
+ * products (S and T read once, P written once; with the leaf gather on, the
+ * parent blocks read once instead of S and T), bytes[3] scatters.  Every
  * stage counts each element it must read and write once: the readable part
  * of a top block (virtual padding is never read), every bottom block, and the
  * writable part of C. */
 rbc_status rbc_plan_traffic(rbc_plan p, double bytes[4]);
+/* Leaf gather (eq. recursive-random-formula, deepest level).  For an
+ * RBC_PREC_F32 plan of two or more levels whose deepest scheme has at most two
+ * nonzero coefficients per product in U and in V (Strassen), rbc_matmul can
+ * form the leaf operands S and T inside the leaf product: each leaf tile
+ * loads the (at most two) sub-blocks of its parent block that its folded
+ * coefficients select and combines them as the deepest level's gather would,
+ * in the same order with one rounding per multiply and add, so C is the same
+ * to the bit.  The leaf operands are then never written to or read from HBM;
+ * the workspace size and the stage calls are the same either way (the stage
+ * calls always gather every level).  By default it is on where a cost
+ * model predicts a gain (the gathers' saved HBM bytes at 5 TB/s against a 9%
+ * slower leaf product: on for N = 4096 with three or four Strassen levels,
+ * off with two); RBC_LEAF_GATHER=1 (=0) in the environment turns it on (off)
+ * for every new plan that qualifies.
+ * set: on = 0 returns to separate gathers; on != 0 fails with
+ * RBC_EUNSUPPORTED for a plan that does not qualify.  get: whether it is on
+ * and whether the plan qualifies (either pointer may be NULL). */
+rbc_status rbc_plan_set_leaf_gather(rbc_plan p, int on);
+rbc_status rbc_plan_get_leaf_gather(rbc_plan p, int* on, int* available);
 void rbc_plan_destroy(rbc_plan p);
 
 /* ---- products ------------------------------------------------------------ */

@@ -272,6 +272,17 @@ class Plan:
         check(lib().rbc_stage_scatter(self._h, sp, pp, int(bool(kappa_scale)), _ptr(C), C.stride(0),
                                       _ptr(workspace), workspace.numel(), ctypes.c_void_p(st.cuda_stream)))
 
+    # ---- leaf gather --------------------------------------------------------
+    @property
+    def leaf_gather(self):
+        """(on, available): whether matmul forms the leaf operands inside the leaf product."""
+        on, av = ctypes.c_int(), ctypes.c_int()
+        check(lib().rbc_plan_get_leaf_gather(self._h, ctypes.byref(on), ctypes.byref(av)))
+        return bool(on.value), bool(av.value)
+
+    def set_leaf_gather(self, on=True):
+        check(lib().rbc_plan_set_leaf_gather(self._h, int(bool(on))))
+
     # ---- timing -------------------------------------------------------------
     def set_timing(self, on=True):
         check(lib().rbc_plan_set_timing(self._h, int(bool(on))))

@@ -172,17 +172,23 @@ rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
   const double e_mid = (p.prec == RBC_PREC_F64 || p.prec == RBC_PREC_BF16X3) ? 8 : 4;  // recombination
   const double e_out = p.prec == RBC_PREC_F64 ? 8 : 4;          // C
   for (int i = 0; i < 4; ++i) bytes[i] = 0;
-  const size_t ng = p.groups.size();
-  for (size_t gi = 0; gi < ng; ++gi) {
-    const Group& g = p.groups[gi];
-    const bool last = gi + 1 == ng;
+  // gathers: the readable part of every top block once, every bottom block once
+  const std::vector<Group>& gg = p.leaf_gather ? p.fgroups : p.groups;
+  for (size_t gi = 0; gi < gg.size(); ++gi) {
+    const Group& g = gg[gi];
+    const bool last = gi + 1 == gg.size() && !p.leaf_gather;
     const double n_out = (double)g.n_in * g.Rg;
-    // gathers: the readable part of every top block once, every bottom block once
     const double rdA = gi == 0 ? (double)p.M * p.K : (double)g.n_in * g.a_rows_top * g.a_cols_top;
     const double rdB = gi == 0 ? (double)p.K * p.N : (double)g.n_in * g.b_rows_top * g.b_cols_top;
     const double wo = last ? e_leaf : e;
     bytes[0] += rdA * e + n_out * g.a_rows_bot * g.a_cols_bot * wo;
     bytes[1] += rdB * e + n_out * g.b_rows_bot * g.b_cols_bot * wo;
+  }
+  const size_t ng = p.groups.size();
+  for (size_t gi = 0; gi < ng; ++gi) {
+    const Group& g = p.groups[gi];
+    const bool last = gi + 1 == ng;
+    const double n_out = (double)g.n_in * g.Rg;
     // scatter: every bottom block once, the writable part of every top block once
     const double rp = last ? e_prod : e_mid;
     const double wc = gi == 0 ? (double)p.M * p.N * e_out : (double)g.n_in * g.c_rows_top * g.c_cols_top * e_mid;
@@ -192,6 +198,12 @@ rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
     bytes[0] += (double)p.M * p.K * 4, bytes[1] += (double)p.K * p.N * 4;  // max|X|
   bytes[2] = (double)p.n_leaves * ((double)p.mM * p.mK * e_leaf + (double)p.mK * p.mN * e_leaf +
                                    (double)p.mM * p.mN * e_prod);
+  if (p.leaf_gather) {  // every parent block once instead of the leaf operands
+    const Group& g = p.fgroups.back();
+    const double n_par = (double)g.n_in * g.Rg;
+    bytes[2] = n_par * ((double)g.a_rows_bot * g.a_cols_bot + (double)g.b_rows_bot * g.b_cols_bot) * e +
+               (double)p.n_leaves * p.mM * p.mN * e_prod;
+  }
   return RBC_OK;
 }
 
@@ -222,10 +234,10 @@ struct Ctx {
   Draws dr;
 };
 
-rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx) {
+rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx, bool leaf_gather = false) {
   std::vector<ScaleLaunch> scale;
   std::vector<GatherLaunch> gl;
-  build_gather(c.p, c.dr, which, X, ldx, c.ws, scale, gl);
+  build_gather(c.p, c.dr, which, X, ldx, c.ws, scale, gl, leaf_gather);
   for (const ScaleLaunch& l : scale) {
     hipError_t e = launch(l, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "scale launch: %s", hipGetErrorString(e));
@@ -237,8 +249,9 @@ rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx) {
   return RBC_OK;
 }
 
-rbc_status run_leaf(Ctx& c) {
-  hipError_t e = launch(build_leaf(c.p, c.ws), c.stream);
+rbc_status run_leaf(Ctx& c, bool leaf_gather = false) {
+  hipError_t e = leaf_gather ? launch(build_leaf_gather(c.p, c.dr, c.ws), c.stream)
+                             : launch(build_leaf(c.p, c.ws), c.stream);
   if (e != hipSuccess) return fail(RBC_EHIP, "leaf launch: %s", hipGetErrorString(e));
   return RBC_OK;
 }
@@ -276,12 +289,13 @@ rbc_status matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, int64
   if ((st = check_draws(p, signs, perms, c.dr)) != RBC_OK) return st;
   if ((st = ensure_device(p)) != RBC_OK) return st;
   if (p.timing && p.recorded >= 4096) return fail(RBC_ENOMEM, "timing buffer full; collect first");
+  const bool lg = p.leaf_gather;
   if ((st = record(p, c.stream, 0)) != RBC_OK) return st;
-  if ((st = run_gather(c, 0, A, lda)) != RBC_OK) return st;
+  if ((st = run_gather(c, 0, A, lda, lg)) != RBC_OK) return st;
   if ((st = record(p, c.stream, 1)) != RBC_OK) return st;
-  if ((st = run_gather(c, 1, B, ldb)) != RBC_OK) return st;
+  if ((st = run_gather(c, 1, B, ldb, lg)) != RBC_OK) return st;
   if ((st = record(p, c.stream, 2)) != RBC_OK) return st;
-  if ((st = run_leaf(c)) != RBC_OK) return st;
+  if ((st = run_leaf(c, lg)) != RBC_OK) return st;
   if ((st = record(p, c.stream, 3)) != RBC_OK) return st;
   if ((st = run_scatter(c, kappa_scale != 0, C, ldc)) != RBC_OK) return st;
   if ((st = record(p, c.stream, 4)) != RBC_OK) return st;
@@ -413,6 +427,21 @@ rbc_status rbc_stage_scatter(rbc_plan h, const int32_t* signs, const int32_t* pe
 rbc_status rbc_plan_set_timing(rbc_plan h, int on) {
   if (!h) return fail(RBC_EINVAL, "null plan");
   h->p.timing = on != 0;
+  return RBC_OK;
+}
+
+rbc_status rbc_plan_set_leaf_gather(rbc_plan h, int on) {
+  if (!h) return fail(RBC_EINVAL, "null plan");
+  if (on && !h->p.leaf_gather_ok)
+    return fail(RBC_EUNSUPPORTED, "leaf gather needs f32, two or more levels and at most two terms per product");
+  h->p.leaf_gather = on != 0;
+  return RBC_OK;
+}
+
+rbc_status rbc_plan_get_leaf_gather(rbc_plan h, int* on, int* available) {
+  if (!h) return fail(RBC_EINVAL, "null plan");
+  if (on) *on = h->p.leaf_gather ? 1 : 0;
+  if (available) *available = h->p.leaf_gather_ok ? 1 : 0;
   return RBC_OK;
 }
 

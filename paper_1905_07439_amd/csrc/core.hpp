@@ -104,6 +104,15 @@ struct Plan {
   size_t g_off[2] = {0, 0};
   // element sizes: combination precision (gather side), recombination (scatter side)
   int comb_bytes = 4, recomb_bytes = 4;
+  // Leaf gather: an f32 plan of two or more levels whose deepest scheme has at
+  // most two nonzero coefficients per product in U and in V can form its leaf
+  // operands inside the leaf product, from the blocks of the level above.
+  // fgroups then gather levels [0, Q - 1) (the last one's bottom blocks, the
+  // parents of the leaves, at off_S and off_T when they fit there); the stage
+  // calls and the batch engine keep the separate gather of every level.
+  bool leaf_gather_ok = false;   // the plan qualifies
+  bool leaf_gather = false;      // rbc_matmul takes that path
+  std::vector<Group> fgroups;
 
   // device state, created on first use (see device.cpp)
   int device = -1;

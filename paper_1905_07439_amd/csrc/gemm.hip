@@ -54,6 +54,31 @@ __global__ __launch_bounds__(256, 3) void k_gemm_f32_128(const float* __restrict
     tiles::gemm_f32_tile<64, 64, 16, 2>(S, T, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem);
 }
 
+// The same tiles with the operands gathered while they are loaded (LeafGather).
+__global__ __launch_bounds__(256, 3) void k_gemm_f32_128_gathered(const LeafGather g, float* __restrict__ P, int m,
+                                                                  int n, int k, int tiles_n, int tiles_per_leaf,
+                                                                  int64_t n_big, int64_t n_small) {
+  __shared__ __attribute__((aligned(16))) float smem[kSmem128 > kSmem64 ? kSmem128 : kSmem64];
+  int64_t bid;
+  if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid))
+    tiles::gemm_f32_tile<128, 128, 16, 4, true>(g.A, g.B, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem, &g);
+  else if (k % 32 == 0)
+    tiles::gemm_f32_tile<64, 64, 32, 2, true>(g.A, g.B, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem,
+                                              &g);
+  else
+    tiles::gemm_f32_tile<64, 64, 16, 2, true>(g.A, g.B, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem,
+                                              &g);
+}
+
+template <int BK, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_gemm_f32_64_gathered(const LeafGather g, float* __restrict__ P, int m,
+                                                                    int n, int k, int tiles_n, int tiles_per_leaf,
+                                                                    int64_t nblocks) {
+  __shared__ __attribute__((aligned(16))) float smem[F32Tile<64, 64, BK, 2>::SMEM];
+  tiles::gemm_f32_tile<64, 64, BK, 2, true>(g.A, g.B, P, m, n, k, tiles_n, tiles_per_leaf,
+                                            tiles::xcd_remap(blockIdx.x, nblocks), smem, &g);
+}
+
 template <int BM, int BN, int BK, int MINB, int EPI>
 __global__ __launch_bounds__(256, MINB) void k_gemm_f32(const float* __restrict__ S,
                                                         const float* __restrict__ T, float* __restrict__ P,
@@ -109,6 +134,28 @@ hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, 
   else
     hipLaunchKernelGGL((k_gemm_f32<64, 64, 16, 8, 2>), grid, block, 0, stream, S, T, P, (int)m, (int)n,
                        (int)k, tiles_n, tiles_per_leaf, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32_gathered(const LeafGather& g, float* P, int64_t m, int64_t n, int64_t k,
+                                    int64_t batch, int tile, hipStream_t stream) {
+  if (batch == 0 || m == 0 || n == 0) return hipSuccess;
+  if (m % tile || n % tile || k % 16 || (tile != 64 && tile != 128)) return hipErrorInvalidValue;
+  if (!g.A || !g.B || !g.la.tab || !g.lb.tab || g.R < 1 || batch % g.R) return hipErrorInvalidValue;
+  const int tiles_n = (int)(n / tile), tiles_per_leaf = (int)((m / tile) * tiles_n);
+  const int64_t nblocks = batch * tiles_per_leaf;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 block(256);
+  if (tile == 128) {
+    const TailSplit sp = tail_split(nblocks, resident_blocks((const void*)k_gemm_f32_128_gathered, 256));
+    hipLaunchKernelGGL(k_gemm_f32_128_gathered, dim3((unsigned)(sp.n_big + sp.n_small)), block, 0, stream, g, P,
+                       (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
+  } else if (k % 32 == 0)
+    hipLaunchKernelGGL((k_gemm_f32_64_gathered<32, 4>), dim3((unsigned)nblocks), block, 0, stream, g, P, (int)m,
+                       (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
+  else
+    hipLaunchKernelGGL((k_gemm_f32_64_gathered<16, 4>), dim3((unsigned)nblocks), block, 0, stream, g, P, (int)m,
+                       (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
   return hipGetLastError();
 }
 

@@ -61,11 +61,48 @@ struct F32Tile {
   static constexpr int SMEM = A_FLOATS + B_FLOATS > E_FLOATS ? A_FLOATS + B_FLOATS : E_FLOATS;
 };
 
+// The nonzero folded coefficients of product r on one side of a level, in
+// row-major sub-block order, with the element offsets of their sub-blocks;
+// n counts them (the host admits at most two).
+struct GatherSlots {
+  float c0, c1;
+  int64_t off0, off1;
+  int n;
+};
+
+__device__ __forceinline__ GatherSlots gather_slots(const SideLevel& L, int br, int bc, int r, int R,
+                                                    int64_t row_blk, int64_t col_blk) {
+  const gbl<const float>* tab = global_ptr(static_cast<const float*>(L.tab));
+  GatherSlots g{0.f, 0.f, 0, 0, 0};
+  for (int kr = 0; kr < br; ++kr)
+    for (int kc = 0; kc < bc; ++kc) {
+      float c = tab[(L.pr[kr] * bc + L.pc[kc]) * R + r];
+      if (L.sr[kr] * L.sc[kc] < 0) c = -c;
+      if (c != 0.f) {
+        const int64_t off = kr * row_blk + kc * col_blk;
+        if (g.n == 0) g.c0 = c, g.off0 = off;
+        else g.c1 = c, g.off1 = off;
+        ++g.n;
+      }
+    }
+  return g;
+}
+
+// c0 x0 (+ c1 x1 when n > 1; zero when n == 0), one rounding per operation.
+__device__ __forceinline__ floatx4 gather_sum(const GatherSlots& g, floatx4 x0, floatx4 x1) {
+#pragma clang fp contract(off)
+  const floatx4 t0 = g.c0 * x0;
+  const floatx4 s = g.n > 1 ? t0 + g.c1 * x1 : t0;
+  return g.n > 0 ? s : floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
 // Output tile `bid` (leaf-major, then tile row, then tile column) of the batched leaf product.
-template <int BM, int BN, int BK, int EPI = 1>
+// GATHER: the operands come from gsrc (LeafGather) instead of S and T.
+template <int BM, int BN, int BK, int EPI = 1, bool GATHER = false>
 __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const float* __restrict__ T,
                                               float* __restrict__ P, int m, int n, int k, int tiles_n,
-                                              int tiles_per_leaf, int64_t bid, float* smem) {
+                                              int tiles_per_leaf, int64_t bid, float* smem,
+                                              const LeafGather* gsrc = nullptr) {
   constexpr int LDA = F32Tile<BM, BN, BK, EPI>::LDA;  // S slab row: k-contiguous, padded
   constexpr int LDB = F32Tile<BM, BN, BK, EPI>::LDB;  // T slab row: n-contiguous, padded
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -90,26 +127,63 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
   const int wm = wave >> 1, wn = wave & 1;
 
   // Per-thread slab sources: S row (tid + 256 i) / KQ, chunk % KQ; T row (tid + 256 i) / (BN/4).
+  // With GATHER they point into the first nonzero sub-block of the leaf's parent, the
+  // second at a fixed offset from the first.
   const gbl<const float>* a_src[A_VEC];
   const gbl<const float>* b_src[B_VEC];
+  int64_t a_ld = k, b_ld = n, a_off1 = 0, b_off1 = 0;
+  GatherSlots ga{1.f, 0.f, 0, 0, 1}, gb{1.f, 0.f, 0, 0, 1};
+  if constexpr (GATHER) {
+    const int64_t parent = leaf / gsrc->R;
+    const int r = (int)(leaf - parent * gsrc->R);
+    ga = gather_slots(gsrc->la, gsrc->bra, gsrc->bca, r, gsrc->R, gsrc->a_row_blk, gsrc->a_col_blk);
+    gb = gather_slots(gsrc->lb, gsrc->brb, gsrc->bcb, r, gsrc->R, gsrc->b_row_blk, gsrc->b_col_blk);
+    a_ld = gsrc->a_ld, b_ld = gsrc->b_ld;
+    a_off1 = ga.off1 - ga.off0, b_off1 = gb.off1 - gb.off0;
+    Sl = global_ptr(gsrc->A) + parent * gsrc->a_batch + ga.off0 + (int64_t)tm * BM * a_ld;
+    Tl = global_ptr(gsrc->B) + parent * gsrc->b_batch + gb.off0 + (int64_t)tn * BN;
+  }
 #pragma unroll
   for (int i = 0; i < A_VEC; ++i) {
     const int idx = tid + 256 * i;
-    a_src[i] = Sl + (int64_t)(idx / KQ) * k + (idx % KQ) * 4;
+    a_src[i] = Sl + (int64_t)(idx / KQ) * a_ld + (idx % KQ) * 4;
   }
 #pragma unroll
   for (int i = 0; i < B_VEC; ++i) {
     const int idx = tid + 256 * i;
-    b_src[i] = Tl + (int64_t)(idx / (BN / 4)) * n + (idx % (BN / 4)) * 4;
+    b_src[i] = Tl + (int64_t)(idx / (BN / 4)) * b_ld + (idx % (BN / 4)) * 4;
   }
-  const int64_t b_step = (int64_t)BK * n;
+  const int64_t b_step = (int64_t)BK * b_ld;
 
-  // clang vector types (not HIP's float4 struct) so the staging stays in registers
+  // clang vector types (not HIP's float4 struct) so the staging stays in registers.
+  // ra, rb: the slab as loaded (first sub-block with GATHER); xa, xb: second sub-block.
   floatx4 ra[A_VEC], rb[B_VEC];
+  floatx4 xa[GATHER ? A_VEC : 1], xb[GATHER ? B_VEC : 1];
+  auto load_slab = [&](int kt) {
 #pragma unroll
-  for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const gbl<const floatx4>*>(a_src[i]);
+    for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const gbl<const floatx4>*>(a_src[i] + kt * BK);
 #pragma unroll
-  for (int i = 0; i < B_VEC; ++i) rb[i] = *reinterpret_cast<const gbl<const floatx4>*>(b_src[i]);
+    for (int i = 0; i < B_VEC; ++i) rb[i] = *reinterpret_cast<const gbl<const floatx4>*>(b_src[i] + kt * b_step);
+    if constexpr (GATHER) {
+      if (ga.n > 1) {
+#pragma unroll
+        for (int i = 0; i < A_VEC; ++i)
+          xa[i] = *reinterpret_cast<const gbl<const floatx4>*>(a_src[i] + a_off1 + kt * BK);
+      }
+      if (gb.n > 1) {
+#pragma unroll
+        for (int i = 0; i < B_VEC; ++i)
+          xb[i] = *reinterpret_cast<const gbl<const floatx4>*>(b_src[i] + b_off1 + kt * b_step);
+      }
+    }
+  };
+  if constexpr (GATHER) {
+#pragma unroll
+    for (int i = 0; i < A_VEC; ++i) xa[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < B_VEC; ++i) xb[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  load_slab(0);
 
   floatx4 acc[FM][FN];
 #pragma unroll
@@ -124,21 +198,19 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
 #pragma unroll
     for (int i = 0; i < A_VEC; ++i) {
       const int idx = tid + 256 * i;
-      *reinterpret_cast<floatx4*>(&As[cur][idx / KQ][(idx % KQ) * 4]) = ra[i];
+      floatx4 v = ra[i];
+      if constexpr (GATHER) v = gather_sum(ga, ra[i], xa[i]);
+      *reinterpret_cast<floatx4*>(&As[cur][idx / KQ][(idx % KQ) * 4]) = v;
     }
 #pragma unroll
     for (int i = 0; i < B_VEC; ++i) {
       const int idx = tid + 256 * i;
-      *reinterpret_cast<floatx4*>(&Bs[cur][idx / (BN / 4)][(idx % (BN / 4)) * 4]) = rb[i];
+      floatx4 v = rb[i];
+      if constexpr (GATHER) v = gather_sum(gb, rb[i], xb[i]);
+      *reinterpret_cast<floatx4*>(&Bs[cur][idx / (BN / 4)][(idx % (BN / 4)) * 4]) = v;
     }
     __syncthreads();
-    if (kt + 1 < nk) {
-#pragma unroll
-      for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const gbl<const floatx4>*>(a_src[i] + (kt + 1) * BK);
-#pragma unroll
-      for (int i = 0; i < B_VEC; ++i)
-        rb[i] = *reinterpret_cast<const gbl<const floatx4>*>(b_src[i] + (kt + 1) * b_step);
-    }
+    if (kt + 1 < nk) load_slab(kt + 1);
     // 16 k per chunk: in MFMA step j, lane group lg carries k = 16 c + 4 lg + j for both
     // operands, so one 16-byte read of S gives a lane its operands for four steps.
 #pragma unroll

@@ -51,6 +51,22 @@ struct ScatterParams {
   SideLevel lev[kMaxGroupLevels];
 };
 
+// f32 leaf products whose operands are formed while they are loaded: leaf l
+// is product r = l % R of parent block l / R of the level above, and its S
+// (T) is the sum, over the parent's sub-blocks (k, l) in row-major order, of
+// the folded coefficient times the sub-block, as the deepest level's gather
+// would have written it (one rounding per multiply and per add).  At most two
+// coefficients of any product may be nonzero on either side.
+struct LeafGather {
+  const float* A;                  // A-side parents: a_batch elements apart, row stride a_ld
+  const float* B;
+  int64_t a_batch, a_ld, b_batch, b_ld;
+  int64_t a_row_blk, a_col_blk;    // element offset of sub-block (1, 0) and of (0, 1) in a parent
+  int64_t b_row_blk, b_col_blk;
+  SideLevel la, lb;                // the deepest level's A and B sides (f32 tables)
+  int32_t bra, bca, brb, bcb, R;
+};
+
 // Element-type codes for launchers.
 enum Elt { ELT_F32 = 0, ELT_F64 = 1 };
 
@@ -66,6 +82,9 @@ hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int vec, int nl, int br, int b
 // each row-major and contiguous, consecutive leaves back to back.
 hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, int64_t n, int64_t k,
                            int64_t batch, int tile, hipStream_t stream);
+// P (batch leaves of m x n) from operands gathered on the fly (LeafGather).
+hipError_t launch_gemm_f32_gathered(const LeafGather& g, float* P, int64_t m, int64_t n, int64_t k,
+                                    int64_t batch, int tile, hipStream_t stream);
 hipError_t launch_gemm_f64(const double* S, const double* T, double* P, int64_t m, int64_t n,
                            int64_t k, int64_t batch, hipStream_t stream);
 // bf16x3: S and T hold hi planes followed (plane elements later) by lo planes.

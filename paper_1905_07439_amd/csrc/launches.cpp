@@ -164,8 +164,9 @@ rbc_status check_ws(const Plan& p, void* ws, size_t bytes) {
 }
 
 void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int64_t ldx, char* ws,
-                  std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out) {
+                  std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out, bool leaf_gather) {
   scale.clear(), out.clear();
+  const std::vector<Group>& groups = leaf_gather ? p.fgroups : p.groups;
   const bool f64 = p.prec == RBC_PREC_F64;
   const bool scaled = p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C;
   int32_t* exps = nullptr;
@@ -180,9 +181,9 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     sl.target = p.prec == RBC_PREC_FP8C ? 448.0f : 32768.0f;
     scale.push_back(sl);
   }
-  for (size_t gi = 0; gi < p.groups.size(); ++gi) {
-    const Group& g = p.groups[gi];
-    const bool last = gi + 1 == p.groups.size();
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
+    const bool last = gi + 1 == groups.size() && !leaf_gather;  // writes the leaf operands
     GatherLaunch L;
     GatherParams& gp = L.p;
     std::memset(&gp, 0, sizeof gp);
@@ -193,7 +194,7 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
       gp.src_rows = which == 0 ? p.M : p.K;
       gp.src_cols = which == 0 ? p.K : p.N;
     } else {
-      const Group& up = p.groups[gi - 1];
+      const Group& up = groups[gi - 1];
       gp.src = ws + (which == 0 ? up.off_a_bot : up.off_b_bot);
       gp.ld_src = cols_top, gp.src_batch = rows_top * cols_top;
       gp.src_rows = rows_top, gp.src_cols = cols_top;
@@ -237,6 +238,26 @@ LeafLaunch build_leaf(const Plan& p, char* ws) {
     L.eS = reinterpret_cast<const int32_t*>(ws + p.off_aux + kAuxExpOffset);
     L.eT = L.eS + p.n_leaves;
   }
+  return L;
+}
+
+LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws) {
+  LeafGatherLaunch L;
+  std::memset(&L.g, 0, sizeof L.g);
+  const Group& up = p.fgroups.back();
+  const Scheme& s = p.levels[p.Q - 1];
+  LeafGather& g = L.g;
+  g.A = reinterpret_cast<const float*>(ws + up.off_a_bot);
+  g.B = reinterpret_cast<const float*>(ws + up.off_b_bot);
+  g.a_ld = up.a_cols_bot, g.a_batch = up.a_rows_bot * up.a_cols_bot;
+  g.b_ld = up.b_cols_bot, g.b_batch = up.b_rows_bot * up.b_cols_bot;
+  g.a_row_blk = p.mM * g.a_ld, g.a_col_blk = p.mK;
+  g.b_row_blk = p.mK * g.b_ld, g.b_col_blk = p.mN;
+  fill_side(p, dr, p.Q - 1, SIDE_A, false, false, g.la);
+  fill_side(p, dr, p.Q - 1, SIDE_B, false, false, g.lb);
+  g.bra = s.b1, g.bca = s.b2, g.brb = s.b2, g.bcb = s.b3, g.R = s.R;
+  L.P = reinterpret_cast<float*>(ws + p.off_P);
+  L.m = p.mM, L.n = p.mN, L.k = p.mK, L.batch = p.n_leaves, L.tile = p.tile_m;
   return L;
 }
 
@@ -303,6 +324,10 @@ hipError_t launch(const LeafLaunch& l, hipStream_t s) {
                                 static_cast<float*>(l.P), l.m, l.n, l.k, l.batch, l.tile, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch(const LeafGatherLaunch& l, hipStream_t s) {
+  return launch_gemm_f32_gathered(l.g, l.P, l.m, l.n, l.k, l.batch, l.tile, s);
 }
 
 hipError_t launch(const ScatterLaunch& l, hipStream_t s) {

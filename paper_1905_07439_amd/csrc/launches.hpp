@@ -51,6 +51,13 @@ struct LeafLaunch {
   const int32_t* eT;
 };
 
+struct LeafGatherLaunch {  // f32 leaf products with the deepest level gathered in the loads
+  LeafGather g;
+  float* P;
+  int64_t m, n, k, batch;
+  int tile;
+};
+
 struct ScatterLaunch {
   ScatterParams p;
   Elt tp, ta, to;
@@ -58,9 +65,13 @@ struct ScatterLaunch {
 };
 
 // which = 0: A (M x K), 1: B (K x N).  `scale` is filled for f16s and fp8c plans.
+// leaf_gather: the gathers of levels [0, Q - 1) only (Plan::fgroups), whose
+// output build_leaf_gather's launch reads.
 void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int64_t ldx, char* ws,
-                  std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out);
+                  std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out, bool leaf_gather = false);
 LeafLaunch build_leaf(const Plan& p, char* ws);
+// Requires p.leaf_gather_ok.
+LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws);
 // In execution order (deepest group first).
 void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, int64_t ldc, char* ws,
                    std::vector<ScatterLaunch>& out);
@@ -68,6 +79,7 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
 hipError_t launch(const ScaleLaunch& l, hipStream_t s);
 hipError_t launch(const GatherLaunch& l, hipStream_t s);
 hipError_t launch(const LeafLaunch& l, hipStream_t s);
+hipError_t launch(const LeafGatherLaunch& l, hipStream_t s);
 hipError_t launch(const ScatterLaunch& l, hipStream_t s);
 
 }  // namespace rbc

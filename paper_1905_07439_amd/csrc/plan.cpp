@@ -45,6 +45,100 @@ static bool same_shape(const Scheme& a, const Scheme& b) {
   return a.b1 == b.b1 && a.b2 == b.b2 && a.b3 == b.b3 && a.R == b.R;
 }
 
+// Fused groups over levels [0, d_end), formed from the deepest level upwards so
+// that the boundaries between passes sit where the intermediate blocks are
+// fewest, with their block dimensions (bottom blocks of levels below d_end
+// included: the leaves are always mM x mK and mK x mN).
+static std::vector<Group> form_groups(const Plan& p, int d_end) {
+  const std::vector<Scheme>& levels = p.levels;
+  std::vector<Group> gs;
+  const int max_nl = max_fused_levels();
+  for (int d = d_end - 1; d >= 0; --d) {
+    const Scheme& s = levels[d];
+    if (!gs.empty()) {
+      Group& g = gs.back();  // the group just below, levels [g.d0, g.d1)
+      const int nl = g.d1 - g.d0 + 1;
+      if (nl <= max_nl && same_shape(s, levels[g.d0]) && fused_supported(s.b1, s.b2, s.b3, s.R, nl)) {
+        g.d0 = d;
+        continue;
+      }
+    }
+    Group g;
+    g.d0 = d, g.d1 = d + 1;
+    g.b1 = s.b1, g.b2 = s.b2, g.b3 = s.b3;
+    gs.push_back(g);
+  }
+  std::reverse(gs.begin(), gs.end());
+  if (p.Q == 0) {  // plain product: one empty group copies A, B in and C out
+    Group g;
+    g.b1 = g.b2 = g.b3 = 1;
+    gs.push_back(g);
+  }
+  int64_t n_in = 1;
+  for (Group& g : gs) {
+    int64_t q1 = 1, q2 = 1, q3 = 1, below1 = 1, below2 = 1, below3 = 1;
+    for (int d = g.d0; d < g.d1; ++d) q1 *= levels[d].b1, q2 *= levels[d].b2, q3 *= levels[d].b3;
+    for (int d = g.d1; d < p.Q; ++d)
+      below1 *= levels[d].b1, below2 *= levels[d].b2, below3 *= levels[d].b3;
+    g.n_in = n_in;
+    g.Rg = 1;
+    for (int d = g.d0; d < g.d1; ++d) g.Rg *= levels[d].R;
+    g.a_rows_bot = p.mM * below1, g.a_cols_bot = p.mK * below2;
+    g.b_rows_bot = p.mK * below2, g.b_cols_bot = p.mN * below3;
+    g.c_rows_bot = p.mM * below1, g.c_cols_bot = p.mN * below3;
+    g.a_rows_top = g.a_rows_bot * q1, g.a_cols_top = g.a_cols_bot * q2;
+    g.b_rows_top = g.b_rows_bot * q2, g.b_cols_top = g.b_cols_bot * q3;
+    g.c_rows_top = g.c_rows_bot * q1, g.c_cols_top = g.c_cols_bot * q3;
+    n_in *= g.Rg;
+  }
+  return gs;
+}
+
+// At most two nonzero coefficients (as f32, the precision the kernels read)
+// in every column r of U and of V: the leaf product's loads can then form the
+// operands (LeafGather).
+static bool two_terms(const Scheme& s) {
+  for (int r = 0; r < s.R; ++r) {
+    int nu = 0, nv = 0;
+    for (int i = 0; i < s.b1 * s.b2; ++i) nu += (float)s.U[i * s.R + r] != 0.0f;
+    for (int i = 0; i < s.b2 * s.b3; ++i) nv += (float)s.V[i * s.R + r] != 0.0f;
+    if (nu > 2 || nv > 2) return false;
+  }
+  return true;
+}
+
+// RBC_LEAF_GATHER=0 turns the leaf gather off for every new plan, =1 on
+// wherever it qualifies; unset, it is on where the cost model below favours it.
+static int leaf_gather_env() {
+  const char* e = std::getenv("RBC_LEAF_GATHER");
+  return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : -1;
+}
+
+// f32 bytes the gathers of A and B move over `gs` (each top block read once,
+// each bottom block written once).
+static double gather_bytes(const Plan& p, const std::vector<Group>& gs) {
+  double b = 0;
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    const Group& g = gs[gi];
+    const double n_out = (double)g.n_in * g.Rg;
+    b += gi == 0 ? (double)p.M * p.K + (double)p.K * p.N
+                 : (double)g.n_in * ((double)g.a_rows_top * g.a_cols_top + (double)g.b_rows_top * g.b_cols_top);
+    b += n_out * ((double)g.a_rows_bot * g.a_cols_bot + (double)g.b_rows_bot * g.b_cols_bot);
+  }
+  return 4 * b;
+}
+
+// Whether the leaf gather pays: the gathers it saves (at 5 TB/s, what they
+// reach) against the leaf product's slowdown from loading up to two
+// sub-blocks per operand (about 9% at 125 TF/s; measured at N = 4096: Q = 3
+// gathers 130 -> 57 us each and the leaf 749 -> 806 us, a gain; Q = 2 gathers
+// 53 -> 41 us and the leaf 810 -> 890 us, a loss).
+static bool leaf_gather_pays(const Plan& p) {
+  const double saved_us = (gather_bytes(p, p.groups) - gather_bytes(p, p.fgroups)) / 5e6;
+  const double flops = 2.0 * p.n_leaves * (double)p.mM * p.mK * p.mN;
+  return saved_us > 0.09 * flops / 125e6;
+}
+
 rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>& levels,
                      rbc_prec prec, int leaf_tile, Plan& out) {
   if (M < 1 || K < 1 || N < 1) return fail(RBC_EINVAL, "empty product %lldx%lldx%lld", (long long)M,
@@ -108,49 +202,9 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : ((prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) ? 2 : 4);
   const int prod_bytes = prec == RBC_PREC_F64 ? 8 : 4;
 
-  // Fused groups, formed from the deepest level upwards so that the
-  // boundaries between passes sit where the intermediate blocks are fewest.
-  const int max_nl = max_fused_levels();
-  for (int d = p.Q - 1; d >= 0; --d) {
-    const Scheme& s = levels[d];
-    if (!p.groups.empty()) {
-      Group& g = p.groups.back();  // the group just below, levels [g.d0, g.d1)
-      const int nl = g.d1 - g.d0 + 1;
-      if (nl <= max_nl && same_shape(s, levels[g.d0]) && fused_supported(s.b1, s.b2, s.b3, s.R, nl)) {
-        g.d0 = d;
-        continue;
-      }
-    }
-    Group g;
-    g.d0 = d, g.d1 = d + 1;
-    g.b1 = s.b1, g.b2 = s.b2, g.b3 = s.b3;
-    p.groups.push_back(g);
-  }
-  std::reverse(p.groups.begin(), p.groups.end());
-  if (p.Q == 0) {  // plain product: one empty group copies A, B in and C out
-    Group g;
-    g.b1 = g.b2 = g.b3 = 1;
-    p.groups.push_back(g);
-  }
-
-  // Dimensions per group.
-  int64_t n_in = 1;
-  for (Group& g : p.groups) {
-    int64_t q1 = 1, q2 = 1, q3 = 1, below1 = 1, below2 = 1, below3 = 1;
-    for (int d = g.d0; d < g.d1; ++d) q1 *= levels[d].b1, q2 *= levels[d].b2, q3 *= levels[d].b3;
-    for (int d = g.d1; d < p.Q; ++d)
-      below1 *= levels[d].b1, below2 *= levels[d].b2, below3 *= levels[d].b3;
-    g.n_in = n_in;
-    g.Rg = 1;
-    for (int d = g.d0; d < g.d1; ++d) g.Rg *= levels[d].R;
-    g.a_rows_bot = p.mM * below1, g.a_cols_bot = p.mK * below2;
-    g.b_rows_bot = p.mK * below2, g.b_cols_bot = p.mN * below3;
-    g.c_rows_bot = p.mM * below1, g.c_cols_bot = p.mN * below3;
-    g.a_rows_top = g.a_rows_bot * q1, g.a_cols_top = g.a_cols_bot * q2;
-    g.b_rows_top = g.b_rows_bot * q2, g.b_cols_top = g.b_cols_bot * q3;
-    g.c_rows_top = g.c_rows_bot * q1, g.c_cols_top = g.c_cols_bot * q3;
-    n_in *= g.Rg;
-  }
+  p.groups = form_groups(p, p.Q);
+  p.leaf_gather_ok = prec == RBC_PREC_F32 && p.Q >= 2 && two_terms(levels[p.Q - 1]);
+  if (p.leaf_gather_ok) p.fgroups = form_groups(p, p.Q - 1);
 
   // Workspace: leaf operands, products, then the group-boundary buffers.
   size_t off = 0;
@@ -171,6 +225,20 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     g.off_b_bot = off, off = align256(off + nb * g.b_rows_bot * g.b_cols_bot * p.comb_bytes);
     g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * p.recomb_bytes);
   }
+  // Leaf gather: the leaves' parents go where the leaf operands would be when
+  // they fit (the two paths never run at once on one workspace).
+  for (size_t gi = 0; gi < p.fgroups.size(); ++gi) {
+    Group& g = p.fgroups[gi];
+    const size_t nb = (size_t)g.n_in * g.Rg;
+    const size_t ba = nb * g.a_rows_bot * g.a_cols_bot * 4, bb = nb * g.b_rows_bot * g.b_cols_bot * 4;
+    const bool last = gi + 1 == p.fgroups.size();
+    if (last && ba <= p.bytes_S) g.off_a_bot = p.off_S;
+    else g.off_a_bot = off, off = align256(off + ba);
+    if (last && bb <= p.bytes_T) g.off_b_bot = p.off_T;
+    else g.off_b_bot = off, off = align256(off + bb);
+  }
+  const int env = leaf_gather_env();
+  p.leaf_gather = p.leaf_gather_ok && (env < 0 ? leaf_gather_pays(p) : env == 1);
   if (prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) {
     p.off_aux = off;
     p.bytes_aux = kAuxExpOffset + 2 * (size_t)p.n_leaves * 4;

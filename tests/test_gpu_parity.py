@@ -462,3 +462,32 @@ def test_tail_split_tiles_give_the_same_bits(prec):
     C2 = small.matmul(A, B, seed=2)
     torch.cuda.synchronize()
     assert torch.equal(C1, C2)
+
+
+@pytest.mark.parametrize("names,M,K,N,tile", [
+    (["strassen"] * 3, 4096, 4096, 4096, 0),
+    (["strassen"] * 3, 1000, 600, 777, 64),
+    (["strassen"] * 2, 300, 192, 500, 64),     # leaf K = 48: 64-tiles with K slabs of 16
+    (["strassen"] * 2, 300, 200, 500, 128),
+    (["laderman", "strassen"], 700, 500, 900, 64),
+    (["strassen"] * 4, 1024, 1024, 1024, 0),
+])
+def test_leaf_gather_same_bits(names, M, K, N, tile):
+    # The leaf product that forms its operands while loading them (deepest level's gather
+    # inside the leaf tile) must give C bitwise equal to the separate gather of every level.
+    _say("leaf gather", names, M, K, N, tile)
+    lib_s, _ = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec="f32", leaf_tile=tile)
+    assert plan.leaf_gather[1]  # available (whether it is on by default is the cost model's call)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(M + K + N)
+    A = torch.randn(M, K, device=DEV, generator=g)
+    B = torch.randn(K, N, device=DEV, generator=g)
+    for seed, mode in [(0, "full"), (5, "full"), (1, "signs"), (3, "none")]:
+        plan.set_leaf_gather(True)
+        C1 = plan.matmul(A, B, seed=seed, mode=mode)
+        plan.set_leaf_gather(False)
+        C2 = plan.matmul(A, B, seed=seed, mode=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(C1, C2), (seed, mode, float((C1 - C2).abs().max()))
+    assert plan.leaf_gather == (False, True)

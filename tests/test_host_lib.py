@@ -139,6 +139,9 @@ def test_plan_geometry():
     assert f.info["n_groups"] == (2 if os.environ.get("RBC_MAX_FUSED_LEVELS") == "3" else 3)
     z = rbc.Plan(100, 50, 30, [], prec="f32")
     assert z.info["n_leaves"] == 1 and z.info["mM"] == 128 and z.info["n_groups"] == 1
+    # the plain product's one group copies A in and C out: its bytes are counted
+    tz = z.traffic()
+    assert tz["gather_A"] == 100 * 50 * 4 + 128 * 64 * 4 and tz["scatter"] == 128 * 64 * 4 + 100 * 30 * 4
 
 
 def test_f16s_plan_geometry():
@@ -169,6 +172,40 @@ def test_fp8c_plan_geometry():
     assert i["bytes_aux"] == 2 * 1024 * 4 + 2 * 49 * 4
     t = p.traffic()
     assert t["leaf"] == 49 * (96 * 128 * 2 + 128 * 64 * 2 + 96 * 64 * 4)
+
+
+def test_leaf_gather_availability_and_traffic():
+    # Available for f32 plans of two or more levels whose deepest scheme has at most two
+    # nonzero coefficients per product in U and in V (Strassen, not Laderman), on by default.
+    S = rbc.Scheme.builtin("strassen")
+    L = rbc.Scheme.builtin("laderman")
+    env = os.environ.get("RBC_LEAF_GATHER")
+    p = rbc.Plan(4096, 4096, 4096, [S, S, S], prec="f32")
+    assert p.leaf_gather == (env != "0", True)
+    # the cost model: off for two Strassen levels at N = 4096 (the gathers save little)
+    assert rbc.Plan(4096, 4096, 4096, [S, S], prec="f32").leaf_gather == (env == "1", True)
+    assert rbc.Plan(4096, 4096, 4096, [S] * 4, prec="f32").leaf_gather == (env != "0", True)
+    assert rbc.Plan(700, 500, 900, [L, S], prec="f32").leaf_gather[1]
+    for q in (rbc.Plan(4096, 4096, 4096, [S], prec="f32"), rbc.Plan(900, 900, 900, [S, L], prec="f32"),
+              rbc.Plan(1024, 1024, 1024, [S, S], prec="f16s"), rbc.Plan(1024, 1024, 1024, [S, S], prec="fp8c"),
+              rbc.Plan(256, 256, 256, [S, S], prec="f64"), rbc.Plan(256, 256, 256, [S, S], prec="bf16x3")):
+        assert q.leaf_gather == (False, False)
+        with pytest.raises(rbc.RbcError) as e:
+            q.set_leaf_gather(True)
+        assert e.value.status == _lib.RBC_EUNSUPPORTED
+        q.set_leaf_gather(False)
+    # Traffic: with the leaf gather the gathers stop at the 49 parents of 1024^2 and the
+    # leaf stage reads each parent once; the scatter is unchanged.
+    p.set_leaf_gather(False)
+    t0 = p.traffic()
+    p.set_leaf_gather(True)
+    t1 = p.traffic()
+    n, e = 4096, 4
+    assert t0["gather_A"] == n * n * e + 7 * 2048 * 2048 * e + 7 * 2048 * 2048 * e + 343 * 512 * 512 * e
+    assert t1["gather_A"] == n * n * e + 49 * 1024 * 1024 * e
+    assert t1["leaf"] == 2 * 49 * 1024 * 1024 * e + 343 * 512 * 512 * e
+    assert t0["scatter"] == t1["scatter"]
+    assert p.workspace_bytes == rbc.Plan(4096, 4096, 4096, [S, S, S], prec="f32").workspace_bytes
 
 
 def test_plan_errors():
