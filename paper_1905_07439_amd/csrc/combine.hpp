@@ -85,9 +85,17 @@ template <typename T, int NL, int R>
 constexpr bool stage_all() {
   return sizeof(T) == 8 || R == 0 || R > 8;
 }
+// f16 outputs: the last level's product loop is not unrolled (its coefficients
+// staged with the rest): N = 4096, Strassen Q = 2, the f16 gathers went from 69
+// to 60.5 us.  For e4m3 outputs the same change freed the 138 spilled SGPRs but
+// was mixed (large products 5% faster, N <= 1024 3% slower), so they stay unrolled.
+template <int OUTF>
+constexpr bool gather_rolled() {
+  return OUTF == OUT_F16S;
+}
 template <typename T, int OUTF, int NL, int R>
 constexpr int gather_staged() {
-  return stage_all<T, NL, R>() ? NL : (OUTF != OUT_SAME && NL > 1 ? NL - 1 : 0);
+  return (stage_all<T, NL, R>() || gather_rolled<OUTF>()) ? NL : (OUTF != OUT_SAME && NL > 1 ? NL - 1 : 0);
 }
 template <typename T, int NL, int R>
 constexpr int scatter_staged() {
@@ -230,7 +238,7 @@ struct GatherEmit {
 // block (k, l) of this level occupying the SUB consecutive values at
 // (k * BC + l) * SUB.  R > 0 is the compiled product count, R == 0 reads it
 // from the level descriptor.
-template <typename T, int V, int NL, int BR, int BC, int R, int NS, int LT, typename Emit>
+template <typename T, int V, int NL, int BR, int BC, int R, int NS, bool ROLL, int LT, typename Emit>
 __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLevel* lev, const T* ct, int64_t idx,
                                              const Emit& emit) {
   if constexpr (LT == NL) {
@@ -241,7 +249,7 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
     const SideLevel& L = lev[LT];
     const int RR = R ? R : L.R;
     // Unroll only the innermost level's product loop, when R is compiled in and small.
-    constexpr int UNR = (R == 0 || R > 8 || LT + 1 < NL) ? 1 : R;
+    constexpr int UNR = (R == 0 || R > 8 || LT + 1 < NL || ROLL) ? 1 : R;
 #pragma unroll UNR
     for (int r = 0; r < RR; ++r) {
       if constexpr (UNR == 1 && RBC_LEVEL_BARRIER) __asm__ volatile("" ::: "memory");
@@ -265,7 +273,7 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
         }
         first = first && !nz;
       }
-      gather_level<T, V, NL, BR, BC, R, NS, LT + 1>(acc, lev, ct, idx * RR + r, emit);
+      gather_level<T, V, NL, BR, BC, R, NS, ROLL, LT + 1>(acc, lev, ct, idx * RR + r, emit);
     }
   }
 }
@@ -344,7 +352,7 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct,
   }
   const int64_t n_out = R ? ipow(R, NL) : p.lev[0].R;
   GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, exps, in * n_out};
-  gather_level<T, V, NL, BR, BC, R, gather_staged<T, OUTF, NL, R>(), 0>(v, p.lev, ct, in, e);
+  gather_level<T, V, NL, BR, BC, R, gather_staged<T, OUTF, NL, R>(), gather_rolled<OUTF>(), 0>(v, p.lev, ct, in, e);
 }
 
 // f16 outputs: held to 128 VGPRs (four workgroups per CU) without spills; at
