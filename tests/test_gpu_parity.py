@@ -471,6 +471,9 @@ def test_tail_split_tiles_give_the_same_bits(prec):
     (["strassen"] * 2, 300, 200, 500, 128),
     (["laderman", "strassen"], 700, 500, 900, 64),
     (["strassen"] * 4, 1024, 1024, 1024, 0),
+    (["strassen"] * 2, 300, 192, 500, 128),    # 128-tiles whose tail tiles take 16-k slabs
+    (["strassen", "naive:2,3,2"], 260, 300, 170, 64),  # non-square deepest level, one term each
+    (["naive:3,2,2", "naive:2,2,2"], 1000, 1000, 1000, 0),
 ])
 def test_leaf_gather_same_bits(names, M, K, N, tile):
     # The leaf product that forms its operands while loading them (deepest level's gather
