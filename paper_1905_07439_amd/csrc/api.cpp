@@ -249,6 +249,27 @@ rbc_status run_gather(Ctx& c, int which, const void* X, int64_t ldx, bool leaf_g
   return RBC_OK;
 }
 
+// The gathers of A and B, each level group's two sides in one launch (the
+// per-side order of the groups is kept; the sides are independent).
+rbc_status run_gathers(Ctx& c, const void* A, int64_t lda, const void* B, int64_t ldb, bool leaf_gather) {
+  std::vector<ScaleLaunch> sa, sb;
+  std::vector<GatherLaunch> ga, gb;
+  build_gather(c.p, c.dr, 0, A, lda, c.ws, sa, ga, leaf_gather);
+  build_gather(c.p, c.dr, 1, B, ldb, c.ws, sb, gb, leaf_gather);
+  for (const std::vector<ScaleLaunch>* v : {&sa, &sb})
+    for (const ScaleLaunch& l : *v) {
+      hipError_t e = launch(l, c.stream);
+      if (e != hipSuccess) return fail(RBC_EHIP, "scale launch: %s", hipGetErrorString(e));
+    }
+  for (size_t i = 0; i < ga.size() || i < gb.size(); ++i) {
+    hipError_t e = hipSuccess;
+    if (i < ga.size() && i < gb.size()) e = launch(ga[i], gb[i], c.stream);
+    else e = launch(i < ga.size() ? ga[i] : gb[i], c.stream);
+    if (e != hipSuccess) return fail(RBC_EHIP, "gather launch: %s", hipGetErrorString(e));
+  }
+  return RBC_OK;
+}
+
 rbc_status run_leaf(Ctx& c, bool leaf_gather = false) {
   hipError_t e = leaf_gather ? launch(build_leaf_gather(c.p, c.dr, c.ws), c.stream)
                              : launch(build_leaf(c.p, c.ws), c.stream);
@@ -291,9 +312,13 @@ rbc_status matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, int64
   if (p.timing && p.recorded >= 4096) return fail(RBC_ENOMEM, "timing buffer full; collect first");
   const bool lg = p.leaf_gather;
   if ((st = record(p, c.stream, 0)) != RBC_OK) return st;
-  if ((st = run_gather(c, 0, A, lda, lg)) != RBC_OK) return st;
-  if ((st = record(p, c.stream, 1)) != RBC_OK) return st;
-  if ((st = run_gather(c, 1, B, ldb, lg)) != RBC_OK) return st;
+  if (p.timing) {  // separate launches, so that the events time A and B apart
+    if ((st = run_gather(c, 0, A, lda, lg)) != RBC_OK) return st;
+    if ((st = record(p, c.stream, 1)) != RBC_OK) return st;
+    if ((st = run_gather(c, 1, B, ldb, lg)) != RBC_OK) return st;
+  } else if ((st = run_gathers(c, A, lda, B, ldb, lg)) != RBC_OK) {
+    return st;
+  }
   if ((st = record(p, c.stream, 2)) != RBC_OK) return st;
   if ((st = run_leaf(c, lg)) != RBC_OK) return st;
   if ((st = record(p, c.stream, 3)) != RBC_OK) return st;

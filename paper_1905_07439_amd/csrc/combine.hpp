@@ -358,8 +358,12 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct,
 // f16 outputs: held to 128 VGPRs (four workgroups per CU) without spills; at
 // N = 4096, Q = 2 the f16 gather went from 60 to 51 us.  The e4m3 emission
 // spills at that bound, and two positions per thread were slower (71 us).
+// Two gathers of one shape in one grid (the A and B sides of a level group):
+// blockIdx.z selects the side; blocks past a side's positions or top blocks
+// do nothing.
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
-__global__ __launch_bounds__(256, OUTF == OUT_F16S ? 4 : 1) void k_gather(GatherParams p) {
+__global__ __launch_bounds__(256, OUTF == OUT_F16S ? 4 : 1) void k_gather(GatherParams pa, GatherParams pb) {
+  const GatherParams& p = blockIdx.z ? pb : pa;
   __shared__ T ct[gather_coef_entries<T, OUTF, NL, BR, BC, R>()];
   stage_gather_coefs<T, OUTF, NL, BR, BC, R>(p.lev, ct);
   if constexpr (OUTF == OUT_F16S || OUTF == OUT_FP8X2) {
@@ -475,9 +479,13 @@ inline dim3 grid_for(int64_t npos, int64_t nbatch) {
 }
 
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
-hipError_t run_gather(const GatherParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((k_gather<T, OUTF, V, NL, BR, BC, R>),
-                     grid_for(p.rows_bot * p.cols_bot / V, p.n_in), dim3(256), 0, s, p);
+hipError_t run_gather(const GatherPair& pp, hipStream_t s) {
+  const GatherParams& a = pp.a;
+  const GatherParams& b = pp.sides == 2 ? pp.b : pp.a;
+  const int64_t na = a.rows_bot * a.cols_bot / V, nb = b.rows_bot * b.cols_bot / V;
+  dim3 g = grid_for(na > nb ? na : nb, a.n_in > b.n_in ? a.n_in : b.n_in);
+  g.z = pp.sides == 2 ? 2 : 1;
+  hipLaunchKernelGGL((k_gather<T, OUTF, V, NL, BR, BC, R>), g, dim3(256), 0, s, a, b);
   return hipGetLastError();
 }
 
@@ -511,7 +519,7 @@ template <typename T, int OUTF, int V>
 struct GatherOf {
   template <int NL, int BR, int BC, int R>
   struct F {
-    static hipError_t run(const GatherParams& p, hipStream_t s) {
+    static hipError_t run(const GatherPair& p, hipStream_t s) {
       return run_gather<T, OUTF, V, NL, BR, BC, R>(p, s);
     }
   };
@@ -530,7 +538,7 @@ struct ScatterOf {
 // vec: positions per thread (1, 2 or 4), chosen by the host from the
 // alignment of every pointer, leading dimension and block stride involved.
 template <typename T, int OUTF>
-hipError_t gather_dispatch(int vec, int nl, int br, int bc, int R, const GatherParams& p, hipStream_t s) {
+hipError_t gather_dispatch(int vec, int nl, int br, int bc, int R, const GatherPair& p, hipStream_t s) {
   if (vec == 4) return dispatch_shape<GatherOf<T, OUTF, 4>::template F>(nl, br, bc, R, p, s);
   if (vec == 2) return dispatch_shape<GatherOf<T, OUTF, 2>::template F>(nl, br, bc, R, p, s);
   return dispatch_shape<GatherOf<T, OUTF, 1>::template F>(nl, br, bc, R, p, s);
@@ -551,7 +559,7 @@ hipError_t scatter_dispatch(int vec, int nl, int br, int bc, int R, const Scatte
   X(float, double, float) X(double, double, float)
 
 #define RBC_DECL_G(T, O)                                                                   \
-  extern template hipError_t gather_dispatch<T, O>(int, int, int, int, int, const GatherParams&, \
+  extern template hipError_t gather_dispatch<T, O>(int, int, int, int, int, const GatherPair&, \
                                                    hipStream_t);
 #define RBC_DECL_S(A, B, C)                                                                          \
   extern template hipError_t scatter_dispatch<A, B, C>(int, int, int, int, int, const ScatterParams&, \

@@ -3,6 +3,6 @@
 
 namespace rbc {
 namespace comb {
-template hipError_t gather_dispatch<double, OUT_SAME>(int, int, int, int, int, const GatherParams&, hipStream_t);
+template hipError_t gather_dispatch<double, OUT_SAME>(int, int, int, int, int, const GatherPair&, hipStream_t);
 }  // namespace comb
 }  // namespace rbc

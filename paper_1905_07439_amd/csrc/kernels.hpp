@@ -38,6 +38,13 @@ struct GatherParams {
   SideLevel lev[kMaxGroupLevels];
 };
 
+// One gather launch: side a alone (sides = 1), or the A and B sides of a
+// level group together (sides = 2; same element type, output, shape and vec).
+struct GatherPair {
+  GatherParams a, b;
+  int sides;
+};
+
 // Scatter of one group: Rg bottom blocks per top block are combined through W.
 struct ScatterParams {
   const void* src;
@@ -74,6 +81,9 @@ enum Elt { ELT_F32 = 0, ELT_F64 = 1 };
 // dimension and block stride of the launch must be a multiple of it.
 hipError_t launch_gather(Elt elt, GatherOut out, int vec, int nl, int br, int bc, int R,
                          const GatherParams& p, hipStream_t stream);
+// The same for two gathers of one shape in one launch (pb: the second side).
+hipError_t launch_gather2(Elt elt, GatherOut out, int vec, int nl, int br, int bc, int R,
+                          const GatherParams& pa, const GatherParams& pb, hipStream_t stream);
 // tp: product element type, ta: accumulation type, to: output element type
 hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int vec, int nl, int br, int bc, int R,
                           const ScatterParams& p, hipStream_t stream);

@@ -305,6 +305,16 @@ hipError_t launch(const GatherLaunch& l, hipStream_t s) {
   return launch_gather(l.elt, l.out, l.vec, l.nl, l.br, l.bc, l.R, l.p, s);
 }
 
+hipError_t launch(const GatherLaunch& a, const GatherLaunch& b, hipStream_t s) {
+  if (a.elt != b.elt || a.out != b.out || a.nl != b.nl || a.br != b.br || a.bc != b.bc || a.R != b.R) {
+    hipError_t e = launch(a, s);
+    return e != hipSuccess ? e : launch(b, s);
+  }
+  // any narrower vec than the host picked for a side is valid for it
+  const int vec = a.vec < b.vec ? a.vec : b.vec;
+  return launch_gather2(a.elt, a.out, vec, a.nl, a.br, a.bc, a.R, a.p, b.p, s);
+}
+
 hipError_t launch(const LeafLaunch& l, hipStream_t s) {
   switch (l.prec) {
     case RBC_PREC_F64:

@@ -78,6 +78,9 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
 
 hipError_t launch(const ScaleLaunch& l, hipStream_t s);
 hipError_t launch(const GatherLaunch& l, hipStream_t s);
+// Two gathers in one launch when they share element type, output and shape
+// (else one after the other); the same results either way.
+hipError_t launch(const GatherLaunch& a, const GatherLaunch& b, hipStream_t s);
 hipError_t launch(const LeafLaunch& l, hipStream_t s);
 hipError_t launch(const LeafGatherLaunch& l, hipStream_t s);
 hipError_t launch(const ScatterLaunch& l, hipStream_t s);

@@ -494,3 +494,33 @@ def test_leaf_gather_same_bits(names, M, K, N, tile):
         torch.cuda.synchronize()
         assert torch.equal(C1, C2), (seed, mode, float((C1 - C2).abs().max()))
     assert plan.leaf_gather == (False, True)
+
+
+@pytest.mark.parametrize("prec,names,M,K,N", [
+    ("f32", ["strassen"] * 2, 300, 200, 500),
+    ("f32", ["laderman", "strassen"], 700, 500, 900),
+    ("f64", ["strassen"] * 2, 64, 64, 64),
+    ("f16s", ["strassen"] * 2, 520, 260, 1030),
+    ("fp8c", ["laderman"], 390, 700, 200),
+    ("bf16x3", ["strassen"] * 2, 256, 192, 320),
+])
+def test_paired_gathers_same_bits(prec, names, M, K, N):
+    # Without stage timing the A and B gathers of each level group share one launch (the grid
+    # spans the larger side; the other side's extra blocks do nothing); with timing they run
+    # apart.  C must be the same bits.
+    _say("paired gathers", prec, names, M, K, N)
+    lib_s, _ = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec=prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = torch.Generator(device=DEV)
+    g.manual_seed(77)
+    A = torch.randn(M, K, device=DEV, generator=g, dtype=dt)
+    B = torch.randn(K, N, device=DEV, generator=g, dtype=dt)
+    for seed in (0, 3):
+        C1 = plan.matmul(A, B, seed=seed)
+        plan.set_timing(True)
+        C2 = plan.matmul(A, B, seed=seed)
+        plan.set_timing(False)
+        plan.timing_collect()
+        torch.cuda.synchronize()
+        assert torch.equal(C1, C2), (seed, float((C1 - C2).abs().max()))
