@@ -256,11 +256,16 @@ rbc_status run_gathers(Ctx& c, const void* A, int64_t lda, const void* B, int64_
   std::vector<GatherLaunch> ga, gb;
   build_gather(c.p, c.dr, 0, A, lda, c.ws, sa, ga, leaf_gather);
   build_gather(c.p, c.dr, 1, B, ldb, c.ws, sb, gb, leaf_gather);
-  for (const std::vector<ScaleLaunch>* v : {&sa, &sb})
-    for (const ScaleLaunch& l : *v) {
-      hipError_t e = launch(l, c.stream);
-      if (e != hipSuccess) return fail(RBC_EHIP, "scale launch: %s", hipGetErrorString(e));
-    }
+  if (sa.size() == 1 && sb.size() == 1) {
+    hipError_t e = launch(sa[0], sb[0], c.stream);
+    if (e != hipSuccess) return fail(RBC_EHIP, "scale launch: %s", hipGetErrorString(e));
+  } else {
+    for (const std::vector<ScaleLaunch>* v : {&sa, &sb})
+      for (const ScaleLaunch& l : *v) {
+        hipError_t e = launch(l, c.stream);
+        if (e != hipSuccess) return fail(RBC_EHIP, "scale launch: %s", hipGetErrorString(e));
+      }
+  }
   for (size_t i = 0; i < ga.size() || i < gb.size(); ++i) {
     hipError_t e = hipSuccess;
     if (i < ga.size() && i < gb.size()) e = launch(ga[i], gb[i], c.stream);

@@ -124,5 +124,8 @@ inline int maxabs_blocks(int64_t rows, int64_t cols) {
   return (int)(b < 1 ? 1 : b);
 }
 hipError_t launch_maxabs(const float* X, int64_t ld, int64_t rows, int64_t cols, float* partial, hipStream_t s);
+// The same for two matrices in one launch.
+hipError_t launch_maxabs2(const float* XA, int64_t lda, int64_t ra, int64_t ca, float* pa, const float* XB,
+                          int64_t ldb, int64_t rb, int64_t cb, float* pb, hipStream_t s);
 
 }  // namespace rbc

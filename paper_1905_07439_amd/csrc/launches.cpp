@@ -301,6 +301,10 @@ hipError_t launch(const ScaleLaunch& l, hipStream_t s) {
   return launch_maxabs(l.X, l.ld, l.rows, l.cols, l.partial, s);
 }
 
+hipError_t launch(const ScaleLaunch& a, const ScaleLaunch& b, hipStream_t s) {
+  return launch_maxabs2(a.X, a.ld, a.rows, a.cols, a.partial, b.X, b.ld, b.rows, b.cols, b.partial, s);
+}
+
 hipError_t launch(const GatherLaunch& l, hipStream_t s) {
   return launch_gather(l.elt, l.out, l.vec, l.nl, l.br, l.bc, l.R, l.p, s);
 }

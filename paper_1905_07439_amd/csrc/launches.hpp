@@ -77,6 +77,7 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
                    std::vector<ScatterLaunch>& out);
 
 hipError_t launch(const ScaleLaunch& l, hipStream_t s);
+hipError_t launch(const ScaleLaunch& a, const ScaleLaunch& b, hipStream_t s);  // both in one launch
 hipError_t launch(const GatherLaunch& l, hipStream_t s);
 // Two gathers in one launch when they share element type, output and shape
 // (else one after the other); the same results either way.
