@@ -355,15 +355,9 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct,
   gather_level<T, V, NL, BR, BC, R, gather_staged<T, OUTF, NL, R>(), gather_rolled<OUTF>(), 0>(v, p.lev, ct, in, e);
 }
 
-// f16 outputs: held to 128 VGPRs (four workgroups per CU) without spills; at
-// N = 4096, Q = 2 the f16 gather went from 60 to 51 us.  The e4m3 emission
-// spills at that bound, and two positions per thread were slower (71 us).
-// Two gathers of one shape in one grid (the A and B sides of a level group):
-// blockIdx.z selects the side; blocks past a side's positions or top blocks
-// do nothing.
+// One side's share of a gather launch.
 template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
-__global__ __launch_bounds__(256, OUTF == OUT_F16S ? 4 : 1) void k_gather(GatherParams pa, GatherParams pb) {
-  const GatherParams& p = blockIdx.z ? pb : pa;
+__device__ __forceinline__ void gather_side(const GatherParams& p) {
   __shared__ T ct[gather_coef_entries<T, OUTF, NL, BR, BC, R>()];
   stage_gather_coefs<T, OUTF, NL, BR, BC, R>(p.lev, ct);
   if constexpr (OUTF == OUT_F16S || OUTF == OUT_FP8X2) {
@@ -377,6 +371,22 @@ __global__ __launch_bounds__(256, OUTF == OUT_F16S ? 4 : 1) void k_gather(Gather
     for (int64_t in = blockIdx.y; in < p.n_in; in += gridDim.y)
       gather_block<T, OUTF, V, NL, BR, BC, R>(p, ct, blockIdx.x, in, nullptr);
   }
+}
+
+// Two gathers of one shape in one grid (the A and B sides of a level group):
+// blockIdx.z selects the side; blocks past a side's positions or top blocks
+// do nothing.  Each branch reads its own parameter block where it lies (a
+// reference chosen between the two at run time made the compiler copy both
+// into scratch memory).
+// f16 outputs: held to 128 VGPRs (four workgroups per CU) without spills; at
+// N = 4096, Q = 2 the f16 gather went from 60 to 51 us.  The e4m3 emission
+// spills at that bound, and two positions per thread were slower (71 us).
+template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
+__global__ __launch_bounds__(256, OUTF == OUT_F16S ? 4 : 1) void k_gather(GatherParams pa, GatherParams pb) {
+  if (blockIdx.z == 0)
+    gather_side<T, OUTF, V, NL, BR, BC, R>(pa);
+  else
+    gather_side<T, OUTF, V, NL, BR, BC, R>(pb);
 }
 
 // Level LT of a scatter group: returns in `out` the BB^(NL-LT) values of the

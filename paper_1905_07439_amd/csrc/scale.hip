@@ -17,10 +17,7 @@ struct MaxAbsSide {
   int32_t blocks;  // workgroups of this side = partial maxima it writes
 };
 
-// One or two matrices (blockIdx.y selects the side; blocks past a side's count
-// do nothing).
-__global__ __launch_bounds__(256) void k_maxabs(MaxAbsSide a, MaxAbsSide b) {
-  const MaxAbsSide& p = blockIdx.y ? b : a;
+__device__ __forceinline__ void maxabs_side(const MaxAbsSide& p) {
   if ((int)blockIdx.x >= p.blocks) return;  // whole workgroup
   // a contiguous range of rows per workgroup, one partial maximum each
   const int64_t per = (p.rows + p.blocks - 1) / p.blocks;
@@ -28,6 +25,15 @@ __global__ __launch_bounds__(256) void k_maxabs(MaxAbsSide a, MaxAbsSide b) {
   const int64_t nr = r0 < p.rows ? (p.rows - r0 < per ? p.rows - r0 : per) : 0;
   const float m = scale::block_max(scale::maxabs_rows(p.X, p.ld, p.cols, r0, nr));
   if (threadIdx.x == 0) global_ptr(p.partial)[blockIdx.x] = m;
+}
+
+// One or two matrices (blockIdx.y selects the side, each branch reading its
+// own argument in place; blocks past a side's count do nothing).
+__global__ __launch_bounds__(256) void k_maxabs(MaxAbsSide a, MaxAbsSide b) {
+  if (blockIdx.y == 0)
+    maxabs_side(a);
+  else
+    maxabs_side(b);
 }
 
 MaxAbsSide side(const float* X, int64_t ld, int64_t rows, int64_t cols, float* partial) {
