@@ -49,6 +49,26 @@ static bool same_shape(const Scheme& a, const Scheme& b) {
 // that the boundaries between passes sit where the intermediate blocks are
 // fewest, with their block dimensions (bottom blocks of levels below d_end
 // included: the leaves are always mM x mK and mK x mN).
+// Levels [d, g_d1) fused into one pass give each thread R_d times the sequential
+// work of the pass below; that pays only when the pass has enough parallel work:
+// (top blocks entering the pass) x (elements of one bottom block), the larger of
+// the A and B sides, at least 2^18.  Measured (products per second, Strassen):
+// below it one-level passes won (f64 N = 256, Q = 3: 54.5 -> 34.9 us; fp8c N = 512,
+// Q = 2: 38.6 -> 28.5 us; f32 N = 1024, Q = 3: 74.4 -> 64.5 us), from it on the fused
+// pass won (fp8c N = 2048, Q = 2: 91.7 vs 109.5 us; f16s 89 vs 109 us; f32 N = 4096,
+// Q = 2: 977 vs 1054 us; Q = 3 at N = 2048: 203 vs 231 us).  RBC_MAX_FUSED_LEVELS set
+// in the environment overrides the rule.
+static bool enough_work(const Plan& p, int d, int g_d1) {
+  if (std::getenv("RBC_MAX_FUSED_LEVELS")) return true;
+  double n_in = 1, a = (double)p.mM * p.mK, b = (double)p.mK * p.mN;
+  for (int e = 0; e < d; ++e) n_in *= p.levels[e].R;
+  for (int e = g_d1; e < p.Q; ++e) {
+    const Scheme& s = p.levels[e];
+    a *= (double)s.b1 * s.b2, b *= (double)s.b2 * s.b3;
+  }
+  return n_in * (a > b ? a : b) >= 262144.0;
+}
+
 static std::vector<Group> form_groups(const Plan& p, int d_end) {
   const std::vector<Scheme>& levels = p.levels;
   std::vector<Group> gs;
@@ -58,7 +78,8 @@ static std::vector<Group> form_groups(const Plan& p, int d_end) {
     if (!gs.empty()) {
       Group& g = gs.back();  // the group just below, levels [g.d0, g.d1)
       const int nl = g.d1 - g.d0 + 1;
-      if (nl <= max_nl && same_shape(s, levels[g.d0]) && fused_supported(s.b1, s.b2, s.b3, s.R, nl)) {
+      if (nl <= max_nl && same_shape(s, levels[g.d0]) && fused_supported(s.b1, s.b2, s.b3, s.R, nl) &&
+          enough_work(p, d, g.d1)) {
         g.d0 = d;
         continue;
       }

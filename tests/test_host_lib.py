@@ -144,6 +144,19 @@ def test_plan_geometry():
     assert tz["gather_A"] == 100 * 50 * 4 + 128 * 64 * 4 and tz["scatter"] == 128 * 64 * 4 + 100 * 30 * 4
 
 
+def test_fusion_needs_parallel_work():
+    # Two levels share one combination pass only when the pass has at least 2^18 elements of
+    # parallel work (top blocks entering it x bottom-block elements); smaller products take one
+    # pass per level.
+    if os.environ.get("RBC_MAX_FUSED_LEVELS"):
+        pytest.skip("the environment fixes the fusion depth")
+    S = rbc.Scheme.builtin("strassen")
+    cases = [("f64", 64, 2, 2), ("f32", 1024, 2, 2), ("f32", 1024, 3, 3), ("fp8c", 1024, 2, 2),
+             ("f32", 2048, 2, 1), ("fp8c", 2048, 2, 1), ("f32", 2048, 3, 2), ("f32", 4096, 3, 2), ("f32", 4096, 2, 1)]
+    for prec, n, q, groups in cases:
+        assert rbc.Plan(n, n, n, [S] * q, prec=prec).info["n_groups"] == groups, (prec, n, q)
+
+
 def test_f16s_plan_geometry():
     L = rbc.Scheme.builtin("laderman")
     S = rbc.Scheme.builtin("strassen")
