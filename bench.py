@@ -212,7 +212,7 @@ def batch512(args):
         lv = batch_levels(n)
         if n not in plans16:
             sch = [L] + [S] * (len(lv) - 1)
-            plans16[n] = rbc.Plan(n, n, n, sch, prec="f16s")
+            plans16[n] = rbc.Plan(n, n, n, sch, prec="f16s", fusion="max")  # batch plans: fewest passes
             plans32[n] = rbc.Plan(n, n, n, sch, prec="f32")
         fa = 10.0 ** np.random.default_rng(4000 + i).uniform(-3, 3)
         fb = 10.0 ** np.random.default_rng(14000 + i).uniform(-3, 3)

@@ -191,6 +191,15 @@ rbc_status rbc_plan_traffic(rbc_plan p, double bytes[4]);
  * RBC_EUNSUPPORTED for a plan that does not qualify.  get: whether it is on
  * and whether the plan qualifies (either pointer may be NULL). */
 rbc_status rbc_plan_set_leaf_gather(rbc_plan p, int on);
+/* Level fusion (how the recursion's levels are grouped into combination passes).
+ * By default (fuse_max = 0) two levels share a pass only when that pass has at
+ * least 2^18 elements of parallel work (top blocks entering it x elements of a
+ * bottom block); smaller products take one pass per level, which is faster for
+ * them alone.  fuse_max = 1 fuses wherever the shapes allow (for batches: many
+ * products share the GPU, and fewer, larger tasks pay).  Changing it re-lays
+ * out the workspace (query rbc_plan_get_info again) and resets the leaf
+ * gather to its default; the results are the same either way. */
+rbc_status rbc_plan_set_fusion(rbc_plan p, int fuse_max);
 rbc_status rbc_plan_get_leaf_gather(rbc_plan p, int* on, int* available);
 void rbc_plan_destroy(rbc_plan p);
 

@@ -134,13 +134,20 @@ def _ptr(t):
 class Plan:
     """A plan for C = F-hat^(Q)(A, B) with A of size M x K and B of size K x N."""
 
-    def __init__(self, M, K, N, schemes, prec="f32", leaf_tile=0):
+    def __init__(self, M, K, N, schemes, prec="f32", leaf_tile=0, fusion="auto"):
+        """fusion: "auto" (two levels share a combination pass only with enough parallel work) or
+        "max" (fuse wherever the shapes allow; for products run in a batch)."""
+        if fusion not in ("auto", "max"):
+            raise ValueError("fusion must be 'auto' or 'max'")
         self.schemes = list(schemes)
         arr = (ctypes.c_void_p * max(1, len(self.schemes)))(*[s._h.value for s in self.schemes])
         h = ctypes.c_void_p()
         check(lib().rbc_plan_create(M, K, N, len(self.schemes), arr, PRECS[prec], leaf_tile, ctypes.byref(h)))
         self._h = h
         self.prec = prec
+        if fusion == "max":
+            check(lib().rbc_plan_set_fusion(self._h, 1))
+        self.fusion = fusion
         inf = PlanInfo()
         check(lib().rbc_plan_get_info(self._h, ctypes.byref(inf)))
         self.info = inf.as_dict()

@@ -460,6 +460,23 @@ rbc_status rbc_plan_set_timing(rbc_plan h, int on) {
   return RBC_OK;
 }
 
+rbc_status rbc_plan_set_fusion(rbc_plan h, int fuse_max) {
+  RBC_GUARD_BEGIN
+  if (!h) return fail(RBC_EINVAL, "null plan");
+  Plan& p = h->p;
+  if (p.fuse_max == (fuse_max != 0)) return RBC_OK;
+  Plan q;
+  rbc_status st = make_plan(p.M, p.K, p.N, p.levels, p.prec, p.tile_m, q, fuse_max != 0);
+  if (st != RBC_OK) return st;
+  // the device tables and events do not depend on the grouping
+  q.device = p.device, q.dev_tables = p.dev_tables, q.tab_off = p.tab_off;
+  q.timing = p.timing, q.events = std::move(p.events), q.recorded = p.recorded;
+  p.dev_tables = nullptr;
+  p = std::move(q);
+  return RBC_OK;
+  RBC_GUARD_END
+}
+
 rbc_status rbc_plan_set_leaf_gather(rbc_plan h, int on) {
   if (!h) return fail(RBC_EINVAL, "null plan");
   if (on && !h->p.leaf_gather_ok)

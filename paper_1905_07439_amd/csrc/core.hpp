@@ -110,6 +110,7 @@ struct Plan {
   // fgroups then gather levels [0, Q - 1) (the last one's bottom blocks, the
   // parents of the leaves, at off_S and off_T when they fit there); the stage
   // calls and the batch engine keep the separate gather of every level.
+  bool fuse_max = false;         // fuse levels regardless of the pass's parallel work
   bool leaf_gather_ok = false;   // the plan qualifies
   bool leaf_gather = false;      // rbc_matmul takes that path
   std::vector<Group> fgroups;
@@ -127,8 +128,10 @@ struct Plan {
 // Is a fused group of `nl` levels of shape <b1,b2,b3> with R products compiled?
 bool fused_supported(int b1, int b2, int b3, int R, int nl);
 
+// fuse_max: fuse up to the most levels per pass even where a pass has little
+// parallel work (for batches, where many products share the GPU).
 rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>& levels,
-                     rbc_prec prec, int leaf_tile, Plan& out);
+                     rbc_prec prec, int leaf_tile, Plan& out, bool fuse_max = false);
 
 // Table index helpers into Plan::tab_off (per level, 8 entries).
 enum TabKind { TAB_U = 0, TAB_V = 1, TAB_W = 2, TAB_WK = 3 };

@@ -59,7 +59,7 @@ static bool same_shape(const Scheme& a, const Scheme& b) {
 // Q = 2: 977 vs 1054 us; Q = 3 at N = 2048: 203 vs 231 us).  RBC_MAX_FUSED_LEVELS set
 // in the environment overrides the rule.
 static bool enough_work(const Plan& p, int d, int g_d1) {
-  if (std::getenv("RBC_MAX_FUSED_LEVELS")) return true;
+  if (p.fuse_max || std::getenv("RBC_MAX_FUSED_LEVELS")) return true;
   double n_in = 1, a = (double)p.mM * p.mK, b = (double)p.mK * p.mN;
   for (int e = 0; e < d; ++e) n_in *= p.levels[e].R;
   for (int e = g_d1; e < p.Q; ++e) {
@@ -161,7 +161,7 @@ static bool leaf_gather_pays(const Plan& p) {
 }
 
 rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>& levels,
-                     rbc_prec prec, int leaf_tile, Plan& out) {
+                     rbc_prec prec, int leaf_tile, Plan& out, bool fuse_max) {
   if (M < 1 || K < 1 || N < 1) return fail(RBC_EINVAL, "empty product %lldx%lldx%lld", (long long)M,
                                           (long long)K, (long long)N);
   if ((int)levels.size() > kMaxLevels) return fail(RBC_EINVAL, "at most %d levels", kMaxLevels);
@@ -173,6 +173,7 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   p.Q = (int)levels.size();
   p.prec = prec;
   p.levels = levels;
+  p.fuse_max = fuse_max;
 
   int64_t P1 = 1, P2 = 1, P3 = 1;
   p.n_leaves = 1;

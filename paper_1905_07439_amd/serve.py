@@ -199,7 +199,9 @@ class GpuExecutor:
                 lv = [self.schemes[r.scheme]] * q
             else:
                 lv = [self.schemes[s] for s in levels_for(r.n, r.scheme)]
-            self.plans[key] = self.rbc.Plan(r.n, r.n, r.n, lv, prec=self.prec)
+            # products that run inside a batch launch take the fewest passes
+            self.plans[key] = self.rbc.Plan(r.n, r.n, r.n, lv, prec=self.prec,
+                                            fusion="max" if self.mode == "batch" else "auto")
         return self.plans[key]
 
     def tune(self, schemes=SCHEMES, grid=(256, 512, 1024, 2048, 4096)):

@@ -524,3 +524,23 @@ def test_paired_gathers_same_bits(prec, names, M, K, N):
         plan.timing_collect()
         torch.cuda.synchronize()
         assert torch.equal(C1, C2), (seed, float((C1 - C2).abs().max()))
+
+
+@pytest.mark.parametrize("prec,n,q", [("f64", 64, 2), ("fp8c", 1024, 3), ("f16s", 512, 2), ("f32", 1024, 3)])
+def test_fusion_choice_same_bits(prec, n, q):
+    # One pass per level (the default for small products) or fused passes: the same
+    # arithmetic per level, so the same bits.
+    _say("fusion choice", prec, n, q)
+    S = rbc.Scheme.builtin("strassen")
+    a = rbc.Plan(n, n, n, [S] * q, prec=prec)
+    m = rbc.Plan(n, n, n, [S] * q, prec=prec, fusion="max")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = torch.Generator(device=DEV)
+    g.manual_seed(n + q)
+    A = torch.randn(n, n, device=DEV, generator=g, dtype=dt)
+    B = torch.randn(n, n, device=DEV, generator=g, dtype=dt)
+    for seed in (0, 9):
+        C1 = a.matmul(A, B, seed=seed)
+        C2 = m.matmul(A, B, seed=seed)
+        torch.cuda.synchronize()
+        assert torch.equal(C1, C2), (seed, float((C1 - C2).abs().max()))

@@ -157,6 +157,22 @@ def test_fusion_needs_parallel_work():
         assert rbc.Plan(n, n, n, [S] * q, prec=prec).info["n_groups"] == groups, (prec, n, q)
 
 
+def test_fusion_max_option():
+    if os.environ.get("RBC_MAX_FUSED_LEVELS"):
+        pytest.skip("the environment fixes the fusion depth")
+    S = rbc.Scheme.builtin("strassen")
+    a = rbc.Plan(1024, 1024, 1024, [S] * 3, prec="fp8c")
+    m = rbc.Plan(1024, 1024, 1024, [S] * 3, prec="fp8c", fusion="max")
+    assert a.info["n_groups"] == 3 and m.info["n_groups"] == 2
+    assert m.info["n_leaves"] == a.info["n_leaves"] and m.info["mM"] == a.info["mM"]
+    # fewer group boundaries: fewer intermediate bytes
+    assert m.traffic()["gather_A"] < a.traffic()["gather_A"]
+    with pytest.raises(ValueError):
+        rbc.Plan(64, 64, 64, [S], fusion="some")
+    L = rbc.lib()
+    assert L.rbc_plan_set_fusion(a._h, 1) == 0 and L.rbc_plan_set_fusion(a._h, 0) == 0
+
+
 def test_f16s_plan_geometry():
     L = rbc.Scheme.builtin("laderman")
     S = rbc.Scheme.builtin("strassen")
