@@ -13,6 +13,7 @@ from those parent blocks while loading them.  Prints one JSON line.
     python bench.py --workload approx3072     # approximate scheme, bf16 hi+lo leaves
     python bench.py --workload batch512       # 512 products of mixed N in one persistent launch
     python bench.py --workload serve          # Poisson request stream, fp8 leaves, p50/p99 latency
+    python bench.py --workload peaks          # measured ceilings: streaming copy, MFMA loops per dtype
     python bench.py --copy-calibration BYTES  # plain copy of known size (counter scale)
 """
 
@@ -126,6 +127,61 @@ def approx3072(args):
            "unit": "TFLOP/s", "n_gpus": 1, "dtype": "bf16x3 leaves / f32 comparator", "data": "synthetic",
            "config": {"workload": "perturbed Strassen (sigma=lambda) Q=3, N=3072, N(0,1)", "n": n},
            "rows": rows, "standard_f32_gemm_same_gpu_ms": round(std_ms, 4)}
+    print(json.dumps(out), flush=True)
+
+
+def peaks(args):
+    """Measured ceilings on this GPU, for reading the rooflines against what the chip attains:
+    the library's streaming copy over 2 x 2 GiB (HBM bytes = 2 x the size) and its register-only
+    matrix-core loops per data type (2048 workgroups of 256 threads, 8 independent chains per
+    wavefront).  Median of 10 timed launches after 2 warm-ups, HIP events on one stream."""
+    import torch
+
+    import paper_1905_07439_amd as rbc
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    s = torch.cuda.current_stream()
+
+    def timed(fn, reps=10, warm=2):
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    nbytes = 2 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+    ms = timed(lambda: rbc.peak_copy(src, dst))
+    hbm = 2.0 * nbytes / (ms * 1e-3) / 1e9
+    ms_t = timed(lambda: dst.copy_(src))
+    hbm_torch = 2.0 * nbytes / (ms_t * 1e-3) / 1e9
+    del src, dst
+    sink = torch.empty(2048 * 256, dtype=torch.float32, device=dev)
+    published = {"f32": 157.3, "f64": 78.6, "f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32_32x32": 157.3,
+                 "f16_32x32": 2500.0, "bf16_32x32": 2500.0}
+    iters = {"f32": 4000, "f64": 4000, "f16": 2000, "bf16": 2000, "fp8": 1000, "f32_32x32": 4000,
+             "f16_32x32": 2000, "bf16_32x32": 2000}
+    mfma = {}
+    for kind in published:
+        fl = [0.0]
+
+        def run():
+            fl[0] = rbc.peak_mfma(kind, sink, iters[kind])
+        ms = timed(run)
+        tf = fl[0] / (ms * 1e-3) / 1e12
+        mfma[kind] = {"tflops": round(tf, 1), "published": published[kind], "frac": round(tf / published[kind], 3)}
+    out = {"metric": "measured ceilings (streaming copy, register-only MFMA loops)", "n_gpus": 1,
+           "hbm_copy_GBs": round(hbm, 1), "hbm_published_GBs": HBM_PEAK_GBS,
+           "hbm_frac": round(hbm / HBM_PEAK_GBS, 3), "hbm_torch_copy_GBs": round(hbm_torch, 1), "mfma": mfma}
     print(json.dumps(out), flush=True)
 
 
@@ -435,7 +491,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="strassen4096",
-                    choices=["strassen4096", "approx3072", "batch512", "serve", "small64"])
+                    choices=["strassen4096", "approx3072", "batch512", "serve", "small64", "peaks"])
     ap.add_argument("--small-reps", type=int, default=1000)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--batch-count", type=int, default=512)
@@ -456,6 +512,8 @@ def main():
         return serve_stream(args)
     if args.workload == "small64":
         return small64(args)
+    if args.workload == "peaks":
+        return peaks(args)
 
     import numpy as np
     import torch

@@ -267,6 +267,23 @@ rbc_status rbc_plan_set_timing(rbc_plan p, int on);
 rbc_status rbc_plan_timing_collect(rbc_plan p, double ms[4], int64_t* calls);
 
 
+/* ---- measured ceilings (for the rooflines) ----------------------------------
+ * rbc_peak_copy: dst = src, bytes a multiple of 16 and both 16-byte aligned
+ * (device pointers), on `stream`; the caller times it (HBM bytes moved:
+ * 2 x bytes).  rbc_peak_mfma: `blocks` workgroups of 256 threads each run
+ * `iters` rounds of independent matrix-core instructions of one type on
+ * register operands (f32: 16x16x4, f64: 16x16x4, f16 and bf16: 16x16x32, fp8
+ * e4m3: 32x32x64 at unit scale; the _32 kinds: f32 32x32x2, f16 and bf16
+ * 32x32x16); `sink` (device, blocks x 256 floats) receives one value per lane;
+ * *flops the floating-point operations launched.  Both return RBC_EINVAL for
+ * bad arguments and RBC_EHIP when the launch fails. */
+enum {
+  RBC_PEAK_F32 = 0, RBC_PEAK_F64 = 1, RBC_PEAK_F16 = 2, RBC_PEAK_BF16 = 3, RBC_PEAK_FP8 = 4,
+  RBC_PEAK_F32_32 = 5, RBC_PEAK_F16_32 = 6, RBC_PEAK_BF16_32 = 7
+};
+rbc_status rbc_peak_copy(const void* src, void* dst, size_t bytes, void* stream);
+rbc_status rbc_peak_mfma(int kind, int blocks, int iters, float* sink, double* flops, void* stream);
+
 /* ---- batches: many independent products in one persistent launch ---------
  * A batch holds products C_i = F-hat^(Q_i)(A_i, B_i), each with its own plan,
  * operands, seed and mode, all of one precision (RBC_PREC_F32,

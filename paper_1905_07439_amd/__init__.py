@@ -131,6 +131,28 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+PEAK_KINDS = {"f32": 0, "f64": 1, "f16": 2, "bf16": 3, "fp8": 4, "f32_32x32": 5, "f16_32x32": 6, "bf16_32x32": 7}
+
+
+def peak_copy(src, dst, stream=None):
+    """dst.copy_(src) by the library's streaming copy kernel (device tensors of equal byte size)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    check(lib().rbc_peak_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(),
+                              ctypes.c_void_p(st.cuda_stream)))
+
+
+def peak_mfma(kind, sink, iters, stream=None):
+    """Launch the register-only matrix-core loop of one data type ("f32", "f64", "f16", "bf16",
+    "fp8") with sink.numel() // 256 workgroups; returns the floating-point operations launched."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(sink.device)
+    fl = ctypes.c_double()
+    check(lib().rbc_peak_mfma(PEAK_KINDS[kind], sink.numel() // 256, iters, _ptr(sink), ctypes.byref(fl),
+                              ctypes.c_void_p(st.cuda_stream)))
+    return fl.value
+
+
 class Plan:
     """A plan for C = F-hat^(Q)(A, B) with A of size M x K and B of size K x N."""
 
