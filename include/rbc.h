@@ -309,7 +309,7 @@ typedef struct {
   int32_t grid;        /* workgroups of the persistent kernel (0: resident maximum) */
   int32_t timeout_ms;  /* limit of one dependency wait (0: 5000) */
   int32_t trace;       /* nonzero: record per-task timestamps (rbc_batch_trace) */
-  int64_t task_bytes;  /* HBM bytes one task aims to move (0: 2 MiB) */
+  int64_t task_bytes;  /* HBM bytes one task aims to move (0: 4 MiB) */
   int64_t item_budget; /* bytes for the products' stage buffers (0: one region per product).
                         * With a budget the regions form a ring: a product reuses the
                         * bytes of earlier ones and its first tasks wait until those

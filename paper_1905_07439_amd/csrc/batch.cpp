@@ -469,7 +469,7 @@ rbc_status build_items(rbc_batch_s& b, char* items_base, const std::vector<size_
   b.gparams.clear(), b.sparams.clear(), b.lparams.clear(), b.cparams.clear();
   b.cslots.clear();
   b.n_counters = 0;
-  Builder bl{b, b.opt.task_bytes > 0 ? b.opt.task_bytes : (int64_t)2 << 20};
+  Builder bl{b, b.opt.task_bytes > 0 ? b.opt.task_bytes : (int64_t)4 << 20};
   per.assign(b.items.size(), ItemTasks{});
   for (size_t i : order) {
     char* base = items_base ? items_base + offs[i] : nullptr;
