@@ -106,20 +106,21 @@ __global__ __launch_bounds__(256) void k_mfma(int iters, float seed, float* __re
 extern "C" {
 
 rbc_status rbc_peak_copy(const void* src, void* dst, size_t bytes, void* stream) {
-  if (!src || !dst) return RBC_EINVAL;
+  if (!src || !dst) return fail(RBC_EINVAL, "null buffer");
   if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
-    return RBC_EINVAL;
+    return fail(RBC_EINVAL, "copy of %zu bytes: size and both pointers must be multiples of 16", bytes);
   const int64_t n = (int64_t)(bytes / 16);
   if (n == 0) return RBC_OK;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                      static_cast<const f4*>(src), static_cast<f4*>(dst), n);
-  return hipGetLastError() == hipSuccess ? RBC_OK : RBC_EHIP;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RBC_OK : fail(RBC_EHIP, "copy launch: %s", hipGetErrorString(e));
 }
 
 rbc_status rbc_peak_mfma(int kind, int blocks, int iters, float* sink, double* flops, void* stream) {
-  if (!sink || blocks < 1 || iters < 1) return RBC_EINVAL;
+  if (!sink || blocks < 1 || iters < 1) return fail(RBC_EINVAL, "null sink or empty launch");
   const dim3 g((unsigned)blocks), b(256);
   const hipStream_t s = (hipStream_t)stream;
   double per;  // flops of one instruction
@@ -132,9 +133,10 @@ rbc_status rbc_peak_mfma(int kind, int blocks, int iters, float* sink, double* f
     case RBC_PEAK_F32_32: hipLaunchKernelGGL(k_mfma<RBC_PEAK_F32_32>, g, b, 0, s, iters, 1.0f, sink); per = 2.0 * 32 * 32 * 2; break;
     case RBC_PEAK_F16_32: hipLaunchKernelGGL(k_mfma<RBC_PEAK_F16_32>, g, b, 0, s, iters, 1.0f, sink); per = 2.0 * 32 * 32 * 16; break;
     case RBC_PEAK_BF16_32: hipLaunchKernelGGL(k_mfma<RBC_PEAK_BF16_32>, g, b, 0, s, iters, 1.0f, sink); per = 2.0 * 32 * 32 * 16; break;
-    default: return RBC_EINVAL;
+    default: return fail(RBC_EINVAL, "unknown matrix-core kind %d", kind);
   }
-  if (hipGetLastError() != hipSuccess) return RBC_EHIP;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RBC_EHIP, "matrix-core loop launch: %s", hipGetErrorString(e));
   const double waves = (double)blocks * 4, chains = (kind == RBC_PEAK_F32 || kind == RBC_PEAK_F64 || kind == RBC_PEAK_F16 ||
                                                     kind == RBC_PEAK_BF16) ? CH : CH / 2;
   if (flops) *flops = waves * iters * chains * per;

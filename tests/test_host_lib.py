@@ -272,3 +272,17 @@ def test_matmul_argument_errors_are_synchronous():
                             1 << 30, null)
     assert st == _lib.RBC_EINVAL
     assert b"draw" in L.rbc_last_error()
+
+
+def test_peak_argument_errors_are_synchronous():
+    # Argument checks of the measured-ceiling calls fire before any device call.
+    L = rbc.lib()
+    null = ctypes.c_void_p()
+    assert L.rbc_peak_copy(null, null, 16, null) == _lib.RBC_EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    assert L.rbc_peak_copy(fake, ctypes.c_void_p(0x1008), 16, null) == _lib.RBC_EINVAL
+    assert L.rbc_peak_copy(fake, fake, 15, null) == _lib.RBC_EINVAL
+    fl = ctypes.c_double()
+    assert L.rbc_peak_mfma(0, 0, 10, fake, ctypes.byref(fl), null) == _lib.RBC_EINVAL
+    assert L.rbc_peak_mfma(99, 1, 10, fake, ctypes.byref(fl), null) == _lib.RBC_EINVAL
+    assert b"kind" in L.rbc_last_error()
