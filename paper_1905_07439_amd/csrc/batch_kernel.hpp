@@ -204,6 +204,14 @@ __device__ __noinline__ void leader_signal(int32_t* ctl, int32_t t, int32_t sign
                                            uint64_t* trace) {
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // The fence writes the L2 back (buffer_wbl2), and the counter may only
+    // move once that write-back is done.  The compiler drops the wait that
+    // the fence needs after the write-back when no memory operation it
+    // tracks is outstanding (the caller has already waited for all of its
+    // own), so the wait is spelled out: without it a workgroup on another
+    // XCD can see the counter, invalidate its caches and still read the old
+    // bytes from memory.
+    __builtin_amdgcn_s_waitcnt(0);
     if (signal >= 0) atomicAdd(ctl + CTL_WORDS + signal, count);
     if (trace) trace[(int64_t)t * 4 + 2] = wall_clock64();
   }

@@ -155,6 +155,26 @@ def test_batch_options_ring_and_graph_replays():
                 assert torch.equal(it[5], w), (engine, rep)
 
 
+@pytest.mark.parametrize("prec,specs", [("f32", F32_SPECS), ("f16s", F16S_SPECS)])
+def test_batch_signals_publish_written_data(prec, specs):
+    """A counter moves only once its task's writes have left the producer's L2: with the stage
+    buffers filled with NaN bytes before every run, the smallest tasks (the most signals, the
+    most consumers on other XCDs) still give the bits of the products run alone."""
+    b, items = _build(prec, specs, "gauss", task_bytes=1 << 16, window=8)
+    ws = b.prepare()
+    ctl = b.info()["control_bytes"]
+    _say("signals", prec, b.info())
+    ref = _alone(items)
+    for rep in range(3):
+        ws[ctl:].fill_(0xFF)
+        for it in items:
+            it[5].fill_(float("nan"))
+        b.launch()
+        b.check()
+        for (plan, A, B, seed, mode, C), R in zip(items, ref):
+            assert torch.equal(C, R), (prec, rep, A.shape[0], seed, mode)
+
+
 def test_batch_reruns_and_check():
     b, items = _build("f32", F32_SPECS[:2], "gauss")
     b.prepare()
