@@ -11,7 +11,9 @@ natural extension the paper's footnote to Section 2.1 anticipates.
 Pins (tests/test_oracle_schemes.py): Strassen and Laderman satisfy the Brent
 equations (eq. requirement) exactly in int64 AND, independently, reproduce
 np.matmul on random integer matrices when evaluated as a plain bilinear
-computation; the perturbed scheme has tau = Theta(sigma).
+computation; the perturbed scheme has tau = Theta(sigma); the rank-10 <3,2,2>
+approximate scheme has, in exact rational arithmetic, a Brent residual with no
+constant term that halves with lam.
 """
 
 import numpy as np
@@ -147,10 +149,47 @@ def perturbed(U, V, W, sigma, rng, n_zero=5):
     return tuple(out)
 
 
-def _assemble(b1, b2, b3, R, a, b, c):
-    U = np.zeros((b1, b2, R), dtype=np.int64)
-    V = np.zeros((b2, b3, R), dtype=np.int64)
-    W = np.zeros((b1, b3, R), dtype=np.int64)
+def apa322(lam):
+    """Rank-10 approximate scheme for <3,2,2> blocks (the APA family of Section 1,
+    eq. APA-y: Y(lam) = X + O(lam), coefficients 1/lam in W).
+
+    The paper names such a scheme (Bini et al. 1979) without printing it.  This one
+    follows that construction: the 3x2 A is split into two 2x2 problems that each
+    miss one block (rows 1, 2 without A22, and rows 3, 2 without A21), each
+    computed approximately with five products, and the two share C's middle row:
+      P1  = (A12 + lam A11)(B12 + lam B22)   P6  = (A31 + lam A32)(B22 + lam B12)
+      P2  = (A21 + lam A11) B11              P7  = (A22 + lam A32) B21
+      P3  = A12 B12                          P8  = A31 B22
+      P4  = A21 (B11 + B12 + lam B21)        P9  = A22 (B21 + B22 + lam B11)
+      P5  = (A12 + A21)(B12 + lam B21)       P10 = (A31 + A22)(B22 + lam B11)
+      C11 = (P2 - P3 - P4 + P5) / lam        C12 = (P1 - P3) / lam
+      C21 = P2 + P7                          C22 = P5 - P3 + P10 - P8
+      C31 = (P7 - P8 - P9 + P10) / lam       C32 = (P6 - P8) / lam
+    C11 and C31 are exact; the other four carry an O(lam) error.  Returns float64
+    arrays of shapes (3,2,10), (2,2,10), (3,2,10).
+    """
+    lam = float(lam)
+    if not lam > 0.0:
+        raise ValueError("lam must be positive")
+    a = [[(1.0, 1, 2), (lam, 1, 1)], [(1.0, 2, 1), (lam, 1, 1)], [(1.0, 1, 2)], [(1.0, 2, 1)],
+         [(1.0, 1, 2), (1.0, 2, 1)],
+         [(1.0, 3, 1), (lam, 3, 2)], [(1.0, 2, 2), (lam, 3, 2)], [(1.0, 3, 1)], [(1.0, 2, 2)],
+         [(1.0, 3, 1), (1.0, 2, 2)]]
+    b = [[(1.0, 1, 2), (lam, 2, 2)], [(1.0, 1, 1)], [(1.0, 1, 2)], [(1.0, 1, 1), (1.0, 1, 2), (lam, 2, 1)],
+         [(1.0, 1, 2), (lam, 2, 1)],
+         [(1.0, 2, 2), (lam, 1, 2)], [(1.0, 2, 1)], [(1.0, 2, 2)], [(1.0, 2, 1), (1.0, 2, 2), (lam, 1, 1)],
+         [(1.0, 2, 2), (lam, 1, 1)]]
+    il = 1.0 / lam
+    c = {(1, 1): [(il, 2), (-il, 3), (-il, 4), (il, 5)], (1, 2): [(il, 1), (-il, 3)],
+         (2, 1): [(1.0, 2), (1.0, 7)], (2, 2): [(1.0, 5), (-1.0, 3), (1.0, 10), (-1.0, 8)],
+         (3, 1): [(il, 7), (-il, 8), (-il, 9), (il, 10)], (3, 2): [(il, 6), (-il, 8)]}
+    return _assemble(3, 2, 2, 10, a, b, c, dtype=np.float64)
+
+
+def _assemble(b1, b2, b3, R, a, b, c, dtype=np.int64):
+    U = np.zeros((b1, b2, R), dtype=dtype)
+    V = np.zeros((b2, b3, R), dtype=dtype)
+    W = np.zeros((b1, b3, R), dtype=dtype)
     for r in range(R):
         for coef, i, j in a[r]:
             U[i - 1, j - 1, r] = coef

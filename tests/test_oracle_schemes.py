@@ -62,3 +62,71 @@ def test_perturbed_scheme_touches_ones_and_five_zeros():
         assert np.all(changed[T0 == 1])
         assert np.sum(changed[T0 == 0]) == 5
         assert not np.any(changed[T0 == -1])
+
+
+def _residual_exact(U, V, W):
+    """Brent residual Y - X (eq. requirement) in exact rationals: every float entry is
+    an exact binary fraction, so Fraction(x) loses nothing."""
+    from fractions import Fraction
+    b1, b2, R = U.shape
+    b3 = V.shape[1]
+    E = {}
+    for i, j, jj, k, ii, kk in np.ndindex(b1, b2, b2, b3, b1, b3):
+        y = sum(Fraction(float(U[i, j, r])) * Fraction(float(V[jj, k, r])) * Fraction(float(W[ii, kk, r]))
+                for r in range(R))
+        E[(i, j, jj, k, ii, kk)] = y - (1 if (i == ii and j == jj and k == kk) else 0)
+    return E
+
+
+def _solve_exact(M, y):
+    """Solve the square system M x = y over Fractions (Gauss-Jordan)."""
+    n = len(y)
+    A = [list(row) + [v] for row, v in zip(M, y)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[p] = A[p], A[c]
+        A[c] = [x / A[c][c] for x in A[c]]
+        for r in range(n):
+            if r != c and A[r][c] != 0:
+                A[r] = [a - A[r][c] * b for a, b in zip(A[r], A[c])]
+    return [A[r][n] for r in range(n)]
+
+
+def test_apa322_residual_is_order_lambda_in_exact_arithmetic():
+    # U and V are affine in lam and W is (1/lam) times constants, so every entry of
+    # Y(lam) - X is c_{-1}/lam + c_0 + c_1 lam + c_2 lam^2.  Recover the four
+    # coefficients exactly from lam = 2^-1 .. 2^-4, require c_{-1} = c_0 = 0 (no
+    # blow-up, no constant term: Y(lam) -> X), some c_1 != 0 (a real approximation),
+    # and check the Laurent polynomial against the exact residual at lam = 2^-5 .. 2^-30.
+    from fractions import Fraction
+    lams = [Fraction(1, 2 ** k) for k in range(1, 31)]
+    res = [_residual_exact(*schemes.apa322(float(l))) for l in lams]
+    M = [[1 / l, Fraction(1), l, l * l] for l in lams[:4]]
+    nonzero_c1 = 0
+    for key in res[0]:
+        c = _solve_exact(M, [r[key] for r in res[:4]])
+        assert c[0] == 0 and c[1] == 0, key
+        nonzero_c1 += c[2] != 0
+        for l, r in zip(lams[4:], res[4:]):
+            assert c[2] * l + c[3] * l * l == r[key], key
+    assert nonzero_c1 > 0
+    # tau(lam) = Theta(lam): halving lam halves tau in the limit
+    t = [tensors.tau(*schemes.apa322(2.0 ** -k)) for k in (20, 21)]
+    assert abs(t[0] / t[1] - 2.0) < 1e-6
+
+
+def test_apa322_approximates_matmul_on_integers():
+    # The scheme as a plain bilinear computation (eq. bilinear-computation-block) on
+    # 3m x 2m times 2m x 2m integer matrices, lam = 2^-20 (every partial sum exact in
+    # float64): blocks C11 and C31 exact, the others within O(lam).
+    lam = 2.0 ** -20
+    U, V, W = schemes.apa322(lam)
+    for m, seed in [(1, 5), (3, 6)]:
+        A = workloads.integers((3 * m, 2 * m), seed).astype(np.float64)
+        B = workloads.integers((2 * m, 2 * m), seed + 100).astype(np.float64)
+        C = tensors.bc_evaluate(U, V, W, A, B)
+        ref = A @ B
+        # at most four O(lam) block products in an entry, each entry of one at most m |A| |B|
+        assert np.abs(C - ref).max() <= 4 * lam * m * np.abs(A).max() * np.abs(B).max()
+        assert np.array_equal(C[:m, :m], ref[:m, :m])          # C11: no lam term
+        assert np.array_equal(C[2 * m:, :m], ref[2 * m:, :m])  # C31: no lam term
