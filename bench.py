@@ -88,9 +88,11 @@ def _time_steps(fn, steps, warmup):
 
 
 def approx3072(args):
-    """Approximate scheme at N = 3072: perturbed Strassen (Section 3.1 recipe, sigma = lambda),
-    three levels (343 leaves of 384^3), bf16 hi+lo leaves with f64 recombination, beside the
-    plain f32 recursive form on the same GPU; N(0,1) inputs (seeds 3001/3002)."""
+    """Approximate schemes at N = 3072, bf16 hi+lo leaves with f64 recombination, beside the
+    plain f32 recursive form on the same GPU; N(0,1) inputs (seeds 3001/3002): the rank-10
+    <3,2,2> APA with 1/lambda coefficients at one, two and three levels (three: 1000 leaves
+    of 128 x 384 x 384, A's rows zero-padded to 27 x 128) and perturbed Strassen (Section 3.1
+    recipe, sigma = lambda) at three levels (343 leaves of 384^3)."""
     import numpy as np
     import torch
 
@@ -107,10 +109,12 @@ def approx3072(args):
     C = torch.empty((n, n), dtype=torch.float32, device=dev)
     S = rbc.Scheme.builtin("strassen")
     rows = []
-    for lam in (1e-1, 1e-2, 1e-3, 1e-4):
-        P = rbc.Scheme.perturbed(S, lam, 42)
+    cases = [("apa322", q, lam) for q in (1, 2, 3) for lam in (1e-1, 1e-2, 1e-3, 1e-4)]
+    cases += [("perturbed_strassen", 3, lam) for lam in (1e-1, 1e-2, 1e-3, 1e-4)]
+    for kind, q, lam in cases:
+        P = rbc.Scheme.builtin("apa322:%r" % lam) if kind == "apa322" else rbc.Scheme.perturbed(S, lam, 42)
         for prec in ("bf16x3", "f32"):
-            plan = rbc.Plan(n, n, n, [P] * 3, prec=prec)
+            plan = rbc.Plan(n, n, n, [P] * q, prec=prec)
             ws = plan.workspace(dev)
             for mode in ("none", "full"):
                 ms = _time_steps(lambda i: plan.matmul(A, B, C=C, seed=i % 16, mode=mode, workspace=ws),
@@ -119,13 +123,15 @@ def approx3072(args):
                 for seed in range(4):
                     plan.matmul(A, B, C=C, seed=seed, mode=mode, workspace=ws)
                     errs.append(float(torch.linalg.norm(C.double() - ref) / torch.linalg.norm(ref)))
-                rows.append({"lambda": lam, "prec": prec, "mode": mode, "ms": round(ms, 4),
+                rows.append({"scheme": kind, "levels": q, "lambda": lam, "prec": prec, "mode": mode,
+                             "ms": round(ms, 4),
                              "tflops": round(2.0 * n ** 3 / ms / 1e9, 2),
                              "rel_err_vs_fp64": [float("%.3g" % e) for e in errs]})
     std_ms = _time_steps(lambda i: torch.matmul(A, B, out=C), args.steps, args.warmup)
     out = {"metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
            "unit": "TFLOP/s", "n_gpus": 1, "dtype": "bf16x3 leaves / f32 comparator", "data": "synthetic",
-           "config": {"workload": "perturbed Strassen (sigma=lambda) Q=3, N=3072, N(0,1)", "n": n},
+           "config": {"workload": "rank-10 <3,2,2> APA (Q=1..3) and perturbed Strassen "
+                                  "(sigma=lambda, Q=3), N=3072, N(0,1)", "n": n},
            "rows": rows, "standard_f32_gemm_same_gpu_ms": round(std_ms, 4)}
     print(json.dumps(out), flush=True)
 

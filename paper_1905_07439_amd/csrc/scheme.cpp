@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -162,6 +163,51 @@ static const int kLadermanC[9][8] = {  // product numbers (1-based), 0 terminate
     {2, 3, 4, 6, 14, 16, 17, 0}, {2, 4, 5, 6, 20, 0},     {14, 16, 17, 18, 21, 0},
     {6, 7, 8, 11, 12, 13, 14, 0}, {12, 13, 14, 15, 22, 0}, {6, 7, 8, 9, 23, 0}};
 
+// Rank-10 approximate scheme for <3,2,2> (an APA: Y(lam) = X + O(lam), 1/lam in
+// W), built as in Bini et al. 1979: a 2x2 problem with one A block missing has
+// an approximate rank-5 formula; two copies cover the 3x2 A and share C's middle
+// row.  Local formula on a11, a12, a21 (a22 missing), B full, five terms of the
+// form sign * (A part) (B part) (C part), each part "unit + lam * pert":
+struct ApaPart {
+  int unit[2][2];  // (row, col) entries with coefficient 1, row < 0: unused
+  int pert[2];     // the entry with coefficient lam, row < 0: none
+};
+struct ApaTerm {
+  int sign;
+  ApaPart a, b, c;  // c entries are output blocks (row, col) of the local C
+};
+static const ApaTerm kApaLocal[5] = {
+    {+1, {{{0, 1}, {-1, 0}}, {0, 0}}, {{{0, 1}, {-1, 0}}, {1, 1}}, {{{0, 1}, {-1, 0}}, {-1, 0}}},
+    {+1, {{{1, 0}, {-1, 0}}, {0, 0}}, {{{0, 0}, {-1, 0}}, {-1, 0}}, {{{0, 0}, {-1, 0}}, {1, 0}}},
+    {-1, {{{0, 1}, {-1, 0}}, {-1, 0}}, {{{0, 1}, {-1, 0}}, {-1, 0}}, {{{0, 0}, {0, 1}}, {1, 1}}},
+    {-1, {{{1, 0}, {-1, 0}}, {-1, 0}}, {{{0, 0}, {0, 1}}, {1, 0}}, {{{0, 0}, {-1, 0}}, {-1, 0}}},
+    {+1, {{{0, 1}, {1, 0}}, {-1, 0}}, {{{0, 1}, {-1, 0}}, {1, 0}}, {{{0, 0}, {-1, 0}}, {1, 1}}},
+};
+// Copy c maps local A/C row i to global row kApaRow[c][i] and local A column
+// (= B row) j to global kApaCol[c][j]; B and C columns are unchanged.
+static const int kApaRow[2][2] = {{0, 1}, {2, 1}};
+static const int kApaCol[2][2] = {{0, 1}, {1, 0}};
+
+static void apa322(double lam, std::vector<double>& U, std::vector<double>& V, std::vector<double>& W) {
+  const int R = 10;
+  U.assign(6 * R, 0), V.assign(4 * R, 0), W.assign(6 * R, 0);
+  for (int c = 0; c < 2; ++c)
+    for (int t = 0; t < 5; ++t) {
+      const ApaTerm& T = kApaLocal[t];
+      const int r = 5 * c + t;
+      const int* rows = kApaRow[c];
+      const int* cols = kApaCol[c];
+      for (int e = 0; e < 2; ++e) {
+        if (T.a.unit[e][0] >= 0) U[(rows[T.a.unit[e][0]] * 2 + cols[T.a.unit[e][1]]) * R + r] += 1;
+        if (T.b.unit[e][0] >= 0) V[(cols[T.b.unit[e][0]] * 2 + T.b.unit[e][1]) * R + r] += 1;
+        if (T.c.unit[e][0] >= 0) W[(rows[T.c.unit[e][0]] * 2 + T.c.unit[e][1]) * R + r] += T.sign / lam;
+      }
+      if (T.a.pert[0] >= 0) U[(rows[T.a.pert[0]] * 2 + cols[T.a.pert[1]]) * R + r] += lam;
+      if (T.b.pert[0] >= 0) V[(cols[T.b.pert[0]] * 2 + T.b.pert[1]) * R + r] += lam;
+      if (T.c.pert[0] >= 0) W[(rows[T.c.pert[0]] * 2 + T.c.pert[1]) * R + r] += T.sign;  // lam / lam
+    }
+}
+
 rbc_status builtin_scheme(const char* name, Scheme& out) {
   if (!name) return fail(RBC_EINVAL, "null scheme name");
   std::vector<double> U, V, W;
@@ -200,6 +246,14 @@ rbc_status builtin_scheme(const char* name, Scheme& out) {
           V[(l * b3 + j) * R + r] = 1;
           W[(i * b3 + j) * R + r] = 1;
         }
+  } else if (!std::strncmp(name, "apa322:", 7)) {
+    char* end = nullptr;
+    const double lam = std::strtod(name + 7, &end);
+    if (end == name + 7 || *end != '\0' || !(lam > 0.0) || !(lam <= 1.0))
+      return fail(RBC_EINVAL, "expected apa322:<lambda> with 0 < lambda <= 1, got '%s'", name);
+    b1 = 3, b2 = 2, b3 = 2, R = 10;
+    apa322(lam, U, V, W);
+    return make_scheme(b1, b2, b3, R, U.data(), V.data(), W.data(), INFINITY, out);
   } else {
     return fail(RBC_EINVAL, "unknown builtin scheme '%s'", name);
   }

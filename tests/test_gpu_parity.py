@@ -38,13 +38,17 @@ BASE = {"strassen": osch.strassen, "laderman": osch.laderman}
 
 def _schemes(names):
     """(library schemes, oracle tensors) for a list of names ("strassen", "laderman",
-    "naive:b1,b2,b3", "pert:<sigma>:<seed>")."""
+    "naive:b1,b2,b3", "pert:<sigma>:<seed>", "apa:<lambda>" for the rank-10 <3,2,2> APA)."""
     lib, ref = [], []
     for n in names:
         if n.startswith("naive:"):
             b = tuple(int(x) for x in n[6:].split(","))
             lib.append(rbc.Scheme.builtin(n))
             ref.append(osch.naive(*b))
+        elif n.startswith("apa:"):
+            lam = float(n[4:])
+            lib.append(rbc.Scheme.builtin("apa322:%r" % lam))
+            ref.append(osch.apa322(lam))
         elif n.startswith("pert:"):
             _, sigma, seed = n.split(":")
             base = osch.strassen()
@@ -85,6 +89,8 @@ GATHER_CASES = [
     (["strassen", "strassen"], 64, 64, 64, "f64", 16),
     (["laderman", "pert:1e-2:1"], 90, 60, 120, "f64", 16),
     ([], 100, 60, 50, "f32", 64),
+    (["apa:0.0625", "strassen"], 150, 100, 90, "f32", 64),
+    (["apa:0.001", "apa:0.01"], 90, 60, 50, "f64", 16),
 ]
 
 
@@ -131,7 +137,8 @@ def test_gather_and_scatter_bit_exact(case, mode):
 
 
 @pytest.mark.parametrize("names,M,K,N", [(["strassen", "strassen"], 256, 192, 320),
-                                         (["laderman"], 192, 96, 288)])
+                                         (["laderman"], 192, 96, 288),
+                                         (["apa:0.001", "strassen"], 288, 160, 192)])
 def test_bf16x3_gather_split_and_f64_scatter_bit_exact(names, M, K, N):
     _say("bf16x3 stages", names, M, K, N)
     lib_s, ref_s = _schemes(names)
@@ -289,6 +296,30 @@ def test_perturbed_f64_matches_oracle_and_expectation_direction():
             ref = recursion.rbc_seeded(A, B, ref_s, seed, mode,
                                        leaf_dims=(plan.info["mM"], plan.info["mK"], plan.info["mN"]))
             assert recursion.rel_err(C, ref) <= 1e-13
+
+
+def test_apa_f64_matches_oracle_and_error_is_order_lambda():
+    # The rank-10 <3,2,2> APA at two levels, f64: the library against the oracle's
+    # recursion on the same draws (1/lambda = 16 amplifies the leaf products' rounding
+    # differences only 16^2-fold), and the approximation error against A B shrinking
+    # with lambda.
+    _say("apa f64")
+    A = workloads.gaussian((150, 100), 7)
+    B = workloads.gaussian((100, 90), 8)
+    AB = A @ B
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    errs = []
+    for lam in (2.0 ** -4, 2.0 ** -8, 2.0 ** -12):
+        lib_s, ref_s = _schemes(["apa:%r" % lam] * 2)
+        plan = rbc.Plan(150, 100, 90, lib_s, prec="f64")
+        for seed, mode in ((0, "full"), (1, "none")):
+            C = plan.matmul(Ad, Bd, seed=seed, mode=mode).cpu().numpy()
+            ref = recursion.rbc_seeded(A, B, ref_s, seed, mode,
+                                       leaf_dims=(plan.info["mM"], plan.info["mK"], plan.info["mN"]))
+            assert recursion.rel_err(C, ref) <= 1e-12 / lam ** 2, (lam, seed, mode)
+        errs.append(recursion.rel_err(C, AB))
+    _say("apa f64 rel err vs A B", errs)
+    assert errs[1] < errs[0] / 8 and errs[2] < errs[1] / 8
 
 
 def test_bf16x3_end_to_end():
