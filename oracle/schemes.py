@@ -186,6 +186,34 @@ def apa322(lam):
     return _assemble(3, 2, 2, 10, a, b, c, dtype=np.float64)
 
 
+def rotate(U, V, W):
+    """The cyclic rotation of a scheme for <b1,b2,b3> into one for <b2,b3,b1>.
+
+    The Brent equations (eq. requirement) are invariant under the cyclic shift
+    A -> B, B -> C^T, C -> A^T of the three matrix roles, so U' = V, V'[k,i] = W[i,k],
+    W'[j,i] = U[i,j] satisfy them whenever (U, V, W) does, with the same residual norm.
+    """
+    return (np.array(V, copy=True), np.ascontiguousarray(np.transpose(W, (1, 0, 2))),
+            np.ascontiguousarray(np.transpose(U, (1, 0, 2))))
+
+
+def apa223(lam):
+    """apa322 rotated once: a rank-10 approximate scheme for <2,2,3>."""
+    return rotate(*apa322(lam))
+
+
+def apa232(lam):
+    """apa322 rotated twice: a rank-10 approximate scheme for <2,3,2>."""
+    return rotate(*apa223(lam))
+
+
+def bini12(lam):
+    """The three levels whose recursion is one step of a rank-1000 approximate scheme
+    for 12 x 12 blocks (<3,2,2> x <2,2,3> x <2,3,2> = <12,12,12>, the Bini et al.
+    construction): the list of per-level tensors, outermost first."""
+    return [apa322(lam), apa223(lam), apa232(lam)]
+
+
 def _assemble(b1, b2, b3, R, a, b, c, dtype=np.int64):
     U = np.zeros((b1, b2, R), dtype=dtype)
     V = np.zeros((b2, b3, R), dtype=dtype)

@@ -92,7 +92,8 @@ def _solve_exact(M, y):
     return [A[r][n] for r in range(n)]
 
 
-def test_apa322_residual_is_order_lambda_in_exact_arithmetic():
+@pytest.mark.parametrize("name", ["apa322", "apa223", "apa232"])
+def test_apa_residual_is_order_lambda_in_exact_arithmetic(name):
     # U and V are affine in lam and W is (1/lam) times constants, so every entry of
     # Y(lam) - X is c_{-1}/lam + c_0 + c_1 lam + c_2 lam^2.  Recover the four
     # coefficients exactly from lam = 2^-1 .. 2^-4, require c_{-1} = c_0 = 0 (no
@@ -100,7 +101,8 @@ def test_apa322_residual_is_order_lambda_in_exact_arithmetic():
     # and check the Laurent polynomial against the exact residual at lam = 2^-5 .. 2^-30.
     from fractions import Fraction
     lams = [Fraction(1, 2 ** k) for k in range(1, 31)]
-    res = [_residual_exact(*schemes.apa322(float(l))) for l in lams]
+    build = getattr(schemes, name)
+    res = [_residual_exact(*build(float(l))) for l in lams]
     M = [[1 / l, Fraction(1), l, l * l] for l in lams[:4]]
     nonzero_c1 = 0
     for key in res[0]:
@@ -111,7 +113,7 @@ def test_apa322_residual_is_order_lambda_in_exact_arithmetic():
             assert c[2] * l + c[3] * l * l == r[key], key
     assert nonzero_c1 > 0
     # tau(lam) = Theta(lam): halving lam halves tau in the limit
-    t = [tensors.tau(*schemes.apa322(2.0 ** -k)) for k in (20, 21)]
+    t = [tensors.tau(*build(2.0 ** -k)) for k in (20, 21)]
     assert abs(t[0] / t[1] - 2.0) < 1e-6
 
 
@@ -130,3 +132,38 @@ def test_apa322_approximates_matmul_on_integers():
         assert np.abs(C - ref).max() <= 4 * lam * m * np.abs(A).max() * np.abs(B).max()
         assert np.array_equal(C[:m, :m], ref[:m, :m])          # C11: no lam term
         assert np.array_equal(C[2 * m:, :m], ref[2 * m:, :m])  # C31: no lam term
+
+
+@pytest.mark.parametrize("name", ["strassen", "laderman", "naive:2,3,4"])
+def test_rotation_keeps_exact_schemes_exact(name):
+    if name.startswith("naive:"):
+        base = schemes.naive(*(int(x) for x in name[6:].split(",")))
+    else:
+        base = getattr(schemes, name)()
+    b1, b2, b3 = base[0].shape[0], base[0].shape[1], base[1].shape[1]
+    U, V, W = schemes.rotate(*base)
+    assert (U.shape[0], U.shape[1], V.shape[1]) == (b2, b3, b1)
+    assert tensors.tau_squared_exact(U, V, W) == 0
+    A = workloads.integers((b2 * 2, b3 * 3), 11)
+    B = workloads.integers((b3 * 3, b1 * 2), 12)
+    assert np.array_equal(tensors.bc_evaluate(U, V, W, A, B), A @ B)
+    # three rotations give the scheme back
+    for got, want in zip(schemes.rotate(*schemes.rotate(U, V, W)), base):
+        assert np.array_equal(got, want)
+
+
+def test_bini12_levels_approximate_matmul():
+    # One step of the 12 x 12 scheme is the three-level recursion over <3,2,2>,
+    # <2,2,3>, <2,3,2> (no randomization): within O(lam) of A B on N = 24, and the
+    # error halves with lam while lam dominates the float64 rounding (amplified 1/lam^3).
+    from oracle import recursion
+    A = workloads.gaussian((24, 24), 21)
+    B = workloads.gaussian((24, 24), 22)
+    AB = A @ B
+    errs = []
+    for k in (8, 9):
+        lam = 2.0 ** -k
+        C = recursion.rbc_seeded(A, B, schemes.bini12(lam), 0, "none")
+        errs.append(recursion.rel_err(C, AB))
+    assert errs[0] < 0.05
+    assert 1.8 < errs[0] / errs[1] < 2.2
