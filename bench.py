@@ -110,11 +110,17 @@ def approx3072(args):
     S = rbc.Scheme.builtin("strassen")
     rows = []
     cases = [("apa322", q, lam) for q in (1, 2, 3) for lam in (1e-1, 1e-2, 1e-3, 1e-4)]
+    cases += [("bini12", 3, lam) for lam in (1e-1, 3e-2, 1.5e-2, 1e-2)]
     cases += [("perturbed_strassen", 3, lam) for lam in (1e-1, 1e-2, 1e-3, 1e-4)]
     for kind, q, lam in cases:
-        P = rbc.Scheme.builtin("apa322:%r" % lam) if kind == "apa322" else rbc.Scheme.perturbed(S, lam, 42)
+        if kind == "apa322":
+            levels = [rbc.Scheme.builtin("apa322:%r" % lam)] * q
+        elif kind == "bini12":  # one step of the 12 x 12 scheme: <3,2,2>, <2,2,3>, <2,3,2>
+            levels = [rbc.Scheme.builtin("%s:%r" % (k, lam)) for k in ("apa322", "apa223", "apa232")]
+        else:
+            levels = [rbc.Scheme.perturbed(S, lam, 42)] * q
         for prec in ("bf16x3", "f32"):
-            plan = rbc.Plan(n, n, n, [P] * q, prec=prec)
+            plan = rbc.Plan(n, n, n, levels, prec=prec)
             ws = plan.workspace(dev)
             for mode in ("none", "full"):
                 ms = _time_steps(lambda i: plan.matmul(A, B, C=C, seed=i % 16, mode=mode, workspace=ws),
@@ -130,8 +136,8 @@ def approx3072(args):
     std_ms = _time_steps(lambda i: torch.matmul(A, B, out=C), args.steps, args.warmup)
     out = {"metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
            "unit": "TFLOP/s", "n_gpus": 1, "dtype": "bf16x3 leaves / f32 comparator", "data": "synthetic",
-           "config": {"workload": "rank-10 <3,2,2> APA (Q=1..3) and perturbed Strassen "
-                                  "(sigma=lambda, Q=3), N=3072, N(0,1)", "n": n},
+           "config": {"workload": "rank-10 <3,2,2> APA (Q=1..3), rank-1000 12x12 APA "
+                                  "(one step), perturbed Strassen (sigma=lambda, Q=3), N=3072, N(0,1)", "n": n},
            "rows": rows, "standard_f32_gemm_same_gpu_ms": round(std_ms, 4)}
     print(json.dumps(out), flush=True)
 

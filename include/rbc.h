@@ -123,7 +123,15 @@ rbc_status rbc_scheme_create(int b1, int b2, int b3, int R, const double* U, con
                              const double* W, double residual_tol, rbc_scheme* out);
 /* Builtin exact schemes: "strassen" (rank 7, 2x2; Strassen 1969 in the form of
  * Golub & Van Loan), "laderman" (rank 23, 3x3; Laderman 1976), and
- * "naive:b1,b2,b3" (the standard algorithm as a BC, R = b1 b2 b3). */
+ * "naive:b1,b2,b3" (the standard algorithm as a BC, R = b1 b2 b3).
+ * Builtin approximate schemes (the APA family of Section 1, eq. APA-y: the Brent
+ * residual is O(lambda) with no constant term, and W holds 1/lambda
+ * coefficients): "apa322:<lambda>", rank 10 for <3,2,2> (two five-product
+ * formulas for a 2x2 problem missing one block of A, after Bini et al. 1979),
+ * and its cyclic rotations "apa223:<lambda>" (<2,2,3>) and "apa232:<lambda>"
+ * (<2,3,2>).  The three as consecutive levels form one step of a rank-1000
+ * approximate scheme for 12x12 blocks.  0 < lambda <= 1, else RBC_EINVAL.
+ * Rounding errors of the leaf products grow like 1/lambda per APA level. */
 rbc_status rbc_scheme_builtin(const char* name, rbc_scheme* out);
 /* dims = {b1, b2, b3, R}; tau (Definition 1), kappa (eq. epsilon-def),
  * ||Y||_F (eq. def-y), q = sqrt(sum_r ||U_r||^2 ||V_r||^2 ||W_r||^2)

@@ -208,6 +208,22 @@ static void apa322(double lam, std::vector<double>& U, std::vector<double>& V, s
     }
 }
 
+// Cyclic rotation <b1,b2,b3> -> <b2,b3,b1>: the Brent equations are invariant
+// under A -> B, B -> C^T, C -> A^T, so U' = V, V'(k,i) = W(i,k), W'(j,i) = U(i,j).
+static void rotate_scheme(int& b1, int& b2, int& b3, int R, std::vector<double>& U, std::vector<double>& V,
+                          std::vector<double>& W) {
+  std::vector<double> U2 = V, V2(W.size()), W2(U.size());
+  for (int i = 0; i < b1; ++i)
+    for (int k = 0; k < b3; ++k)
+      for (int r = 0; r < R; ++r) V2[(k * b1 + i) * R + r] = W[(i * b3 + k) * R + r];
+  for (int i = 0; i < b1; ++i)
+    for (int j = 0; j < b2; ++j)
+      for (int r = 0; r < R; ++r) W2[(j * b1 + i) * R + r] = U[(i * b2 + j) * R + r];
+  const int t = b1;
+  b1 = b2, b2 = b3, b3 = t;
+  U.swap(U2), V.swap(V2), W.swap(W2);
+}
+
 rbc_status builtin_scheme(const char* name, Scheme& out) {
   if (!name) return fail(RBC_EINVAL, "null scheme name");
   std::vector<double> U, V, W;
@@ -246,13 +262,16 @@ rbc_status builtin_scheme(const char* name, Scheme& out) {
           V[(l * b3 + j) * R + r] = 1;
           W[(i * b3 + j) * R + r] = 1;
         }
-  } else if (!std::strncmp(name, "apa322:", 7)) {
+  } else if (!std::strncmp(name, "apa322:", 7) || !std::strncmp(name, "apa223:", 7) ||
+             !std::strncmp(name, "apa232:", 7)) {
     char* end = nullptr;
     const double lam = std::strtod(name + 7, &end);
     if (end == name + 7 || *end != '\0' || !(lam > 0.0) || !(lam <= 1.0))
-      return fail(RBC_EINVAL, "expected apa322:<lambda> with 0 < lambda <= 1, got '%s'", name);
+      return fail(RBC_EINVAL, "expected %.6s:<lambda> with 0 < lambda <= 1, got '%s'", name, name);
     b1 = 3, b2 = 2, b3 = 2, R = 10;
     apa322(lam, U, V, W);
+    const int turns = name[3] == '3' ? 0 : (name[5] == '3' ? 1 : 2);  // 322, 223, 232
+    for (int t = 0; t < turns; ++t) rotate_scheme(b1, b2, b3, R, U, V, W);
     return make_scheme(b1, b2, b3, R, U.data(), V.data(), W.data(), INFINITY, out);
   } else {
     return fail(RBC_EINVAL, "unknown builtin scheme '%s'", name);

@@ -38,17 +38,17 @@ BASE = {"strassen": osch.strassen, "laderman": osch.laderman}
 
 def _schemes(names):
     """(library schemes, oracle tensors) for a list of names ("strassen", "laderman",
-    "naive:b1,b2,b3", "pert:<sigma>:<seed>", "apa:<lambda>" for the rank-10 <3,2,2> APA)."""
+    "naive:b1,b2,b3", "pert:<sigma>:<seed>", "apa322:<lambda>" for the rank-10 <3,2,2> APA, "apa223:", "apa232:" for its rotations)."""
     lib, ref = [], []
     for n in names:
         if n.startswith("naive:"):
             b = tuple(int(x) for x in n[6:].split(","))
             lib.append(rbc.Scheme.builtin(n))
             ref.append(osch.naive(*b))
-        elif n.startswith("apa:"):
-            lam = float(n[4:])
-            lib.append(rbc.Scheme.builtin("apa322:%r" % lam))
-            ref.append(osch.apa322(lam))
+        elif n.startswith("apa"):  # apa322:<lambda>, apa223:<lambda>, apa232:<lambda>
+            kind, lam = n.split(":")
+            lib.append(rbc.Scheme.builtin("%s:%r" % (kind, float(lam))))
+            ref.append(getattr(osch, kind)(float(lam)))
         elif n.startswith("pert:"):
             _, sigma, seed = n.split(":")
             base = osch.strassen()
@@ -89,8 +89,9 @@ GATHER_CASES = [
     (["strassen", "strassen"], 64, 64, 64, "f64", 16),
     (["laderman", "pert:1e-2:1"], 90, 60, 120, "f64", 16),
     ([], 100, 60, 50, "f32", 64),
-    (["apa:0.0625", "strassen"], 150, 100, 90, "f32", 64),
-    (["apa:0.001", "apa:0.01"], 90, 60, 50, "f64", 16),
+    (["apa322:0.0625", "strassen"], 150, 100, 90, "f32", 64),
+    (["apa322:0.001", "apa322:0.01"], 90, 60, 50, "f64", 16),
+    (["apa322:0.015", "apa223:0.015", "apa232:0.015"], 130, 100, 120, "f32", 64),
 ]
 
 
@@ -138,7 +139,8 @@ def test_gather_and_scatter_bit_exact(case, mode):
 
 @pytest.mark.parametrize("names,M,K,N", [(["strassen", "strassen"], 256, 192, 320),
                                          (["laderman"], 192, 96, 288),
-                                         (["apa:0.001", "strassen"], 288, 160, 192)])
+                                         (["apa322:0.001", "strassen"], 288, 160, 192),
+                                         (["apa322:0.03", "apa223:0.03", "apa232:0.03"], 240, 240, 240)])
 def test_bf16x3_gather_split_and_f64_scatter_bit_exact(names, M, K, N):
     _say("bf16x3 stages", names, M, K, N)
     lib_s, ref_s = _schemes(names)
@@ -310,7 +312,7 @@ def test_apa_f64_matches_oracle_and_error_is_order_lambda():
     Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
     errs = []
     for lam in (2.0 ** -4, 2.0 ** -8, 2.0 ** -12):
-        lib_s, ref_s = _schemes(["apa:%r" % lam] * 2)
+        lib_s, ref_s = _schemes(["apa322:%r" % lam] * 2)
         plan = rbc.Plan(150, 100, 90, lib_s, prec="f64")
         for seed, mode in ((0, "full"), (1, "none")):
             C = plan.matmul(Ad, Bd, seed=seed, mode=mode).cpu().numpy()
@@ -320,6 +322,31 @@ def test_apa_f64_matches_oracle_and_error_is_order_lambda():
         errs.append(recursion.rel_err(C, AB))
     _say("apa f64 rel err vs A B", errs)
     assert errs[1] < errs[0] / 8 and errs[2] < errs[1] / 8
+
+
+def test_bini12_step_f64_and_f32_match_oracle():
+    # One step of the rank-1000 12 x 12 approximate scheme (three levels <3,2,2>,
+    # <2,2,3>, <2,3,2>) at N = 240: f64 against the oracle's recursion on the same
+    # draws, and f32 within the f32 emulation's error, which grows like u / lambda^3.
+    _say("bini12 f64/f32")
+    A = workloads.gaussian((240, 240), 31)
+    B = workloads.gaussian((240, 240), 32)
+    AB = A @ B
+    lam = 2.0 ** -5
+    lib_s, ref_s = _schemes(["apa322:%r" % lam, "apa223:%r" % lam, "apa232:%r" % lam])
+    plan = rbc.Plan(240, 240, 240, lib_s, prec="f64")
+    dims = (plan.info["mM"], plan.info["mK"], plan.info["mN"])
+    for seed, mode in ((0, "full"), (2, "none")):
+        C = plan.matmul(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV), seed=seed, mode=mode)
+        ref = recursion.rbc_seeded(A, B, ref_s, seed, mode, leaf_dims=dims)
+        assert recursion.rel_err(C.cpu().numpy(), ref) <= 1e-11
+    e64 = recursion.rel_err(C.cpu().numpy(), AB)
+    p32 = rbc.Plan(240, 240, 240, lib_s, prec="f32")
+    C32 = p32.matmul(torch.from_numpy(A.astype(np.float32)).to(DEV),
+                     torch.from_numpy(B.astype(np.float32)).to(DEV), seed=2, mode="none").cpu().numpy()
+    e32 = recursion.rel_err(C32, AB)
+    _say("bini12 rel err f64 %.3g f32 %.3g" % (e64, e32))
+    assert e64 < 0.2 and e32 < e64 + 2.0 ** -23 / lam ** 3 * 64
 
 
 def test_bf16x3_end_to_end():

@@ -51,22 +51,24 @@ def test_builtin_schemes_match_oracle(name, builder):
 
 
 @pytest.mark.parametrize("lam", [1.0, 0.1, 1e-3, 2.0 ** -20])
-def test_apa322_builtin_matches_oracle(lam):
-    s = rbc.Scheme.builtin("apa322:%r" % lam)
-    for got, want in zip(s.tensors(), oschemes.apa322(lam)):
+@pytest.mark.parametrize("name,dims", [("apa322", (3, 2, 2)), ("apa223", (2, 2, 3)), ("apa232", (2, 3, 2))])
+def test_apa_builtins_match_oracle(name, dims, lam):
+    s = rbc.Scheme.builtin("%s:%r" % (name, lam))
+    for got, want in zip(s.tensors(), getattr(oschemes, name)(lam)):
         np.testing.assert_array_equal(got, want)
     i = s.info()
-    assert (i["b1"], i["b2"], i["b3"], i["R"]) == (3, 2, 2, 10)
-    U, V, W = oschemes.apa322(lam)
+    assert (i["b1"], i["b2"], i["b3"], i["R"]) == dims + (10,)
+    U, V, W = getattr(oschemes, name)(lam)
     assert i["tau"] == pytest.approx(otensors.tau(U, V, W), rel=1e-12)
     assert i["kappa"] == pytest.approx(otensors.kappa(U, V, W), abs=1e-12)
-    for bad in ("apa322:0", "apa322:-0.1", "apa322:1.5", "apa322:", "apa322:1e-3x", "apa322:nan"):
+    for bad in ("0", "-0.1", "1.5", "", "1e-3x", "nan"):
         with pytest.raises(rbc.RbcError):
-            rbc.Scheme.builtin(bad)
-    # three levels at N = 3072: 27 x 8 x 8 blocks, zero padding to whole leaves
+            rbc.Scheme.builtin("%s:%s" % (name, bad))
+    # three levels at N = 3072: b^3 blocks per dimension, zero padding to whole leaves
     p = rbc.Plan(3072, 3072, 3072, [s] * 3, prec="bf16x3")
     assert p.info["n_leaves"] == 1000
-    assert p.info["mM"] * 27 >= 3072 and p.info["mK"] * 8 >= 3072 and p.info["mN"] * 8 >= 3072
+    b1, b2, b3 = dims
+    assert p.info["mM"] * b1 ** 3 >= 3072 and p.info["mK"] * b2 ** 3 >= 3072 and p.info["mN"] * b3 ** 3 >= 3072
 
 
 def test_naive_builtin_and_rank_one_scheme():
