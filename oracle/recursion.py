@@ -182,3 +182,18 @@ def rel_err(C, ref):
     C = np.asarray(C, np.float64)
     ref = np.asarray(ref, np.float64)
     return float(np.linalg.norm(C - ref) / np.linalg.norm(ref))
+
+
+def apa_ebc(A, B, levels_at, eps, seed=0, mode="none", kappa_scale=None, leaf_dims=None):
+    """The exact product from an approximate scheme (Section 1, eq. APA-to-EBC):
+    sum_i alpha_i F(A, B; eps_i), F the recursion over the level tensors
+    levels_at(eps_i) with the draws of (seed, mode), which depend only on the levels'
+    block shapes and so are the same for every eps_i.  alpha from
+    schemes.apa_ebc_weights; the terms are added in the order of eps, in f64."""
+    from . import schemes
+    alpha = schemes.apa_ebc_weights(eps)
+    out = None
+    for a, e in zip(alpha, eps):
+        Y = rbc_seeded(A, B, levels_at(e), seed, mode, kappa_scale=kappa_scale, leaf_dims=leaf_dims)
+        out = a * Y if out is None else out + a * Y
+    return out

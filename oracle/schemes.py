@@ -227,3 +227,24 @@ def _assemble(b1, b2, b3, R, a, b, c, dtype=np.int64):
         for coef, r in lst:
             W[i - 1, j - 1, r - 1] = coef
     return U, V, W
+
+
+def apa_ebc_weights(eps):
+    """Weights alpha_1..alpha_{d+1} that turn an approximate scheme into an exact one
+    (Section 1, eq. APA-to-EBC): sum_i alpha_i Y(eps_i) = X.
+
+    Every entry of the error E(eps) = Y(eps) - X is a polynomial in eps with zero
+    constant term and degree at most d, so the combination is exact for every such
+    E exactly when sum_i alpha_i = 1 and sum_i alpha_i eps_i^k = 0 for k = 1..d:
+    the (d+1) x (d+1) Vandermonde system solved here.  The eps_i must be distinct;
+    d = len(eps) - 1 may exceed the scheme's own degree (the combination stays exact).
+    """
+    e = np.asarray(eps, dtype=np.float64)
+    if e.ndim != 1 or e.size < 1:
+        raise ValueError("eps must be a non-empty 1-D sequence")
+    if np.unique(e).size != e.size:
+        raise ValueError("eps values must be distinct")
+    powers = np.vander(e, increasing=True).T  # powers[k, i] = eps_i ** k
+    rhs = np.zeros(e.size)
+    rhs[0] = 1.0
+    return np.linalg.solve(powers, rhs)
