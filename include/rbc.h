@@ -241,6 +241,36 @@ rbc_status rbc_matmul_average(rbc_plan p, const void* A, int64_t lda, const void
  * over explicit draws. */
 rbc_status rbc_accumulate(double* acc, const void* X, int x_is_f64, int64_t rows, int64_t cols, int64_t ldx,
                           int first, void* stream);
+/* acc = (first ? 0 : acc) + weight * X elementwise, otherwise as rbc_accumulate
+ * (rbc_accumulate is weight = 1).  Error: RBC_EINVAL for a null pointer, a bad
+ * shape or a weight that is not finite. */
+rbc_status rbc_accumulate_weighted(double* acc, const void* X, int x_is_f64, int64_t rows, int64_t cols,
+                                   int64_t ldx, double weight, int first, void* stream);
+
+/* ---- exact product from an approximate scheme (Section 1, eq. APA-to-EBC) --
+ * An approximate scheme's product Y(eps) differs from A B by a polynomial in eps
+ * with zero constant term; with d + 1 distinct values the weighted sum
+ * sum_i alpha_i Y(eps_i) is exact when that degree is at most d.
+ *
+ * rbc_apa_ebc_weights: alpha[0..n-1] (host) for eps[0..n-1] (host, distinct,
+ * nonzero, finite, 1 <= n <= RBC_EBC_MAX_VALUES): the solution of
+ * sum_i alpha_i = 1, sum_i alpha_i eps_i^k = 0 for k = 1..n-1.
+ *
+ * rbc_matmul_apa_ebc: C (device, M x N contiguous f64) = sum_i alpha_i F-hat_i(A, B),
+ * F-hat_i from plans[i] (host array of n plans), whose schemes are the
+ * approximate scheme at eps[i]: all plans share M, K, N, precision and the block
+ * shapes of their levels, and every product uses the draws of (seed, mode) and
+ * kappa_scale as rbc_matmul.  A, B as rbc_matmul.  Products are computed one at a
+ * time into the workspace (at least the largest rbc_average_workspace of the
+ * plans) and added in the order i = 0..n-1 with the f64 accumulator.  Errors:
+ * RBC_EINVAL for null pointers, bad eps, plans that differ, or a short
+ * workspace; nothing is launched then. */
+#define RBC_EBC_MAX_VALUES 32
+rbc_status rbc_apa_ebc_weights(const double* eps, int64_t n, double* alpha);
+rbc_status rbc_matmul_apa_ebc(const rbc_plan* plans, const double* eps, int64_t n, const void* A, int64_t lda,
+                              const void* B, int64_t ldb, double* C, uint64_t seed, rbc_mode mode,
+                              int kappa_scale, void* workspace, size_t ws_bytes, void* stream);
+
 /* x[i] *= s for i < n (device f64). */
 rbc_status rbc_scale_f64(double* x, int64_t n, double s, void* stream);
 

@@ -462,3 +462,54 @@ class Batch:
                 lib().rbc_batch_destroy(h)
             except Exception:
                 pass
+
+
+def apa_ebc_weights(eps):
+    """Weights alpha_i with sum_i alpha_i Y(eps_i) = X for an approximate scheme whose
+    error has degree < len(eps) in eps (Section 1, eq. APA-to-EBC); a list of floats."""
+    n = len(eps)
+    e = (ctypes.c_double * n)(*[float(x) for x in eps])
+    a = (ctypes.c_double * n)()
+    check(lib().rbc_apa_ebc_weights(e, n, a))
+    return list(a)
+
+
+def apa_scheme_levels(names, eps):
+    """Scheme names for one eps: each "apa322"/"apa223"/"apa232" entry gets ":<eps>",
+    any other name (an exact scheme) is kept."""
+    return [("%s:%r" % (n, float(eps))) if n in ("apa322", "apa223", "apa232") else n for n in names]
+
+
+def matmul_apa_ebc(A, B, names, eps, prec="f64", seed=0, mode="none", kappa_scale=None, stream=None,
+                   leaf_tile=0, fusion="auto"):
+    """The exact product from an approximate scheme: sum_i alpha_i F-hat(A, B) with the
+    levels ``names`` at eps[i] (apa entries take eps[i], see apa_scheme_levels), every
+    product with the draws of (seed, mode), combined on the device in f64 in the order
+    of eps (a new float64 M x N tensor)."""
+    import torch
+    if kappa_scale is None:
+        kappa_scale = mode != "none"
+    M, K = A.shape
+    N = B.shape[1]
+    keep = []
+    for e in eps:
+        levels = [Scheme.builtin(n) for n in apa_scheme_levels(names, e)]
+        keep.append((levels, Plan(M, K, N, levels, prec=prec, leaf_tile=leaf_tile, fusion=fusion)))
+    plans = [p for _, p in keep]
+    for name, X, shape in (("A", A, (M, K)), ("B", B, (K, N))):
+        if tuple(X.shape) != shape or X.dtype != plans[0].dtype or not X.is_cuda or X.stride(1) != 1:
+            raise ValueError("%s must be a row-major %s CUDA tensor of shape %s" % (name, plans[0].dtype, shape))
+    need = 0
+    for p in plans:
+        n = ctypes.c_size_t()
+        check(lib().rbc_average_workspace(p._h, ctypes.byref(n)))
+        need = max(need, n.value)
+    ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+    out = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    hs = (ctypes.c_void_p * len(plans))(*[getattr(p._h, "value", p._h) for p in plans])
+    e = (ctypes.c_double * len(eps))(*[float(x) for x in eps])
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    check(lib().rbc_matmul_apa_ebc(hs, e, len(eps), _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(out),
+                                   int(seed) & 0xFFFFFFFFFFFFFFFF, MODES[mode], int(bool(kappa_scale)), _ptr(ws),
+                                   ws.numel(), ctypes.c_void_p(st.cuda_stream)))
+    return out

@@ -84,6 +84,13 @@ SIGNATURES = {
     "rbc_matmul_average": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, ctypes.POINTER(ctypes.c_uint64),
                                           c_i64, ctypes.c_int, ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]),
     "rbc_accumulate": (ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_i64, c_i64, c_i64, ctypes.c_int, c_vp]),
+    "rbc_accumulate_weighted": (ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_i64, c_i64, c_i64, ctypes.c_double,
+                                               ctypes.c_int, c_vp]),
+    "rbc_apa_ebc_weights": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), c_i64,
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "rbc_matmul_apa_ebc": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(ctypes.c_double), c_i64, c_vp, c_i64,
+                                          c_vp, c_i64, c_vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, c_vp,
+                                          ctypes.c_size_t, c_vp]),
     "rbc_scale_f64": (ctypes.c_int, [c_vp, c_i64, ctypes.c_double, c_vp]),
     "rbc_stage_gather": (ctypes.c_int, [c_vp, ctypes.c_int, c_vp, c_i64, c_i32_p, c_i32_p, c_vp,
                                         ctypes.c_size_t, c_vp]),

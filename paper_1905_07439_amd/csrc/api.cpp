@@ -410,6 +410,77 @@ rbc_status rbc_matmul_average(rbc_plan h, const void* A, int64_t lda, const void
   RBC_GUARD_END
 }
 
+rbc_status rbc_accumulate_weighted(double* acc, const void* X, int x_is_f64, int64_t rows, int64_t cols,
+                                   int64_t ldx, double weight, int first, void* stream) {
+  if (!acc || !X) return fail(RBC_EINVAL, "null pointer");
+  if (rows < 0 || cols < 0 || ldx < cols) return fail(RBC_EINVAL, "bad shape");
+  if (!std::isfinite(weight)) return fail(RBC_EINVAL, "weight is not finite");
+  HIP_CHECK(launch_accumulate(acc, X, x_is_f64 ? ELT_F64 : ELT_F32, rows, cols, ldx, first != 0,
+                              (hipStream_t)stream, weight));
+  return RBC_OK;
+}
+
+rbc_status rbc_apa_ebc_weights(const double* eps, int64_t n, double* alpha) {
+  if (!eps || !alpha) return fail(RBC_EINVAL, "null argument");
+  if (n < 1 || n > RBC_EBC_MAX_VALUES) return fail(RBC_EINVAL, "n = %lld outside [1, %d]", (long long)n,
+                                                   RBC_EBC_MAX_VALUES);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(eps[i]) || eps[i] == 0.0) return fail(RBC_EINVAL, "eps[%lld] is zero or not finite",
+                                                             (long long)i);
+    for (int64_t j = 0; j < i; ++j)
+      if (eps[j] == eps[i]) return fail(RBC_EINVAL, "eps[%lld] repeats eps[%lld]", (long long)i, (long long)j);
+  }
+  // The combination must reproduce the value at eps = 0 of every polynomial of
+  // degree < n through the n points: the Lagrange basis evaluated at zero.
+  for (int64_t i = 0; i < n; ++i) {
+    double a = 1.0;
+    for (int64_t j = 0; j < n; ++j)
+      if (j != i) a *= eps[j] / (eps[j] - eps[i]);
+    alpha[i] = a;
+  }
+  return RBC_OK;
+}
+
+rbc_status rbc_matmul_apa_ebc(const rbc_plan* plans, const double* eps, int64_t n, const void* A, int64_t lda,
+                              const void* B, int64_t ldb, double* C, uint64_t seed, rbc_mode mode,
+                              int kappa_scale, void* workspace, size_t ws_bytes, void* stream) {
+  RBC_GUARD_BEGIN
+  if (!plans || !eps || !C) return fail(RBC_EINVAL, "null argument");
+  if (mode < RBC_MODE_FULL || mode > RBC_MODE_NONE) return fail(RBC_EINVAL, "bad mode %d", (int)mode);
+  double alpha[RBC_EBC_MAX_VALUES];
+  rbc_status st = rbc_apa_ebc_weights(eps, n, alpha);
+  if (st != RBC_OK) return st;
+  for (int64_t i = 0; i < n; ++i)
+    if (!plans[i]) return fail(RBC_EINVAL, "plans[%lld] is null", (long long)i);
+  const Plan& p0 = plans[0]->p;
+  std::vector<int32_t> s0, pm0, s, pm;
+  seeded_draws(p0, seed, mode, s0, pm0);
+  size_t need = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const Plan& p = plans[i]->p;
+    if (p.M != p0.M || p.K != p0.K || p.N != p0.N || p.prec != p0.prec)
+      return fail(RBC_EINVAL, "plans[%lld] differs from plans[0] in shape or precision", (long long)i);
+    seeded_draws(p, seed, mode, s, pm);
+    if (s != s0 || pm != pm0) return fail(RBC_EINVAL, "plans[%lld] differs from plans[0] in its levels' block shapes",
+                                          (long long)i);
+    size_t b = 0;
+    if ((st = rbc_average_workspace(plans[i], &b)) != RBC_OK) return st;
+    need = b > need ? b : need;
+  }
+  if (!workspace || ws_bytes < need) return fail(RBC_EINVAL, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  const Elt elt = p0.prec == RBC_PREC_F64 ? ELT_F64 : ELT_F32;
+  for (int64_t i = 0; i < n; ++i) {
+    Plan& p = plans[i]->p;
+    const size_t plan_ws = (p.ws_bytes + 255) / 256 * 256;
+    void* prod = static_cast<char*>(workspace) + plan_ws;
+    st = matmul_impl(p, A, lda, B, ldb, prod, p.N, s0.data(), pm0.data(), kappa_scale, workspace, plan_ws, stream);
+    if (st != RBC_OK) return st;
+    HIP_CHECK(launch_accumulate(C, prod, elt, p.M, p.N, p.N, i == 0, (hipStream_t)stream, alpha[i]));
+  }
+  return RBC_OK;
+  RBC_GUARD_END
+}
+
 rbc_status rbc_stage_gather(rbc_plan h, int which, const void* X, int64_t ldx, const int32_t* signs,
                             const int32_t* perms, void* workspace, size_t ws_bytes, void* stream) {
   RBC_GUARD_BEGIN

@@ -110,7 +110,7 @@ hipError_t launch_gemm_fp8c(const uint8_t* S, const uint8_t* T, float* P, int64_
                             int64_t batch, int tile, const int32_t* eS, const int32_t* eT, hipStream_t stream);
 // acc (rows x cols, contiguous f64) = (first ? 0 : acc) + x (row stride ldx), elementwise.
 hipError_t launch_accumulate(double* acc, const void* x, Elt elt, int64_t rows, int64_t cols, int64_t ldx,
-                             int first, hipStream_t s);
+                             int first, hipStream_t s, double weight = 1.0);
 hipError_t launch_scale_f64(double* acc, int64_t n, double scale, hipStream_t s);
 // Partial maxima of |X|: maxabs_blocks(rows, cols) floats at `partial`
 // (overwritten), at most kScalePartials.  The gather of the leaf operands

@@ -307,3 +307,13 @@ def test_peak_argument_errors_are_synchronous():
     assert L.rbc_peak_mfma(0, 0, 10, fake, ctypes.byref(fl), null) == _lib.RBC_EINVAL
     assert L.rbc_peak_mfma(99, 1, 10, fake, ctypes.byref(fl), null) == _lib.RBC_EINVAL
     assert b"kind" in L.rbc_last_error()
+
+
+def test_apa_ebc_weights_match_the_oracle():
+    # The library takes the Lagrange route, the oracle solves the Vandermonde system.
+    from oracle import schemes as osch
+    for eps in ([0.1 * k for k in range(1, 8)], [0.5], [0.03, 0.2], [2.0 ** -5, 0.3, 0.11, 0.7]):
+        np.testing.assert_allclose(rbc.apa_ebc_weights(eps), osch.apa_ebc_weights(eps), rtol=1e-10, atol=1e-10)
+    for bad in ([0.1, 0.1], [], [0.0, 0.2], [float("nan")], [0.01] * 40):
+        with pytest.raises(Exception):
+            rbc.apa_ebc_weights(bad)
