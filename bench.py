@@ -133,11 +133,32 @@ def approx3072(args):
                              "ms": round(ms, 4),
                              "tflops": round(2.0 * n ** 3 / ms / 1e9, 2),
                              "rel_err_vs_fp64": [float("%.3g" % e) for e in errs]})
+    # The exact combination of the 12 x 12 step over lambda = 0.1..0.7 (7 products, weights
+    # +-C(7, i), f64 accumulation on the device), plans built before the timed region.
+    eps7 = [0.1 * k for k in range(1, 8)]
+    names = ["apa322", "apa223", "apa232"]
+    Cd = torch.empty((n, n), dtype=torch.float64, device=dev)
+    for prec in ("bf16x3", "f32"):
+        plans = rbc.apa_ebc_plans(n, n, n, names, eps7, prec=prec)
+        ws = torch.empty(max(p.info["workspace_bytes"] for p in plans) + 256 + n * n * 4, dtype=torch.uint8,
+                         device=dev)
+        for mode in ("none", "full"):
+            run = lambda i: rbc.matmul_apa_ebc(A, B, names, eps7, prec=prec, seed=i % 16, mode=mode, plans=plans,
+                                               workspace=ws, out=Cd)
+            ms = _time_steps(run, args.steps, args.warmup)
+            errs = []
+            for seed in range(4):
+                run(seed)
+                errs.append(float(torch.linalg.norm(Cd - ref) / torch.linalg.norm(ref)))
+            rows.append({"scheme": "bini12_ebc_7", "levels": 3, "lambda": eps7, "prec": prec, "mode": mode,
+                         "ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 2),
+                         "rel_err_vs_fp64": [float("%.3g" % e) for e in errs]})
     std_ms = _time_steps(lambda i: torch.matmul(A, B, out=C), args.steps, args.warmup)
     out = {"metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
            "unit": "TFLOP/s", "n_gpus": 1, "dtype": "bf16x3 leaves / f32 comparator", "data": "synthetic",
            "config": {"workload": "rank-10 <3,2,2> APA (Q=1..3), rank-1000 12x12 APA "
-                                  "(one step), perturbed Strassen (sigma=lambda, Q=3), N=3072, N(0,1)", "n": n},
+                                  "(one step) and its exact combination over 7 lambda, perturbed Strassen (sigma=lambda, Q=3), "
+                                  "N=3072, N(0,1)", "n": n},
            "rows": rows, "standard_f32_gemm_same_gpu_ms": round(std_ms, 4)}
     print(json.dumps(out), flush=True)
 

@@ -480,8 +480,14 @@ def apa_scheme_levels(names, eps):
     return [("%s:%r" % (n, float(eps))) if n in ("apa322", "apa223", "apa232") else n for n in names]
 
 
+def apa_ebc_plans(M, K, N, names, eps, prec="f64", leaf_tile=0, fusion="auto"):
+    """One Plan per eps for the levels ``names`` (see apa_scheme_levels)."""
+    return [Plan(M, K, N, [Scheme.builtin(n) for n in apa_scheme_levels(names, e)], prec=prec,
+                 leaf_tile=leaf_tile, fusion=fusion) for e in eps]
+
+
 def matmul_apa_ebc(A, B, names, eps, prec="f64", seed=0, mode="none", kappa_scale=None, stream=None,
-                   leaf_tile=0, fusion="auto"):
+                   leaf_tile=0, fusion="auto", plans=None, workspace=None, out=None):
     """The exact product from an approximate scheme: sum_i alpha_i F-hat(A, B) with the
     levels ``names`` at eps[i] (apa entries take eps[i], see apa_scheme_levels), every
     product with the draws of (seed, mode), combined on the device in f64 in the order
@@ -491,11 +497,10 @@ def matmul_apa_ebc(A, B, names, eps, prec="f64", seed=0, mode="none", kappa_scal
         kappa_scale = mode != "none"
     M, K = A.shape
     N = B.shape[1]
-    keep = []
-    for e in eps:
-        levels = [Scheme.builtin(n) for n in apa_scheme_levels(names, e)]
-        keep.append((levels, Plan(M, K, N, levels, prec=prec, leaf_tile=leaf_tile, fusion=fusion)))
-    plans = [p for _, p in keep]
+    if plans is None:
+        plans = apa_ebc_plans(M, K, N, names, eps, prec, leaf_tile, fusion)
+    if len(plans) != len(eps):
+        raise ValueError("one plan per eps value")
     for name, X, shape in (("A", A, (M, K)), ("B", B, (K, N))):
         if tuple(X.shape) != shape or X.dtype != plans[0].dtype or not X.is_cuda or X.stride(1) != 1:
             raise ValueError("%s must be a row-major %s CUDA tensor of shape %s" % (name, plans[0].dtype, shape))
@@ -504,8 +509,13 @@ def matmul_apa_ebc(A, B, names, eps, prec="f64", seed=0, mode="none", kappa_scal
         n = ctypes.c_size_t()
         check(lib().rbc_average_workspace(p._h, ctypes.byref(n)))
         need = max(need, n.value)
-    ws = torch.empty(need, dtype=torch.uint8, device=A.device)
-    out = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=A.device)
+    if ws.numel() < need:
+        raise ValueError("workspace of %d bytes < %d needed" % (ws.numel(), need))
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    elif tuple(out.shape) != (M, N) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of shape (%d, %d)" % (M, N))
     hs = (ctypes.c_void_p * len(plans))(*[getattr(p._h, "value", p._h) for p in plans])
     e = (ctypes.c_double * len(eps))(*[float(x) for x in eps])
     st = stream if stream is not None else torch.cuda.current_stream(A.device)

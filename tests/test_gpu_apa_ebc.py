@@ -37,8 +37,8 @@ def test_ebc_f64_matches_oracle_and_is_exact(names, M, K, N, seed, mode):
     _say(names, M, K, N, seed, mode)
     for kind in ("ints", "gauss"):
         if kind == "ints":
-            A = workloads.integers((M, K), 21, -3, 3)
-            B = workloads.integers((K, N), 22, -3, 3)
+            A = workloads.integers((M, K), 21, -3, 3).astype(np.float64)
+            B = workloads.integers((K, N), 22, -3, 3).astype(np.float64)
         else:
             A = workloads.gaussian((M, K), 23)
             B = workloads.gaussian((K, N), 24)
