@@ -34,27 +34,32 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
+F32_LEAF_SOURCES = ("gemm.hip", "tile_f32.hpp", "gemm_tiles.hpp", "occupancy.hpp", "devptr.hpp")
+
+
 def _kernel_source_hash():
-    """Hash of the sources the f32 leaf GEMM is compiled from."""
+    """Hash of the sources the f32 leaf GEMM is compiled from (and nothing else)."""
     h = hashlib.sha256()
-    for f in ("gemm.hip", "gemm_tiles.hpp", "occupancy.hpp", "devptr.hpp", "kernels.hpp"):
+    for f in F32_LEAF_SOURCES:
         with open(os.path.join(ROOT, "paper_1905_07439_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(launch_flops_unused=None):
-    """HBM bytes per leaf-GEMM launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def _traffic():
+    """(HBM bytes per leaf-GEMM launch from the committed rocprofv3 counter summary, note).
+    The bytes are None, with the reason in the note, when there is no summary or the
+    kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "leaf_gemm_f32_n4096_counters.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except OSError:
-        return None
-    if d.get("kernel_source_sha256_16") != _kernel_source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return None, "no counter summary at profiles/leaf_gemm_f32_n4096_counters.json"
+    have, want = d.get("kernel_source_sha256_16"), _kernel_source_hash()
+    if have != want:
+        return None, "stale: counters taken for kernel sources %s, built from %s" % (have, want)
+    return d.get("hbm_bytes_per_launch"), "FETCH_SIZE/WRITE_SIZE (rocprofv3), copy-calibrated: " + d.get("source", "")
 
 
 def cpu_baseline(A, B):
@@ -118,7 +123,7 @@ def approx3072(args):
         elif kind == "bini12":  # one step of the 12 x 12 scheme: <3,2,2>, <2,2,3>, <2,3,2>
             levels = [rbc.Scheme.builtin("%s:%r" % (k, lam)) for k in ("apa322", "apa223", "apa232")]
         else:
-            levels = [rbc.Scheme.perturbed(S, lam, 42)] * q
+            levels = [rbc.Scheme.builtin("perturbed_strassen", lam, 42)] * q
         for prec in ("bf16x3", "f32"):
             plan = rbc.Plan(n, n, n, levels, prec=prec)
             ws = plan.workspace(dev)
@@ -218,11 +223,11 @@ def peaks(args):
     print(json.dumps(out), flush=True)
 
 
-def small64(args):
+def small64_stats(reps, warmup):
     """The small case: plain randomized Strassen in f64, N = 64, two levels (49 leaves of 16^3),
     A, B ~ N(0,1) (seeds 1001/1002) and integers in [-4, 4] (seed 1003 for A, 1004 for B),
     algorithm seed 0, mode full.  Launch-latency bound: per-call latency (HIP events around
-    each call) over --small-reps calls, p50 and p99, and effective TFLOP/s at the p50."""
+    each call) over `reps` calls, p50 and p99 in microseconds."""
     import numpy as np
     import torch
 
@@ -239,9 +244,8 @@ def small64(args):
     C = torch.empty((n, n), dtype=torch.float64, device=dev)
     ws = plan.workspace(dev)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.matmul(A, B, C=C, seed=0, workspace=ws)
-    reps = args.small_reps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     torch.cuda.synchronize()
     for e0, e1 in ev:
@@ -255,17 +259,66 @@ def small64(args):
     err = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
     Ci = plan.matmul(Ai, Bi, seed=0, workspace=ws)
     exact = bool(torch.equal(Ci, Ai @ Bi))
+    return {"p50_us": round(p50, 2), "p99_us": round(float(np.percentile(lat, 99)), 2),
+            "min_us": round(float(lat.min()), 2), "reps": reps,
+            "tflops_at_p50": round(2.0 * n ** 3 / (p50 * 1e-6) / 1e12, 6),
+            "rel_err_vs_fp64": err, "integers_exact": exact}
+
+
+def small64(args):
+    st = small64_stats(args.small_reps, args.warmup)
     out = {"metric": "effective TFLOP/s (2n³/t) at stated rel-err vs FP64 oracle; p50/p99 latency",
-           "value": round(2.0 * n ** 3 / (p50 * 1e-6) / 1e12, 6), "unit": "TFLOP/s", "n_gpus": 1,
-           "steps": reps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64", "data": "synthetic",
+           "value": st["tflops_at_p50"], "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": args.small_reps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "randomized Strassen, f64, N=64, 2 levels (49 leaves of 16^3), N(0,1) and "
-                                  "integers in [-4,4], algorithm seed 0, mode full", "n": n, "levels": 2,
+                                  "integers in [-4,4], algorithm seed 0, mode full", "n": 64, "levels": 2,
                       "parallelism": "single GPU"},
-           "latency_us": {"p50": round(p50, 2), "p99": round(float(np.percentile(lat, 99)), 2),
-                          "min": round(float(lat.min()), 2)},
-           "rel_err_vs_fp64": err, "integers_exact": exact}
+           "latency_us": {"p50": st["p50_us"], "p99": st["p99_us"], "min": st["min_us"]},
+           "rel_err_vs_fp64": st["rel_err_vs_fp64"], "integers_exact": st["integers_exact"]}
     print(json.dumps(out), flush=True)
+
+
+def apa3072_row(steps, warmup, lam=1e-3):
+    """One approximate-scheme row: the rank-10 <3,2,2> APA (1/lambda coefficients in W) at one
+    level, N = 3072 (10 leaves of 1024 x 1536 x 1536), bf16 hi+lo leaves (three bf16 MFMA
+    products, f32 accumulation) with the W-recombination in f64, N(0,1) inputs (seeds
+    3001/3002), mode full, algorithm seeds 0..15.  Reports ms per product (HIP events), the
+    relative error against the f64 product of the same (f32) inputs, and the same plan in f32."""
+    import numpy as np
+    import torch
+
+    import paper_1905_07439_amd as rbc
+    import workloads
+
+    n, dev = 3072, "cuda:0"
+    A = torch.from_numpy(workloads.gaussian((n, n), 3001).astype(np.float32)).to(dev)
+    B = torch.from_numpy(workloads.gaussian((n, n), 3002).astype(np.float32)).to(dev)
+    ref = A.double() @ B.double()
+    C = torch.empty((n, n), dtype=torch.float32, device=dev)
+    S = rbc.Scheme.builtin("apa322", lam)
+    row = {"scheme": "apa322", "levels": 1, "lambda": lam, "mode": "full", "n": n}
+    for prec in ("bf16x3", "f32"):
+        plan = rbc.Plan(n, n, n, [S], prec=prec)
+        ws = plan.workspace(dev)
+        for i in range(warmup):
+            plan.matmul(A, B, C=C, seed=i % 16, workspace=ws)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            plan.matmul(A, B, C=C, seed=i % 16, workspace=ws, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        errs = []
+        for seed in range(2):
+            plan.matmul(A, B, C=C, seed=seed, workspace=ws)
+            errs.append(float(torch.linalg.norm(C.double() - ref) / torch.linalg.norm(ref)))
+        row[prec] = {"ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 2), "leaf_tile": plan.info["tile_m"],
+                     "rel_err_vs_fp64": [float("%.3g" % e) for e in errs]}
+        del plan, ws
+    return row
 
 
 def batch_levels(n):
@@ -603,9 +656,12 @@ def main():
     leaf_ms = stage_ms[2] / calls
     leaf_flops = info["n_leaves"] * 2.0 * info["mM"] * info["mN"] * info["mK"]
     achieved = leaf_flops / (leaf_ms * 1e-3) / 1e12
+    traffic, traffic_note = _traffic()
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
-                "traffic": _traffic()}
+                "traffic": traffic, "traffic_note": traffic_note,
+                "kernel": "leaf GEMM (f32 MFMA 16x16x4, operands formed from the level-2 blocks while loading)",
+                "algorithmic_flops_per_launch": leaf_flops}
     tr = plan.traffic()  # algorithmic bytes of the path the plan takes
     comb_bytes = tr["gather_A"] + tr["gather_B"] + tr["scatter"]
     comb_ms = stage_ms[0] / calls + stage_ms[1] / calls + stage_ms[3] / calls
@@ -627,6 +683,9 @@ def main():
                                        "lib": "torch.matmul (hipBLASLt/rocBLAS)"},
         "roofline": roofline,
     }
+    # the other configurations' headline figures, cheap enough for the default line
+    out["small64_f64_n64_q2"] = small64_stats(1000, 20)
+    out["apa322_n3072_q1_bf16x3"] = apa3072_row(max(5, args.steps // 2), 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A64, B64)
     print(json.dumps(out), flush=True)

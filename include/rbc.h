@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define RBC_ABI_VERSION 1
+#define RBC_ABI_VERSION 2
 #define RBC_MAX_LEVELS 8
 
 typedef enum {
@@ -50,7 +50,8 @@ typedef enum {
   RBC_ESCHEME = 2,      /* scheme residual above tolerance, or |1 - kappa| too small */
   RBC_ENOMEM = 3,       /* workspace too small, or host allocation failed */
   RBC_EHIP = 4,         /* a HIP runtime call failed (message in rbc_last_error) */
-  RBC_EUNSUPPORTED = 5  /* valid request this build does not implement */
+  RBC_EUNSUPPORTED = 5, /* valid request this build does not implement */
+  RBC_EBUSY = 6         /* a shared resource is in use by another host thread; retry later */
 } rbc_status;
 
 /* Randomization modes (Section 3.2: fully randomized, random sign, random
@@ -121,18 +122,35 @@ int rbc_abi_version(void);
  * Limits: 1 <= b1, b2, b3 <= 4, 1 <= R <= 64. */
 rbc_status rbc_scheme_create(int b1, int b2, int b3, int R, const double* U, const double* V,
                              const double* W, double residual_tol, rbc_scheme* out);
-/* Builtin exact schemes: "strassen" (rank 7, 2x2; Strassen 1969 in the form of
- * Golub & Van Loan), "laderman" (rank 23, 3x3; Laderman 1976), and
- * "naive:b1,b2,b3" (the standard algorithm as a BC, R = b1 b2 b3).
- * Builtin approximate schemes (the APA family of Section 1, eq. APA-y: the Brent
- * residual is O(lambda) with no constant term, and W holds 1/lambda
- * coefficients): "apa322:<lambda>", rank 10 for <3,2,2> (two five-product
- * formulas for a 2x2 problem missing one block of A, after Bini et al. 1979),
- * and its cyclic rotations "apa223:<lambda>" (<2,2,3>) and "apa232:<lambda>"
- * (<2,3,2>).  The three as consecutive levels form one step of a rank-1000
- * approximate scheme for 12x12 blocks.  0 < lambda <= 1, else RBC_EINVAL.
- * Rounding errors of the leaf products grow like 1/lambda per APA level. */
-rbc_status rbc_scheme_builtin(const char* name, rbc_scheme* out);
+/* Builtin schemes, by family name; `lambda` and `aux_seed` parameterise the
+ * approximate families and must both be 0 for the exact ones.
+ *   Exact (Brent residual 0, validated in integers):
+ *     "strassen"  rank 7, <2,2,2> (Strassen 1969 in the form of Golub & Van Loan);
+ *     "laderman"  rank 23, <3,3,3> (Laderman 1976);
+ *     "naive:b1,b2,b3"  the standard algorithm as a BC, R = b1 b2 b3.
+ *   Approximate, APA family (Section 1, eq. APA-y: the residual is O(lambda)
+ *   with no constant term and W holds 1/lambda coefficients), 0 < lambda <= 1:
+ *     "apa322"  rank 10 for <3,2,2> (two five-product formulas for a 2x2
+ *               problem missing one block of A, after Bini et al. 1979);
+ *     "apa223", "apa232"  its cyclic rotations (<2,2,3>, <2,3,2>).  The three
+ *               as consecutive levels form one step of a rank-1000 approximate
+ *               scheme for 12x12 blocks.  Rounding errors of the leaf products
+ *               grow like 1/lambda per APA level.
+ *   Approximate, perturbed exact schemes (Section 3.1), 0 <= lambda <= 1:
+ *     "perturbed_strassen", "perturbed_laderman": each of U, V, W gets i.i.d.
+ *     N(0, sigma^2) noise, sigma = lambda, on every entry equal to +1 and on 5
+ *     entries equal to 0 drawn uniformly without replacement.  The random
+ *     numbers are a fixed function of aux_seed: Philox4x64-10 with key
+ *     (aux_seed, 1), blocks at counters (1,0,0,0), (2,0,0,0), ..., words in
+ *     order; per tensor (U, V, W): one normal per +1 entry in row-major order,
+ *     then 5 picks among the zero entries (row-major list, partial Fisher-Yates:
+ *     for i = 0..4, j = i + floor(word (nz - i) / 2^64), swap entries i and j
+ *     of the list), then one normal per pick in pick order.  A word gives
+ *     u = (floor(word / 2^12) + 1/2) 2^-52; a normal is the Box-Muller value
+ *     sqrt(-2 ln u1) cos(2 pi u2) of two consecutive words (libm log, cos,
+ *     sqrt); an entry x becomes fl(x + fl(sigma z)).
+ * Errors: RBC_EINVAL for an unknown name or a lambda / aux_seed out of range. */
+rbc_status rbc_scheme_builtin(const char* name, double lambda, uint64_t aux_seed, rbc_scheme* out);
 /* dims = {b1, b2, b3, R}; tau (Definition 1), kappa (eq. epsilon-def),
  * ||Y||_F (eq. def-y), q = sqrt(sum_r ||U_r||^2 ||V_r||^2 ||W_r||^2)
  * (eq. square-root-of-sum).  Any output pointer may be NULL. */
@@ -259,8 +277,10 @@ rbc_status rbc_accumulate_weighted(double* acc, const void* X, int x_is_f64, int
  * rbc_matmul_apa_ebc: C (device, M x N contiguous f64) = sum_i alpha_i F-hat_i(A, B),
  * F-hat_i from plans[i] (host array of n plans), whose schemes are the
  * approximate scheme at eps[i]: all plans share M, K, N, precision and the block
- * shapes of their levels, and every product uses the draws of (seed, mode) and
- * kappa_scale as rbc_matmul.  A, B as rbc_matmul.  Products are computed one at a
+ * shapes of their levels, and every product uses the draws of (seed, mode) as
+ * rbc_matmul.  The identity sum_i alpha_i Y(eps_i) = X holds for the unscaled
+ * products, so kappa_scale must be 0 unless every level of every plan has
+ * kappa = 0 (then it changes nothing); otherwise RBC_EINVAL.  A, B as rbc_matmul.  Products are computed one at a
  * time into the workspace (at least the largest rbc_average_workspace of the
  * plans) and added in the order i = 0..n-1 with the f64 accumulator.  Errors:
  * RBC_EINVAL for null pointers, bad eps, plans that differ, or a short

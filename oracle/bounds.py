@@ -16,8 +16,11 @@ while n^(-5/2) tau = delta / 2 for n = 2).  ``p`` defaults to the corrected
 The hypotheses "(4n + m + R - 2) eps <= 1.01" of Props. 9-12 are read as
 "<= 0.01", the precondition of Prop. 8 and of Golub & Van Loan Lemma 2.7.1.
 
-Pins: Prop. 4(ii) and the corrected kappa bound hold on every tested draw;
-example13(p=2.5) reproduces the printed 0.0024 (tests/test_oracle_bounds.py).
+Pins (tests/test_oracle_decimal2_bounds.py, tests/test_oracle_tensors.py):
+Prop. 4(ii) and the corrected kappa bound hold on every tested draw;
+example13(p=2.5) reproduces the printed 0.0024; prop5 holds on perturbed
+Strassen and Laderman schemes and equals its closed form on the scaled-W
+family, where the printed constant (p = 5/2) fails for n = 3.
 """
 
 import numpy as np

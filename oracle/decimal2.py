@@ -7,7 +7,7 @@ The BC is evaluated in the same sequential order as the float recursion:
 S_r over (k, l) row-major, T_r likewise, P_r = fl(S_r T_r), C_ij over
 ascending r, zero coefficients skipped.  Blocks are scalars (m = 1, Q = 1).
 
-Pins (tests/test_oracle_decimal2.py): with A = B = [[.99, .001], [.001, .99]]
+Pins (tests/test_oracle_decimal2_bounds.py): with A = B = [[.99, .001], [.001, .99]]
 the deterministic Strassen error is 0.0283 against the printed "approximately
 0.0286", the reversed-column error 0.00015 against "approximately 0.0001",
 and E[g-hat] has the same error for A and for the reversed pair, as printed.

@@ -103,12 +103,3 @@ def leaf_exponent(maxabs, G, target=32768.0):
     _, x = np.frexp(q)
     return int(min(max(int(x) - 1, -120), 120))
 
-
-def pow2_scale(maxabs, target):
-    """Power of two 2^e with maxabs * 2^e <= target (e chosen as large as possible)."""
-    if maxabs == 0 or not np.isfinite(maxabs):
-        return 1.0
-    e = int(np.floor(np.log2(target / maxabs)))
-    while maxabs * 2.0 ** e > target:
-        e -= 1
-    return 2.0 ** e

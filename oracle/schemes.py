@@ -16,6 +16,8 @@ approximate scheme has, in exact rational arithmetic, a Brent residual with no
 constant term that halves with lam.
 """
 
+import math
+
 import numpy as np
 
 
@@ -124,27 +126,61 @@ def rank_one_all_ones(n=2):
     return one.copy(), one.copy(), one.copy()
 
 
-def perturbed(U, V, W, sigma, rng, n_zero=5):
+def aux_words(aux_seed):
+    """Endless raw 64-bit words of Philox4x64-10 with key (aux_seed, 1), blocks at
+    counters (1,0,0,0), (2,0,0,0), ... (numpy's Philox started at counter 0)."""
+    key = np.array([int(aux_seed) & 0xFFFFFFFFFFFFFFFF, 1], dtype=np.uint64)
+    g = np.random.Philox(key=key, counter=np.zeros(4, dtype=np.uint64))
+    while True:
+        for w in g.random_raw(64):
+            yield int(w)
+
+
+def open_unit(word):
+    """u = (floor(word / 2^12) + 1/2) 2^-52, a double in (0, 1) (exact)."""
+    return (float(word >> 12) + 0.5) * 2.0 ** -52
+
+
+def box_muller(words):
+    """One standard normal from two words: sqrt(-2 ln u1) cos(2 pi u2) (Box and Muller 1958)."""
+    u1 = open_unit(next(words))
+    u2 = open_unit(next(words))
+    return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
+def perturbed(U, V, W, sigma, aux_seed, n_zero=5):
     """Approximate scheme of Section 3.1: perturb an exact scheme.
 
     For each of the three tensors independently: add i.i.d. N(0, sigma^2) noise
     to every entry equal to 1, and to n_zero entries equal to 0 chosen uniformly
-    without replacement.  The paper uses sigma = 1e-3 and n_zero = 5.
-    Entries equal to -1 are left unchanged (the paper names entries equal to 1).
-    ``rng`` is a numpy Generator; the draw order is U, V, W and within a tensor
-    the ones (row-major order) first, then the chosen zeros.
+    without replacement.  The paper uses sigma = 1e-3 and n_zero = 5.  Entries
+    equal to -1 are left unchanged (the paper names entries equal to 1).
+
+    Random numbers (a reading: the paper does not say how they are drawn): the
+    words of ``aux_words(aux_seed)`` in order; per tensor (U, V, W): one normal
+    (``box_muller``) per entry equal to 1 in row-major order; then the picks:
+    the row-major list of zero positions, shuffled partially by Fisher-Yates
+    (for i < n_zero: j = i + floor(word * (nz - i) / 2^64), swap items i and j),
+    the first n_zero items picked; then one normal per pick in pick order.  An
+    entry x becomes x + sigma * z, each operation rounded to double.
     """
+    words = aux_words(aux_seed)
     out = []
     for T in (U, V, W):
         T = np.asarray(T, dtype=np.float64).copy()
         flat = T.reshape(-1)
-        ones = np.flatnonzero(flat == 1.0)
-        zeros = np.flatnonzero(flat == 0.0)
-        noise_ones = rng.normal(0.0, sigma, size=ones.size)
-        pick = rng.choice(zeros.size, size=min(n_zero, zeros.size), replace=False)
-        noise_zero = rng.normal(0.0, sigma, size=pick.size)
-        flat[ones] += noise_ones
-        flat[zeros[pick]] += noise_zero
+        zeros = [i for i in range(flat.size) if flat[i] == 0.0]
+        for i in range(flat.size):
+            if flat[i] == 1.0:
+                noise = sigma * box_muller(words)
+                flat[i] = float(flat[i]) + noise
+        picks = min(n_zero, len(zeros))
+        for i in range(picks):
+            j = i + ((next(words) * (len(zeros) - i)) >> 64)
+            zeros[i], zeros[j] = zeros[j], zeros[i]
+        for i in range(picks):
+            noise = sigma * box_muller(words)
+            flat[zeros[i]] = float(flat[zeros[i]]) + noise
         out.append(T)
     return tuple(out)
 

@@ -91,10 +91,6 @@ def ynorm(U, V, W):
     return float(np.sqrt(np.sum(Y * Y)))
 
 
-def xnorm(b1, b2, b3):
-    return float(np.sqrt(b1 * b2 * b3))
-
-
 def q_uvw(U, V, W):
     U = np.asarray(U, np.float64)
     V = np.asarray(V, np.float64)

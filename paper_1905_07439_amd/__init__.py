@@ -38,10 +38,18 @@ class Scheme:
     def __init__(self, handle):
         self._h = ctypes.c_void_p(handle)
 
+    # families whose builtin takes lambda (and, for the perturbed ones, aux_seed)
+    LAMBDA_FAMILIES = ("apa322", "apa223", "apa232", "perturbed_strassen", "perturbed_laderman")
+
     @classmethod
-    def builtin(cls, name):
+    def builtin(cls, name, lam=None, aux_seed=0):
+        """A builtin scheme (include/rbc.h, rbc_scheme_builtin).  For the lambda families
+        the name may carry lambda after a colon ("apa322:0.001"), or lam gives it."""
+        if lam is None and ":" in name and name.split(":", 1)[0] in cls.LAMBDA_FAMILIES:
+            name, lam = name.split(":", 1)
+        lam = 0.0 if lam is None else float(lam)
         h = ctypes.c_void_p()
-        check(lib().rbc_scheme_builtin(name.encode(), ctypes.byref(h)))
+        check(lib().rbc_scheme_builtin(name.encode(), lam, int(aux_seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(h)))
         return cls(h.value)
 
     @classmethod
@@ -57,29 +65,6 @@ class Scheme:
         h = ctypes.c_void_p()
         check(lib().rbc_scheme_create(b1, b2, b3, R, up, vp, wp, float(residual_tol), ctypes.byref(h)))
         return cls(h.value)
-
-    @classmethod
-    def perturbed(cls, base, sigma, seed, n_zero=5):
-        """Approximate scheme of Section 3.1 built from an exact ``base``.
-
-        Independently for U, V, W: i.i.d. N(0, sigma^2) noise on every entry
-        equal to 1 and on ``n_zero`` entries equal to 0 picked without
-        replacement (numpy PCG64 stream of ``seed``; ones in row-major order
-        first, then the picked zeros).  The result is accepted whatever its
-        Brent residual.
-        """
-        g = np.random.Generator(np.random.PCG64(seed))
-        out = []
-        for T in base.tensors():
-            T = T.copy()
-            flat = T.reshape(-1)
-            ones = np.flatnonzero(flat == 1.0)
-            zeros = np.flatnonzero(flat == 0.0)
-            flat[ones] += g.normal(0.0, sigma, size=ones.size)
-            pick = g.choice(zeros.size, size=min(n_zero, zeros.size), replace=False)
-            flat[zeros[pick]] += g.normal(0.0, sigma, size=pick.size)
-            out.append(T)
-        return cls.from_tensors(*out, residual_tol=float("inf"))
 
     def info(self):
         dims = (ctypes.c_int * 4)()
@@ -491,10 +476,12 @@ def matmul_apa_ebc(A, B, names, eps, prec="f64", seed=0, mode="none", kappa_scal
     """The exact product from an approximate scheme: sum_i alpha_i F-hat(A, B) with the
     levels ``names`` at eps[i] (apa entries take eps[i], see apa_scheme_levels), every
     product with the draws of (seed, mode), combined on the device in f64 in the order
-    of eps (a new float64 M x N tensor)."""
+    of eps (a new float64 M x N tensor).  The products are not scaled by (1 - kappa)^-1
+    (the combination is exact only for the unscaled ones); kappa_scale=True is accepted
+    only when every level has kappa = 0, where it changes nothing."""
     import torch
     if kappa_scale is None:
-        kappa_scale = mode != "none"
+        kappa_scale = False
     M, K = A.shape
     N = B.shape[1]
     if plans is None:

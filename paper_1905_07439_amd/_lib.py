@@ -6,7 +6,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbc.so")
 
-RBC_OK, RBC_EINVAL, RBC_ESCHEME, RBC_ENOMEM, RBC_EHIP, RBC_EUNSUPPORTED = range(6)
+RBC_OK, RBC_EINVAL, RBC_ESCHEME, RBC_ENOMEM, RBC_EHIP, RBC_EUNSUPPORTED, RBC_EBUSY = range(7)
 MODES = {"full": 0, "signs": 1, "perms": 2, "none": 3}
 PRECS = {"f64": 0, "f32": 1, "bf16x3": 2, "f16s": 3, "fp8c": 4}
 
@@ -64,7 +64,7 @@ SIGNATURES = {
     "rbc_abi_version": (ctypes.c_int, []),
     "rbc_scheme_create": (ctypes.c_int, [ctypes.c_int] * 4 + [c_dbl_p] * 3 + [ctypes.c_double,
                                                                               ctypes.POINTER(c_vp)]),
-    "rbc_scheme_builtin": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(c_vp)]),
+    "rbc_scheme_builtin": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(c_vp)]),
     "rbc_scheme_info": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_int)] + [c_dbl_p] * 4),
     "rbc_scheme_tensors": (ctypes.c_int, [c_vp] + [c_dbl_p] * 3),
     "rbc_scheme_destroy": (None, [c_vp]),
@@ -129,7 +129,8 @@ class RbcError(RuntimeError):
 
 
 STATUS_NAMES = {RBC_OK: "ok", RBC_EINVAL: "RBC_EINVAL", RBC_ESCHEME: "RBC_ESCHEME",
-                RBC_ENOMEM: "RBC_ENOMEM", RBC_EHIP: "RBC_EHIP", RBC_EUNSUPPORTED: "RBC_EUNSUPPORTED"}
+                RBC_ENOMEM: "RBC_ENOMEM", RBC_EHIP: "RBC_EHIP", RBC_EUNSUPPORTED: "RBC_EUNSUPPORTED",
+                RBC_EBUSY: "RBC_EBUSY"}
 
 
 def lib():

@@ -27,7 +27,8 @@ HOST_ONLY = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 def _extra(name):
     # The block-combination kernels (stand-alone and inside the batch engine)
     # must not contract c * x + acc into an FMA.
-    return ["-ffp-contract=off"] if name.startswith(("combine", "batch")) else []
+    # The scheme builder's perturbation (x + sigma z) rounds the product and the sum apart.
+    return ["-ffp-contract=off"] if name.startswith(("combine", "batch", "scheme")) else []
 
 
 def _hipcc():

@@ -49,6 +49,7 @@ const char* rbc_status_str(rbc_status s) {
     case RBC_ENOMEM: return "out of memory";
     case RBC_EHIP: return "HIP error";
     case RBC_EUNSUPPORTED: return "unsupported";
+    case RBC_EBUSY: return "busy";
   }
   return "unknown status";
 }
@@ -70,12 +71,12 @@ rbc_status rbc_scheme_create(int b1, int b2, int b3, int R, const double* U, con
   RBC_GUARD_END
 }
 
-rbc_status rbc_scheme_builtin(const char* name, rbc_scheme* out) {
+rbc_status rbc_scheme_builtin(const char* name, double lambda, uint64_t aux_seed, rbc_scheme* out) {
   RBC_GUARD_BEGIN
   if (!out) return fail(RBC_EINVAL, "null output handle");
   *out = nullptr;
   Scheme s;
-  rbc_status st = builtin_scheme(name, s);
+  rbc_status st = builtin_scheme(name, lambda, aux_seed, s);
   if (st != RBC_OK) return st;
   *out = new rbc_scheme_s{std::move(s)};
   return RBC_OK;
@@ -463,6 +464,13 @@ rbc_status rbc_matmul_apa_ebc(const rbc_plan* plans, const double* eps, int64_t 
     seeded_draws(p, seed, mode, s, pm);
     if (s != s0 || pm != pm0) return fail(RBC_EINVAL, "plans[%lld] differs from plans[0] in its levels' block shapes",
                                           (long long)i);
+    // The weights make sum_i alpha_i Y(eps_i) = X for the unscaled Y; a level with
+    // kappa != 0 scaled by (1 - kappa)^-1 would break that identity.
+    if (kappa_scale)
+      for (int d = 0; d < p.Q; ++d)
+        if (p.levels[d].kappa != 0.0)
+          return fail(RBC_EINVAL, "kappa_scale with plans[%lld] level %d: kappa = %.17g != 0 (the combination "
+                      "is exact only for the unscaled products)", (long long)i, d, p.levels[d].kappa);
     size_t b = 0;
     if ((st = rbc_average_workspace(plans[i], &b)) != RBC_OK) return st;
     need = b > need ? b : need;

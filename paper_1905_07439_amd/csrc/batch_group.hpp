@@ -9,7 +9,9 @@
 
 #include "batch.hpp"
 #include "combine.hpp"
-#include "gemm_tiles.hpp"
+#include "tile_f32.hpp"
+#include "tile_fp8.hpp"
+#include "tile_lowp.hpp"
 #include "scale.hpp"
 
 namespace rbc {

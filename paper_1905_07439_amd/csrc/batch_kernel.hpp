@@ -18,7 +18,9 @@
 
 #include "batch.hpp"
 #include "combine.hpp"
-#include "gemm_tiles.hpp"
+#include "tile_f32.hpp"
+#include "tile_fp8.hpp"
+#include "tile_lowp.hpp"
 #include "scale.hpp"
 
 namespace rbc {
@@ -212,7 +214,10 @@ __device__ __noinline__ void leader_signal(int32_t* ctl, int32_t t, int32_t sign
     // XCD can see the counter, invalidate its caches and still read the old
     // bytes from memory.
     __builtin_amdgcn_s_waitcnt(0);
-    if (signal >= 0) atomicAdd(ctl + CTL_WORDS + signal, count);
+    // The update itself is a release operation at agent scope as well, so that
+    // the ordering does not rest on the fence and the wait alone.
+    if (signal >= 0)
+      __hip_atomic_fetch_add(ctl + CTL_WORDS + signal, count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (trace) trace[(int64_t)t * 4 + 2] = wall_clock64();
   }
 }

@@ -33,7 +33,7 @@ struct Scheme {
 void analyse(Scheme& s);
 rbc_status make_scheme(int b1, int b2, int b3, int R, const double* U, const double* V,
                        const double* W, double residual_tol, Scheme& out);
-rbc_status builtin_scheme(const char* name, Scheme& out);
+rbc_status builtin_scheme(const char* name, double lambda, uint64_t aux_seed, Scheme& out);
 
 // ---- draws (Section 2.1) ----------------------------------------------------
 void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

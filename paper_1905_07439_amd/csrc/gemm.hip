@@ -26,7 +26,7 @@
 // read straight from global memory (small leaves; latency bound).
 #include <hip/hip_runtime.h>
 
-#include "gemm_tiles.hpp"
+#include "tile_f32.hpp"
 #include "occupancy.hpp"
 
 namespace rbc {

@@ -1,10 +1,10 @@
 // fp8 leaf products with one correction pass on CDNA4 matrix cores (the tile
-// is described in gemm_tiles.hpp): P = 2^-(eS + eT) (hi hi + (hi lo + lo hi) / 16)
+// is described in tile_fp8.hpp): P = 2^-(eS + eT) (hi hi + (hi lo + lo hi) / 16)
 // with S = 2^-eS (hi + lo / 16) and likewise T, every byte an OCP e4m3 value.
 // The dropped lo lo term is below 2^-8 relative to |S||T|.
 #include <hip/hip_runtime.h>
 
-#include "gemm_tiles.hpp"
+#include "tile_fp8.hpp"
 #include "occupancy.hpp"
 
 namespace rbc {

@@ -9,7 +9,7 @@
 //
 // Tile BM x BN (32, 64, 96 or 128) per workgroup of 4 wavefronts, each a
 // (BM/2) x (BN/2) quarter of 16x16 MFMA tiles, K slabs of 32 (the tile is
-// described in gemm_tiles.hpp: S operands are 16-byte LDS reads, T operands
+// described in tile_lowp.hpp: S operands are 16-byte LDS reads, T operands
 // transposing LDS reads).  Two LDS buffers: a slab held in registers is
 // written to one, one barrier, then the next slab's global loads stay in
 // flight while the MFMAs consume the buffer.  Block ids are remapped so that
@@ -17,7 +17,7 @@
 // last round of the resident grid as tiles of half the side (split_tail).
 #include <hip/hip_runtime.h>
 
-#include "gemm_tiles.hpp"
+#include "tile_lowp.hpp"
 #include "occupancy.hpp"
 
 namespace rbc {

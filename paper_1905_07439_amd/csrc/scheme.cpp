@@ -224,8 +224,95 @@ static void rotate_scheme(int& b1, int& b2, int& b3, int R, std::vector<double>&
   U.swap(U2), V.swap(V2), W.swap(W2);
 }
 
-rbc_status builtin_scheme(const char* name, Scheme& out) {
+// ---- approximate schemes of Section 3.1 (perturbed exact schemes) ----------
+//
+// Each of U, V, W gets i.i.d. N(0, sigma^2) noise on every entry equal to +1
+// and on n_zero = 5 entries equal to 0 drawn uniformly without replacement.
+// The random numbers come from Philox4x64-10 with key (aux_seed, 1) (the level
+// draws use key word 1 = 0), blocks at counters (1,0,0,0), (2,0,0,0), ...,
+// four words each, consumed in order:
+//   tensor by tensor (U, V, W): one normal per +1 entry in row-major order;
+//   then the picks: positions of the zero entries in row-major order, partial
+//   Fisher-Yates: for i = 0..n_zero-1, j = i + floor(word (nz - i) / 2^64),
+//   swap; the first n_zero positions are picked; then one normal per pick in
+//   pick order.
+// A word maps to u = (floor(word / 2^12) + 1/2) 2^-52 in (0, 1), exact in
+// double; a normal takes two words, u1 then u2, and is the Box-Muller value
+// sqrt(-2 ln u1) cos(2 pi u2) (Box and Muller 1958).  An entry becomes
+// x + sigma z with one rounding for the product and one for the sum.
+namespace {
+struct AuxStream {
+  uint64_t key[2], ctr[4] = {0, 0, 0, 0}, buf[4];
+  int pos = 4;
+  explicit AuxStream(uint64_t aux_seed) { key[0] = aux_seed, key[1] = 1; }
+  uint64_t next() {
+    if (pos == 4) {
+      ++ctr[0];
+      philox4x64_10(ctr, key, buf);
+      pos = 0;
+    }
+    return buf[pos++];
+  }
+};
+
+double open_unit(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+
+double box_muller(AuxStream& st) {
+  const double u1 = open_unit(st.next());
+  const double u2 = open_unit(st.next());
+  const double two_pi = 6.283185307179586;  // 2 pi rounded to double
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2);
+}
+
+void perturb_tensor(std::vector<double>& T, double sigma, int n_zero, AuxStream& st) {
+#pragma STDC FP_CONTRACT OFF
+  std::vector<size_t> zeros;
+  for (size_t i = 0; i < T.size(); ++i)
+    if (T[i] == 0.0) zeros.push_back(i);
+  for (size_t i = 0; i < T.size(); ++i)
+    if (T[i] == 1.0) {
+      const double noise = sigma * box_muller(st);
+      T[i] = T[i] + noise;
+    }
+  const size_t nz = zeros.size(), picks = (size_t)n_zero < nz ? (size_t)n_zero : nz;
+  for (size_t i = 0; i < picks; ++i) {
+    const unsigned __int128 p = (unsigned __int128)st.next() * (uint64_t)(nz - i);
+    const size_t j = i + (size_t)(uint64_t)(p >> 64);
+    const size_t t = zeros[i];
+    zeros[i] = zeros[j];
+    zeros[j] = t;
+  }
+  for (size_t i = 0; i < picks; ++i) {
+    const double noise = sigma * box_muller(st);
+    T[zeros[i]] = T[zeros[i]] + noise;
+  }
+}
+}  // namespace
+
+rbc_status builtin_scheme(const char* name, double lambda, uint64_t aux_seed, Scheme& out) {
   if (!name) return fail(RBC_EINVAL, "null scheme name");
+  if (!std::strncmp(name, "perturbed_", 10)) {
+    if (std::strcmp(name + 10, "strassen") && std::strcmp(name + 10, "laderman"))
+      return fail(RBC_EINVAL, "unknown builtin scheme '%s' (perturbed_strassen, perturbed_laderman)", name);
+    if (!(lambda >= 0.0) || !(lambda <= 1.0))
+      return fail(RBC_EINVAL, "%s: sigma = %g outside [0, 1]", name, lambda);
+    Scheme base;
+    rbc_status st = builtin_scheme(name + 10, 0.0, 0, base);
+    if (st != RBC_OK) return st;
+    AuxStream rng(aux_seed);
+    perturb_tensor(base.U, lambda, 5, rng);
+    perturb_tensor(base.V, lambda, 5, rng);
+    perturb_tensor(base.W, lambda, 5, rng);
+    return make_scheme(base.b1, base.b2, base.b3, base.R, base.U.data(), base.V.data(), base.W.data(),
+                       INFINITY, out);
+  }
+  const bool apa = !std::strcmp(name, "apa322") || !std::strcmp(name, "apa223") || !std::strcmp(name, "apa232");
+  if (apa) {
+    if (!(lambda > 0.0) || !(lambda <= 1.0))
+      return fail(RBC_EINVAL, "%s: lambda = %g outside (0, 1]", name, lambda);
+  } else if (lambda != 0.0 || aux_seed != 0) {
+    return fail(RBC_EINVAL, "exact scheme '%s' takes lambda = 0 and aux_seed = 0", name);
+  }
   std::vector<double> U, V, W;
   int b1, b2, b3, R;
   if (!std::strcmp(name, "strassen")) {
@@ -262,14 +349,9 @@ rbc_status builtin_scheme(const char* name, Scheme& out) {
           V[(l * b3 + j) * R + r] = 1;
           W[(i * b3 + j) * R + r] = 1;
         }
-  } else if (!std::strncmp(name, "apa322:", 7) || !std::strncmp(name, "apa223:", 7) ||
-             !std::strncmp(name, "apa232:", 7)) {
-    char* end = nullptr;
-    const double lam = std::strtod(name + 7, &end);
-    if (end == name + 7 || *end != '\0' || !(lam > 0.0) || !(lam <= 1.0))
-      return fail(RBC_EINVAL, "expected %.6s:<lambda> with 0 < lambda <= 1, got '%s'", name, name);
+  } else if (apa) {
     b1 = 3, b2 = 2, b3 = 2, R = 10;
-    apa322(lam, U, V, W);
+    apa322(lambda, U, V, W);
     const int turns = name[3] == '3' ? 0 : (name[5] == '3' ? 1 : 2);  // 322, 223, 232
     for (int t = 0; t < turns; ++t) rotate_scheme(b1, b2, b3, R, U, V, W);
     return make_scheme(b1, b2, b3, R, U.data(), V.data(), W.data(), INFINITY, out);

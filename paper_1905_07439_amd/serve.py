@@ -188,7 +188,7 @@ class GpuExecutor:
         self.keep = keep  # dict rid -> C (and operands) for requests to keep, or None
         S = rbc.Scheme.builtin("strassen")
         self.schemes = {"strassen": S, "laderman": rbc.Scheme.builtin("laderman"),
-                        "approx": rbc.Scheme.perturbed(S, APPROX_LAMBDA, 42)}
+                        "approx": rbc.Scheme.builtin("perturbed_strassen", APPROX_LAMBDA, 42)}
         self.gen = torch.Generator(device=device)
 
     def plan(self, r):

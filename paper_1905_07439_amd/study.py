@@ -39,9 +39,8 @@ def matrices(kind, n, seed):
     if kind == "hilbert":
         H = workloads.hilbert(n)
         return H, H.copy()
-    if kind.startswith("adversarial"):
-        t = int(kind[-1])
-        return workloads.adversarial(t, n, seed), workloads.adversarial(t, n, seed + 1)
+    if kind.startswith("adversarial"):  # a pair of Definition 14's type 1, 2 or 3
+        return workloads.adversarial(int(kind[-1]), n, seed)
     raise ValueError("unknown matrix kind %r" % kind)
 
 
@@ -49,7 +48,7 @@ def _schemes(name, q):
     import paper_1905_07439_amd as rbc
     S = rbc.Scheme.builtin("strassen")
     if name == "pert":  # Section 3.1: sigma = 1e-3 on the ones and on five zeros per tensor
-        return [rbc.Scheme.perturbed(S, 1e-3, 42)] * q
+        return [rbc.Scheme.builtin("perturbed_strassen", 1e-3, 42)] * q
     return [rbc.Scheme.builtin(name)] * q
 
 

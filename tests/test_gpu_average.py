@@ -30,7 +30,7 @@ def _say(*a):
 
 def _pert():
     S = rbc.Scheme.builtin("strassen")
-    P = rbc.Scheme.perturbed(S, 1e-3, 42)
+    P = rbc.Scheme.builtin("perturbed_strassen", 1e-3, 42)
     return P, tuple(np.asarray(x) for x in P.tensors())
 
 
@@ -83,3 +83,51 @@ def test_error_distribution_harness():
     for k, v in res["errors"].items():
         assert all(np.isfinite(v)) and all(0 < x < 1e-3 for x in v), k
     assert len(res["errors"]["Q1/none"]) == 1 and len(res["errors"]["Q1/full"]) == 4
+
+
+def _pert_levels(q):
+    return [osch.perturbed(*osch.strassen(), 1e-3, 42)] * q
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "adversarial1", "hilbert"])
+def test_error_distribution_matches_oracle(kind):
+    # The harness's per-trial errors (Section 3.1 setting: perturbed Strassen, f64) against
+    # the errors of the oracle's F-hat^(Q) on the same draws (trial t = algorithm seed t),
+    # for Q = 1..3 and the four modes.  The errors are ~1e-3 (algorithmic); a wrong draw,
+    # mode or fold would move them far more than the 1e-12 allowed.
+    n = 64
+    res = study.error_distribution(kind, n=n, qs=(1, 2, 3), trials=3, scheme="pert", prec="f64")
+    A, B = study.matrices(kind, n, 1)
+    AB = A @ B
+    for q in (1, 2, 3):
+        plan = rbc.Plan(n, n, n, [rbc.Scheme.builtin("perturbed_strassen", 1e-3, 42)] * q, prec="f64")
+        dims = (plan.info["mM"], plan.info["mK"], plan.info["mN"])
+        for m in study.MODES:
+            errs = res["errors"]["Q%d/%s" % (q, m)]
+            assert len(errs) == (1 if m == "none" else 3)
+            for t, e in enumerate(errs):
+                C = recursion.rbc_seeded(A, B, _pert_levels(q), t, m, leaf_dims=dims)
+                e_or = recursion.rel_err(C, AB)
+                assert e_or > 1e-6 and abs(e - e_or) <= 1e-12, (kind, q, m, t, e, e_or)
+    _say("error distribution %s matches the oracle; Q3 full %s" % (kind, res["errors"]["Q3/full"]))
+
+
+@pytest.mark.parametrize("mode", ["full", "signs"])
+def test_error_of_average_matches_oracle(mode):
+    # The harness's error-of-average curve (eq. error-of-average) against the oracle's average
+    # of F-hat over the same seeds 0..k-1, at each checkpoint k.
+    n, K = 64, 8
+    res = study.error_of_average("adversarial1", n=n, qs=(1, 2, 3), K=K, checkpoints=(1, 2, 5, 8), scheme="pert",
+                                 prec="f64", mode=mode)
+    A, B = study.matrices("adversarial1", n, 1)
+    AB = A @ B
+    for q in (1, 2, 3):
+        plan = rbc.Plan(n, n, n, [rbc.Scheme.builtin("perturbed_strassen", 1e-3, 42)] * q, prec="f64")
+        dims = (plan.info["mM"], plan.info["mK"], plan.info["mN"])
+        acc = np.zeros((n, n))
+        curve = dict(res["curves"]["Q%d" % q])
+        for k in range(1, K + 1):
+            acc += recursion.rbc_seeded(A, B, _pert_levels(q), k - 1, mode, leaf_dims=dims)
+            if k in curve:
+                e_or = recursion.rel_err(acc / k, AB)
+                assert abs(curve[k] - e_or) <= 1e-12 * max(1.0, e_or / 1e-3), (q, k, curve[k], e_or)

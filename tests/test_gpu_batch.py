@@ -37,7 +37,7 @@ _PLANS = {}
 def _scheme(name):
     if name.startswith("pert:"):  # perturbed Strassen, pert:<sigma>:<seed>
         _, sigma, seed = name.split(":")
-        return rbc.Scheme.perturbed(rbc.Scheme.builtin("strassen"), float(sigma), int(seed))
+        return rbc.Scheme.builtin("perturbed_strassen", float(sigma), int(seed))
     return rbc.Scheme.builtin(name)
 
 

@@ -52,8 +52,8 @@ def _schemes(names):
         elif n.startswith("pert:"):
             _, sigma, seed = n.split(":")
             base = osch.strassen()
-            lib.append(rbc.Scheme.perturbed(rbc.Scheme.builtin("strassen"), float(sigma), int(seed)))
-            ref.append(osch.perturbed(*base, float(sigma), np.random.default_rng(int(seed))))
+            lib.append(rbc.Scheme.builtin("perturbed_strassen", float(sigma), int(seed)))
+            ref.append(osch.perturbed(*base, float(sigma), int(seed)))
         else:
             lib.append(rbc.Scheme.builtin(n))
             ref.append(BASE[n]())
@@ -96,7 +96,7 @@ GATHER_CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(GATHER_CASES)))
-@pytest.mark.parametrize("mode", ["full", "none"])
+@pytest.mark.parametrize("mode", ["full", "none", "signs", "perms"])
 def test_gather_and_scatter_bit_exact(case, mode):
     names, M, K, N, prec, tile = GATHER_CASES[case]
     _say("gather/scatter case", names, M, K, N, prec, mode)
@@ -501,7 +501,7 @@ def test_results_are_deterministic_and_stream_ordered():
     assert not torch.equal(C1, C3)
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16s", "fp8c"])
+@pytest.mark.parametrize("prec", ["f32", "f16s", "fp8c", "bf16x3"])
 def test_tail_split_tiles_give_the_same_bits(prec):
     # N = 2048, Q = 2: 49 leaves of 512^2, 784 tiles of 128 -- more than one round of the resident
     # grid and not a whole number of rounds, so the last round runs as 64-tiles; the products must
@@ -602,3 +602,79 @@ def test_fusion_choice_same_bits(prec, n, q):
         C2 = m.matmul(A, B, seed=seed)
         torch.cuda.synchronize()
         assert torch.equal(C1, C2), (seed, float((C1 - C2).abs().max()))
+
+
+# Leaf products of the 16-bit formats, element by element.  The plans only lay out the
+# workspace: the test writes its own leaf operands (bf16 hi and lo planes from a split of
+# f32 values; f16 values and per-leaf exponents), runs the leaf stage alone and compares
+# every product (or every product on sampled rows) with the f64 product of the same bits.
+# Tile counts: 161 leaves x 16 (128-tiles) = 2576 and x 64 (64-tiles) = 10304 are no
+# whole number of rounds of any resident grid of 256 x (1..8) workgroups and exceed one
+# round, so those launches run their last round as tiles of half the side.
+LOWP_LEAF_CASES = [
+    # (prec, schemes, M, K, N, tile, sampled rows or 0 for all)
+    ("bf16x3", ["laderman", "strassen"], 3072, 384, 3072, 128, 0),
+    ("bf16x3", ["laderman", "strassen"], 3072, 384, 3072, 64, 0),
+    ("bf16x3", ["apa322:0.001"], 3072, 3072, 3072, 128, 24),   # the approximate-scheme leaves, 1024 x 1536 x 1536
+    ("f16s", ["laderman", "strassen"], 3072, 384, 3072, 128, 0),
+    ("f16s", ["laderman", "strassen"], 3072, 384, 3072, 64, 0),
+    ("f16s", ["laderman", "strassen"], 1728, 192, 1728, 96, 0),
+    ("f16s", ["laderman", "strassen"], 384, 384, 384, 32, 0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(LOWP_LEAF_CASES)))
+def test_lowp_leaf_products_elementwise(case):
+    prec, names, M, K, N, tile, nrows = LOWP_LEAF_CASES[case]
+    lib_s, _ = _schemes(names)
+    plan = rbc.Plan(M, K, N, lib_s, prec=prec, leaf_tile=tile)
+    info = plan.info
+    L, m, k, n = info["n_leaves"], info["mM"], info["mK"], info["mN"]
+    assert info["tile_m"] == tile
+    _say("lowp leaf", prec, tile, "leaves", L, "leaf", (m, k, n), "tiles", L * (m // tile) * (n // tile))
+    g = np.random.default_rng(100 + case)
+    ws = torch.zeros(info["workspace_bytes"], dtype=torch.uint8, device=DEV)
+    if prec == "bf16x3":
+        S = g.standard_normal((L, m, k)).astype(np.float32)
+        T = g.standard_normal((L, k, n)).astype(np.float32) * np.float32(3.0)
+        planes = []
+        for X in (S, T):
+            hi, lo = precision.split_hi_lo(X, "bf16")
+            planes.append((hi, lo))
+            bits = np.stack([(hi.view(np.uint32) >> 16).astype(np.uint16), (lo.view(np.uint32) >> 16).astype(np.uint16)])
+            off = info["off_S"] if X is S else info["off_T"]
+            ws[off:off + bits.nbytes].copy_(torch.from_numpy(bits.view(np.uint8).reshape(-1)))
+        (sh, sl), (th, tl) = planes
+        passes = 3
+    else:
+        S16 = (g.standard_normal((L, m, k)) * 100.0).astype(np.float16)
+        T16 = (g.standard_normal((L, k, n)) * 0.01).astype(np.float16)
+        ex = g.integers(-6, 7, size=(2, L)).astype(np.int32)
+        for X, off in ((S16, info["off_S"]), (T16, info["off_T"])):
+            ws[off:off + X.nbytes].copy_(torch.from_numpy(X.view(np.uint8).reshape(-1)))
+        a = info["off_aux"] + AUX_EXPS
+        ws[a:a + ex.nbytes].copy_(torch.from_numpy(ex.view(np.uint8).reshape(-1)))
+        passes = 1
+    plan.stage_leaf(ws)
+    torch.cuda.synchronize()
+    P = _region(ws, info["off_P"], info["bytes_P"], torch.float32, (L, m, n))
+    rows = np.arange(m) if not nrows else np.unique(np.concatenate(
+        [[0, 1, m // 2, m - 1], g.integers(0, m, size=nrows)]))
+    gK = passes * k * 2.0 ** -24 / (1 - passes * k * 2.0 ** -24)
+    worst = 0.0
+    for l in range(L):
+        if prec == "bf16x3":
+            a_h, a_l = sh[l][rows].astype(np.float64), sl[l][rows].astype(np.float64)
+            b_h, b_l = th[l].astype(np.float64), tl[l].astype(np.float64)
+            ref = a_h @ b_h + a_h @ b_l + a_l @ b_h
+            mag = np.abs(a_h) @ np.abs(b_h) + np.abs(a_h) @ np.abs(b_l) + np.abs(a_l) @ np.abs(b_h)
+        else:
+            sc = -(int(ex[0, l]) + int(ex[1, l]))
+            a16, b16 = S16[l][rows].astype(np.float64), T16[l].astype(np.float64)
+            ref = np.ldexp(a16 @ b16, sc)
+            mag = np.ldexp(np.abs(a16) @ np.abs(b16), sc)
+        bound = gK * mag + 2.0 ** -24 * np.abs(ref) + 1e-38
+        d = np.abs(P[l][rows].astype(np.float64) - ref)
+        worst = max(worst, float(np.max(d / bound)))
+        assert np.all(d <= bound), (l, float(np.max(d / bound)))
+    _say("lowp leaf %s tile %d: max |P - ref| / bound = %.3g" % (prec, tile, worst))

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
         assert n in _lib.SIGNATURES, n
-    assert L.rbc_abi_version() == 1
+    assert L.rbc_abi_version() == 2
 
 
 @pytest.mark.parametrize("name,builder", [("strassen", oschemes.strassen), ("laderman", oschemes.laderman)])
@@ -61,8 +61,12 @@ def test_apa_builtins_match_oracle(name, dims, lam):
     U, V, W = getattr(oschemes, name)(lam)
     assert i["tau"] == pytest.approx(otensors.tau(U, V, W), rel=1e-12)
     assert i["kappa"] == pytest.approx(otensors.kappa(U, V, W), abs=1e-12)
-    for bad in ("0", "-0.1", "1.5", "", "1e-3x", "nan"):
-        with pytest.raises(rbc.RbcError):
+    for bad in (0.0, -0.1, 1.5, float("nan"), float("inf")):
+        with pytest.raises(rbc.RbcError) as e:
+            rbc.Scheme.builtin(name, bad)
+        assert e.value.status == _lib.RBC_EINVAL
+    for bad in ("", "1e-3x"):  # the binding's name parsing
+        with pytest.raises(ValueError):
             rbc.Scheme.builtin("%s:%s" % (name, bad))
     # three levels at N = 3072: b^3 blocks per dimension, zero padding to whole leaves
     p = rbc.Plan(3072, 3072, 3072, [s] * 3, prec="bf16x3")
@@ -80,10 +84,13 @@ def test_naive_builtin_and_rank_one_scheme():
     assert one.info()["tau"] == pytest.approx(math.sqrt(56.0), rel=1e-15)
 
 
-def test_perturbed_scheme_matches_oracle_recipe_and_kappa():
-    for sigma, seed in [(1e-3, 0), (1e-1, 7)]:
-        s = rbc.Scheme.perturbed(rbc.Scheme.builtin("strassen"), sigma, seed)
-        ref = oschemes.perturbed(*oschemes.strassen(), sigma, np.random.default_rng(seed))
+@pytest.mark.parametrize("base", ["strassen", "laderman"])
+def test_perturbed_scheme_matches_oracle_recipe_and_kappa(base):
+    # The library's seeded perturbation (Philox words, Box-Muller normals, partial
+    # Fisher-Yates picks) and the oracle's, written separately, agree to the bit.
+    for sigma, seed in [(1e-3, 0), (1e-1, 7), (1e-4, 42), (0.5, 2 ** 64 - 1), (1e-2, 12345)]:
+        s = rbc.Scheme.builtin("perturbed_" + base, sigma, seed)
+        ref = oschemes.perturbed(*getattr(oschemes, base)(), sigma, seed)
         for a, b in zip(s.tensors(), ref):
             np.testing.assert_array_equal(a, b)
         i = s.info()
@@ -107,6 +114,13 @@ def test_scheme_validation_errors():
     assert e.value.status == _lib.RBC_EINVAL
     with pytest.raises(rbc.RbcError):
         rbc.Scheme.builtin("winograd")
+    # exact schemes take no lambda or aux seed; the approximate ones need lambda in range
+    for name, lam, seed in [("strassen", 0.1, 0), ("laderman", 0.0, 3), ("apa322", 0.0, 0), ("apa223", 2.0, 0),
+                            ("perturbed_strassen", -1e-3, 0), ("perturbed_strassen", float("nan"), 0),
+                            ("perturbed_winograd", 1e-3, 0)]:
+        with pytest.raises(rbc.RbcError) as e:
+            rbc.Scheme.builtin(name, lam, seed)
+        assert e.value.status == _lib.RBC_EINVAL, (name, lam, seed)
 
 
 @pytest.mark.parametrize("b", [(2, 2, 2), (3, 3, 3), (3, 2, 2), (1, 4, 2)])
@@ -121,7 +135,7 @@ def test_draws_match_oracle(b, mode):
 
 
 def test_fold_matches_oracle_bitwise():
-    base = oschemes.perturbed(*oschemes.laderman(), 1e-2, np.random.default_rng(3))
+    base = oschemes.perturbed(*oschemes.laderman(), 1e-2, 3)
     s = rbc.Scheme.from_tensors(*base, residual_tol=math.inf)
     for seed in range(10):
         sg, pm = rbc.draw(seed, 1, 3, 3, 3)

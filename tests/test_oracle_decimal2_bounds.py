@@ -79,3 +79,44 @@ def test_prop9_bound_holds_in_float32_blocks():
         exact = recursion.rbc_seeded(A, B, [(U, V, W)], seed)
         fl = recursion.rbc_seeded(A, B, [(U, V, W)], seed, arith="f32")
         assert np.linalg.norm(fl - exact) <= bounds.prop9(2, 16, 7, eps, mu, q)
+
+
+def _prop5_lhs(U, V, W, mu):
+    """|eta| mu^2 ||Y|| of Prop. 5, eta = (1 - kappa)^-1 - 1, from the oracle's kappa and ||Y||."""
+    return abs(bounds.eta(float(tensors.kappa(U, V, W)))) * mu * mu * tensors.ynorm(U, V, W)
+
+
+def test_prop5_holds_on_perturbed_schemes():
+    # Prop. 5 (with the corrected |kappa| <= n^(-3/2) tau) on perturbed Strassen (n = 2)
+    # and Laderman (n = 3) at several noise levels, where |kappa| <= 1/2.
+    for base, n in ((schemes.strassen(), 2), (schemes.laderman(), 3)):
+        for sigma in (1e-4, 1e-3, 1e-2, 1e-1, 0.3):
+            for seed in range(5):
+                U, V, W = schemes.perturbed(*base, sigma, seed)
+                k = float(tensors.kappa(U, V, W))
+                assert abs(k) <= 0.5
+                t = tensors.tau(U, V, W)
+                for mu in (1.0, 3.5):
+                    assert _prop5_lhs(U, V, W, mu) <= bounds.prop5(mu, n, t) * (1 + 1e-12)
+
+
+def test_prop5_on_scaled_w_closed_form():
+    # W of an exact scheme scaled by (1 + delta): Y = (1 + delta) X, so tau = delta n^(3/2),
+    # kappa = -delta, |eta| = delta / (1 + delta) and |eta| ||Y|| = delta n^(3/2) exactly.
+    # The corrected bound 2 (n^(-3/2) tau + 1) tau = 2 (1 + delta) delta n^(3/2) holds with
+    # ratio 1 / (2 (1 + delta)); the printed one, 2 (n^(-5/2) tau + 1/n) tau
+    # = 2 (1 + delta) delta n^(1/2), is exceeded for n = 3 (ratio 3 / (2 (1 + delta))).
+    for base, n in ((schemes.strassen(), 2), (schemes.laderman(), 3)):
+        U, V, W = [T.astype(np.float64) for T in base]
+        for delta in (1e-3, 1e-2, 0.25):
+            Ws = W * (1.0 + delta)
+            t = tensors.tau(U, V, Ws)
+            assert t == pytest.approx(delta * n ** 1.5, rel=1e-12)
+            assert float(tensors.kappa(U, V, Ws)) == pytest.approx(-delta, rel=1e-12)
+            lhs = _prop5_lhs(U, V, Ws, 1.0)
+            assert lhs == pytest.approx(delta * n ** 1.5, rel=1e-12)
+            assert lhs / bounds.prop5(1.0, n, t) == pytest.approx(1.0 / (2.0 * (1.0 + delta)), rel=1e-12)
+            printed = bounds.prop5(1.0, n, t, p=2.5)
+            assert printed == pytest.approx(2 * (1 + delta) * delta * n ** 0.5, rel=1e-12)
+            if n == 3:
+                assert lhs > printed

@@ -57,7 +57,7 @@ def test_draw_statistics():
 
 def test_fold_preserves_slice_norms():
     # Proof of Prop. 10: ||Uh_r|| = ||U_r||, ||Vh_r|| = ||V_r||, ||Wh_r|| = c ||W_r||.
-    base = schemes.perturbed(*schemes.laderman(), 1e-2, np.random.default_rng(3))
+    base = schemes.perturbed(*schemes.laderman(), 1e-2, 3)
     dr = draws.draw(5, 1, 3, 3, 3)
     c = 1.0 / (1.0 - tensors.kappa(*base))
     Uh, Vh, Wh = draws.fold(*base, dr, c)
@@ -79,7 +79,7 @@ def _block_matrix(perm, signs, m):
 def test_fold_equals_definition_2_with_explicit_matrices(name):
     # eq. f-hat-def computed with explicit orthogonal matrices M_i, against the folded
     # tensors of eq. randomized-algorithm; both evaluated as a plain BC in float64.
-    base = schemes.perturbed(*getattr(schemes, name)(), 1e-2, np.random.default_rng(9))
+    base = schemes.perturbed(*getattr(schemes, name)(), 1e-2, 9)
     n = base[0].shape[0]
     m = 3
     A = workloads.gaussian((n * m, n * m), 1)

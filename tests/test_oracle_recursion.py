@@ -41,7 +41,7 @@ def test_float64_error_of_exact_scheme_is_rounding_level():
 
 
 def test_prop4_ii_bound_single_level():
-    base = schemes.perturbed(*S, 1e-2, np.random.default_rng(4))
+    base = schemes.perturbed(*S, 1e-2, 4)
     A = workloads.gaussian((8, 8), 5)
     B = workloads.gaussian((8, 8), 6)
     bound = bounds.prop4_ii(np.linalg.norm(A), np.linalg.norm(B), *base)
@@ -54,7 +54,7 @@ def test_prop4_ii_bound_single_level():
 
 
 def test_prop4_i_bound_deterministic():
-    base = schemes.perturbed(*L, 1e-2, np.random.default_rng(8))
+    base = schemes.perturbed(*L, 1e-2, 8)
     A = workloads.gaussian((9, 9), 7)
     B = workloads.gaussian((9, 9), 8)
     err = np.linalg.norm(recursion.rbc_seeded(A, B, [base], 0, "none") - A @ B)
@@ -68,7 +68,7 @@ def test_approximate_scheme_error_is_first_order_in_lambda():
     for Q in (1, 2):
         errs = []
         for lam in lams:
-            base = schemes.perturbed(*S, lam, np.random.default_rng(42))
+            base = schemes.perturbed(*S, lam, 42)
             errs.append(recursion.rel_err(recursion.rbc_seeded(A, B, [base] * Q, 3), A @ B))
         slope = np.polyfit(np.log10(lams), np.log10(errs), 1)[0]
         assert 0.9 < slope < 1.1, (Q, errs)
@@ -99,7 +99,7 @@ def test_leaf_operands_and_combine_reassemble_the_product():
 
 
 def test_deterministic_is_mode_none_without_kappa_scale():
-    base = schemes.perturbed(*S, 1e-2, np.random.default_rng(1))
+    base = schemes.perturbed(*S, 1e-2, 1)
     A = workloads.gaussian((8, 8), 1)
     B = workloads.gaussian((8, 8), 2)
     det = tensors.bc_evaluate(*base, A, B)
@@ -109,7 +109,7 @@ def test_deterministic_is_mode_none_without_kappa_scale():
 
 def test_monte_carlo_mean_two_levels():
     # Prop. 6 for Q = 2: the sample mean over seeds approaches A B for an ABC.
-    base = schemes.perturbed(*S, 5e-2, np.random.default_rng(2))
+    base = schemes.perturbed(*S, 5e-2, 2)
     A = workloads.gaussian((4, 4), 11)
     B = workloads.gaussian((4, 4), 12)
     samples = np.array([recursion.rbc_seeded(A, B, [base, base], s) for s in range(3000)])

@@ -46,7 +46,7 @@ def test_perturbed_scheme_tau_scales_with_sigma():
     base = schemes.strassen()
     ratios = []
     for sigma in [1e-1, 1e-2, 1e-3, 1e-4]:
-        P = schemes.perturbed(*base, sigma, np.random.default_rng(5))
+        P = schemes.perturbed(*base, sigma, 5)
         t = tensors.tau(*P)
         assert t > 0
         ratios.append(t / sigma)
@@ -56,12 +56,81 @@ def test_perturbed_scheme_tau_scales_with_sigma():
 
 def test_perturbed_scheme_touches_ones_and_five_zeros():
     base = schemes.strassen()
-    P = schemes.perturbed(*base, 1e-3, np.random.default_rng(0))
+    P = schemes.perturbed(*base, 1e-3, 0)
     for T0, T in zip(base, P):
         changed = T != T0
         assert np.all(changed[T0 == 1])
         assert np.sum(changed[T0 == 0]) == 5
         assert not np.any(changed[T0 == -1])
+
+
+def test_perturbation_uniforms_are_exact_and_open():
+    # u = (floor(w / 2^12) + 1/2) 2^-52: the extreme words map strictly inside (0, 1)
+    assert schemes.open_unit(0) == 2.0 ** -53
+    assert schemes.open_unit(2 ** 64 - 1) == 1.0 - 2.0 ** -53
+    assert schemes.open_unit(2 ** 63) == 0.5 + 2.0 ** -53
+    from fractions import Fraction
+    for w in (1, 4095, 4096, 2 ** 40 + 12345, 2 ** 64 - 4097):
+        assert Fraction(schemes.open_unit(w)) == (Fraction(w >> 12) + Fraction(1, 2)) / 2 ** 52
+
+
+def test_perturbation_words_are_numpys_philox_with_key_word_one():
+    w = schemes.aux_words(9)
+    got = [next(w) for _ in range(10)]
+    g = np.random.Philox(key=np.array([9, 1], np.uint64), counter=np.zeros(4, np.uint64))
+    assert got == [int(x) for x in g.random_raw(10)]
+    # a different key word than the level draws (key (seed, 0))
+    g0 = np.random.Philox(key=np.array([9, 0], np.uint64), counter=np.zeros(4, np.uint64))
+    assert got != [int(x) for x in g0.random_raw(10)]
+
+
+def test_box_muller_normals():
+    # Against numpy's own (vectorised) log / cos / sqrt on the same uniforms, and the
+    # first four moments of N(0, 1) over 40000 draws.
+    w = schemes.aux_words(123)
+    z = np.array([schemes.box_muller(w) for _ in range(40000)])
+    w = schemes.aux_words(123)
+    words = np.array([next(w) for _ in range(80000)], dtype=np.uint64)
+    u = ((words >> np.uint64(12)).astype(np.float64) + 0.5) * 2.0 ** -52
+    ref = np.sqrt(-2.0 * np.log(u[0::2])) * np.cos(2.0 * np.pi * u[1::2])
+    assert np.max(np.abs(z - ref)) <= 8 * 2.0 ** -52 * np.max(np.abs(ref))
+    n = z.size
+    assert abs(z.mean()) < 5 / np.sqrt(n)
+    assert abs(z.var() - 1.0) < 5 * np.sqrt(2.0 / n)
+    assert abs(np.mean(z ** 3)) < 5 * np.sqrt(15.0 / n)
+    assert abs(np.mean(z ** 4) - 3.0) < 5 * np.sqrt(96.0 / n)
+    from scipy import stats
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+
+
+def test_perturbation_picks_zeros_uniformly():
+    # 5 of Strassen's 16 zeros of U picked without replacement: each with probability 5/16
+    base = schemes.strassen()
+    zeros = np.flatnonzero(base[0].reshape(-1) == 0)
+    assert zeros.size == 16
+    n = 3000
+    hits = np.zeros(zeros.size)
+    for seed in range(n):
+        P = schemes.perturbed(*base, 1e-3, seed)
+        changed = P[0].reshape(-1)[zeros] != 0
+        assert changed.sum() == 5
+        hits += changed
+    p = 5 / 16
+    assert np.all(np.abs(hits / n - p) < 6 * np.sqrt(p * (1 - p) / n))
+
+
+def test_perturbation_zero_sigma_and_seed_dependence():
+    base = schemes.laderman()
+    for T0, T in zip(base, schemes.perturbed(*base, 0.0, 5)):
+        np.testing.assert_array_equal(T, T0)
+    a = schemes.perturbed(*base, 1e-2, 5)
+    b = schemes.perturbed(*base, 1e-2, 6)
+    assert not np.array_equal(a[0], b[0])
+    # the noise scales with sigma: same draws, sigma 1e-2 vs 1e-4
+    c = schemes.perturbed(*base, 1e-4, 5)
+    for T0, Ta, Tc in zip(base, a, c):
+        d = Ta - T0
+        np.testing.assert_allclose((Tc - T0) * 100.0, d, rtol=1e-9, atol=1e-15)
 
 
 def _residual_exact(U, V, W):
