@@ -245,6 +245,25 @@ rbc_status rbc_matmul_draws(rbc_plan p, const void* A, int64_t lda, const void* 
                             void* C, int64_t ldc, const int32_t* signs, const int32_t* perms,
                             int kappa_scale, void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rbc_matmul with the
+ * workspace taken from a fixed device array of RBC_NOALLOC_MAX_WORKSPACE bytes
+ * inside the library, instead of a caller's buffer.  Same kernels, so C is
+ * bitwise that of rbc_matmul with the same arguments.  Nothing is allocated:
+ * every device that runs the library holds one copy of the array until the
+ * process ends.  Calls on one device share that copy: calls that overlap on
+ * one device (two streams, two host threads) race and give wrong results;
+ * serialize them (one stream).  Every call writes each workspace byte it
+ * reads, so what an earlier call left there does not matter.
+ * Errors (nothing launched): RBC_EINVAL for a plan whose workspace_bytes
+ * exceed RBC_NOALLOC_MAX_WORKSPACE, a plan whose coefficient tables are not
+ * on the current device yet (a plan's first rbc_matmul on a device uploads
+ * them, allocating once: run it once before), a plan with stage timing on,
+ * a bad mode or the argument errors of rbc_matmul. */
+#define RBC_NOALLOC_MAX_WORKSPACE ((size_t)64 << 20)
+rbc_status rbc_matmul_noalloc(rbc_plan p, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                              int64_t ldc, uint64_t seed, rbc_mode mode, int kappa_scale, void* stream);
+
 /* ---- averages of several products (Section 3, error of average) -----------
  * Cavg = (1/K) sum_k F-hat_k(A, B), F-hat_k with the draws of (seeds[k], mode),
  * accumulated elementwise in f64 in the order k = 0, 1, ..., K-1 (Cavg: device,

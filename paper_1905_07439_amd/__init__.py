@@ -207,6 +207,23 @@ class Plan:
                                ws.numel(), st))
         return C
 
+    def matmul_noalloc(self, A, B, C, seed=0, mode="full", kappa_scale=None, stream=None):
+        """As matmul, into a given C, with the workspace in the library's fixed device array
+        (rbc_matmul_noalloc): the call allocates nothing.  The plan must have run once
+        through matmul on this device."""
+        import torch
+        if kappa_scale is None:
+            kappa_scale = mode != "none"
+        M, K, N = self.info["M"], self.info["K"], self.info["N"]
+        for name, X, shape in (("A", A, (M, K)), ("B", B, (K, N)), ("C", C, (M, N))):
+            if tuple(X.shape) != shape or X.dtype != self.dtype or not X.is_cuda or X.stride(1) != 1:
+                raise ValueError("%s must be a row-major %s CUDA tensor of shape %s" % (name, self.dtype, shape))
+        st = stream if stream is not None else torch.cuda.current_stream(A.device)
+        check(lib().rbc_matmul_noalloc(self._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                                       seed & 0xFFFFFFFFFFFFFFFF, MODES[mode], int(bool(kappa_scale)),
+                                       ctypes.c_void_p(st.cuda_stream)))
+        return C
+
     def matmul_draws(self, A, B, signs, perms, C=None, kappa_scale=True, workspace=None, stream=None):
         C, ws, st = self._common(A, B, C, workspace, stream)
         s, sp = _i32(signs)

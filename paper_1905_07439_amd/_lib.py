@@ -78,6 +78,8 @@ SIGNATURES = {
     "rbc_plan_destroy": (None, [c_vp]),
     "rbc_matmul": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, ctypes.c_uint64,
                                   ctypes.c_int, ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]),
+    "rbc_matmul_noalloc": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, ctypes.c_uint64,
+                                          ctypes.c_int, ctypes.c_int, c_vp]),
     "rbc_matmul_draws": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, c_i32_p, c_i32_p,
                                         ctypes.c_int, c_vp, ctypes.c_size_t, c_vp]),
     "rbc_average_workspace": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),

@@ -305,9 +305,11 @@ rbc_status record(Plan& p, hipStream_t s, int slot) {
   return RBC_OK;
 }
 
-rbc_status matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                       int64_t ldc, const int32_t* signs, const int32_t* perms, int kappa_scale,
-                       void* ws, size_t ws_bytes, void* stream) {
+}  // namespace
+
+rbc_status rbc::matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                            int64_t ldc, const int32_t* signs, const int32_t* perms, int kappa_scale,
+                            void* ws, size_t ws_bytes, void* stream) {
   if (!A || !B || !C) return fail(RBC_EINVAL, "null matrix pointer");
   if (lda < p.K || ldb < p.N || ldc < p.N) return fail(RBC_EINVAL, "leading dimension too small");
   rbc_status st = check_ws(p, ws, ws_bytes);
@@ -333,8 +335,6 @@ rbc_status matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, int64
   if (p.timing) ++p.recorded;
   return RBC_OK;
 }
-
-}  // namespace
 
 extern "C" {
 

@@ -22,6 +22,11 @@ void seeded_draws(const Plan& p, uint64_t seed, rbc_mode mode, std::vector<int32
 rbc_status check_ws(const Plan& p, void* ws, size_t bytes);
 // Upload the coefficient tables of every level on first use on a device.
 rbc_status ensure_device(Plan& p);
+// One product with the plan's draws given (validated, per level), the workspace
+// supplied by the caller: the body of rbc_matmul and rbc_matmul_draws.
+rbc_status matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                       int64_t ldc, const int32_t* signs, const int32_t* perms, int kappa_scale,
+                       void* ws, size_t ws_bytes, void* stream);
 
 struct ScaleLaunch {  // f16s, fp8c: partial maxima of |X| (launch), per-leaf exponent inputs
   const float* X;
