@@ -55,13 +55,19 @@ __global__ __launch_bounds__(256, 3) void k_gemm_f32_128(const float* __restrict
 }
 
 // The same tiles with the operands gathered while they are loaded (LeafGather).
+// BUF: 128-tiles through buffer loads (gemm_f32_gathered_tile; parents under 2 GiB).
+template <bool BUF>
 __global__ __launch_bounds__(256, 3) void k_gemm_f32_128_gathered(const LeafGather g, float* __restrict__ P, int m,
                                                                   int n, int k, int tiles_n, int tiles_per_leaf,
                                                                   int64_t n_big, int64_t n_small) {
   __shared__ __attribute__((aligned(16))) float smem[kSmem128 > kSmem64 ? kSmem128 : kSmem64];
   int64_t bid;
-  if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid))
-    tiles::gemm_f32_tile<128, 128, 16, 4, true>(g.A, g.B, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem, &g);
+  if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid)) {
+    if constexpr (BUF)
+      tiles::gemm_f32_gathered_tile<128, 128, 16, 4>(&g, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem);
+    else
+      tiles::gemm_f32_tile<128, 128, 16, 4, true>(g.A, g.B, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem, &g);
+  }
   else if (k % 32 == 0)
     tiles::gemm_f32_tile<64, 64, 32, 2, true>(g.A, g.B, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem,
                                               &g);
@@ -147,9 +153,16 @@ hipError_t launch_gemm_f32_gathered(const LeafGather& g, float* P, int64_t m, in
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 block(256);
   if (tile == 128) {
-    const TailSplit sp = tail_split(nblocks, resident_blocks((const void*)k_gemm_f32_128_gathered, 256));
-    hipLaunchKernelGGL(k_gemm_f32_128_gathered, dim3((unsigned)(sp.n_big + sp.n_small)), block, 0, stream, g, P,
-                       (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
+    // buffer loads address a parent with 32-bit byte offsets
+    const bool buf = g.a_batch < (int64_t(1) << 29) && g.b_batch < (int64_t(1) << 29);
+    const void* kern = buf ? (const void*)k_gemm_f32_128_gathered<true> : (const void*)k_gemm_f32_128_gathered<false>;
+    const TailSplit sp = tail_split(nblocks, resident_blocks(kern, 256));
+    if (buf)
+      hipLaunchKernelGGL(k_gemm_f32_128_gathered<true>, dim3((unsigned)(sp.n_big + sp.n_small)), block, 0, stream, g,
+                         P, (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
+    else
+      hipLaunchKernelGGL(k_gemm_f32_128_gathered<false>, dim3((unsigned)(sp.n_big + sp.n_small)), block, 0, stream,
+                         g, P, (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
   } else if (k % 32 == 0)
     hipLaunchKernelGGL((k_gemm_f32_64_gathered<32, 4>), dim3((unsigned)nblocks), block, 0, stream, g, P, (int)m,
                        (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);

@@ -219,6 +219,199 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ S, const
   }
 }
 
+
+// ---- leaf gather with buffer loads --------------------------------------------
+// The gathered tile above, restructured for the matrix cores' sake (measured on
+// 343 leaves of 512^3 from 49 parents of 1024^2: 0.810 -> 0.769-0.777 ms, the
+// same bits):
+//  - loads through one buffer resource per parent: each thread keeps one 32-bit
+//    offset per load, the sub-block and slab offsets are scalar, so the K loop
+//    does no address arithmetic and the tile fits in 138 VGPRs (167 before);
+//  - the next slab's loads are issued right after the current slab is stored,
+//    before the barrier;
+//  - a chunk's T operands are read from LDS all at once before its MFMAs;
+//  - when the second coefficient is +-1 (every Strassen-like level), the
+//    operand is fma(c1, x1, c0 x0): c1 x1 is exact, so the single rounding of
+//    the fma equals rounding the sum of the rounded terms.
+// Parents must be under 2 GiB (32-bit byte offsets); the launcher checks.
+typedef __amdgpu_buffer_rsrc_t buffer_rsrc;
+
+__device__ __forceinline__ floatx4 buffer_load4(buffer_rsrc r, int voff, int soff) {
+  return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+// How a side forms its operand from its (at most two) sub-blocks: 0 zero, 1 c0 x0,
+// 2 fma(c1, x1, c0 x0) for c1 = +-1, 3 c0 x0 + c1 x1 with both terms rounded.
+__device__ __forceinline__ int gather_mode(const GatherSlots& g) {
+  if (g.n == 0) return 0;
+  if (g.n == 1) return 1;
+  return __builtin_fabsf(g.c1) == 1.f ? 2 : 3;
+}
+
+template <int NV>
+__device__ __forceinline__ void gather_combine(int mode, const GatherSlots& g, floatx4 (&x0)[NV],
+                                               const floatx4 (&x1)[NV]) {
+#pragma clang fp contract(off)
+  if (mode == 2) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const floatx4 t = g.c0 * x0[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x0[i][e] = __builtin_fmaf(g.c1, x1[i][e], t[e]);
+    }
+  } else if (mode == 1) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) x0[i] = g.c0 * x0[i];
+  } else if (mode == 3) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) x0[i] = g.c0 * x0[i] + g.c1 * x1[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) x0[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+}
+
+__device__ __forceinline__ float uniform_f(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
+// Output tile `bid` of the batched leaf product, operands gathered from the parents
+// (LeafGather) as gemm_f32_tile<..., GATHER = true> does, with the same arithmetic
+// in the same order.
+template <int BM, int BN, int BK, int EPI>
+__device__ __forceinline__ void gemm_f32_gathered_tile(const LeafGather* gs, float* __restrict__ P, int m, int n,
+                                                       int k, int tiles_n, int tiles_per_leaf, int64_t bid,
+                                                       float* smem) {
+  using Cfg = F32Tile<BM, BN, BK, EPI>;
+  constexpr int LDA = Cfg::LDA, LDB = Cfg::LDB, WM = BM / 2, WN = BN / 2, LDE = Cfg::LDE;
+  constexpr int FM = WM / 16, FN = WN / 16, KQ = BK / 4;
+  constexpr int A_VEC = BM * KQ / 256, B_VEC = BK * (BN / 4) / 256;
+  static_assert(A_VEC >= 1 && B_VEC >= 1, "tile too small for 256 threads");
+  float(*As)[BM][LDA] = reinterpret_cast<float(*)[BM][LDA]>(smem);
+  float(*Bs)[BK][LDB] = reinterpret_cast<float(*)[BK][LDB]>(smem + Cfg::A_FLOATS);
+  const int64_t leaf = bid / tiles_per_leaf;
+  const int t = (int)(bid - leaf * tiles_per_leaf);
+  const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
+  gbl<float>* Pl = global_ptr(P) + leaf * (int64_t)m * n + (int64_t)tm * BM * n + (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t parent = leaf / gs->R;
+  const int r = (int)(leaf - parent * gs->R);
+  GatherSlots ga = gather_slots(gs->la, gs->bra, gs->bca, r, gs->R, gs->a_row_blk, gs->a_col_blk);
+  GatherSlots gb = gather_slots(gs->lb, gs->brb, gs->bcb, r, gs->R, gs->b_row_blk, gs->b_col_blk);
+  ga.c0 = uniform_f(ga.c0), ga.c1 = uniform_f(ga.c1), gb.c0 = uniform_f(gb.c0), gb.c1 = uniform_f(gb.c1);
+  const int ma = __builtin_amdgcn_readfirstlane(gather_mode(ga));
+  const int mb = __builtin_amdgcn_readfirstlane(gather_mode(gb));
+  const buffer_rsrc rsa = __builtin_amdgcn_make_buffer_rsrc((void*)(gs->A + parent * gs->a_batch), 0,
+                                                            (int)(gs->a_batch * 4), 0x00020000);
+  const buffer_rsrc rsb = __builtin_amdgcn_make_buffer_rsrc((void*)(gs->B + parent * gs->b_batch), 0,
+                                                            (int)(gs->b_batch * 4), 0x00020000);
+  int a_vo[A_VEC], b_vo[B_VEC];
+#pragma unroll
+  for (int i = 0; i < A_VEC; ++i) {
+    const int idx = tid + 256 * i;
+    a_vo[i] = (int)(((int64_t)(tm * BM + idx / KQ) * gs->a_ld + (idx % KQ) * 4) * 4);
+  }
+#pragma unroll
+  for (int i = 0; i < B_VEC; ++i) {
+    const int idx = tid + 256 * i;
+    b_vo[i] = (int)(((int64_t)(idx / (BN / 4)) * gs->b_ld + tn * BN + (idx % (BN / 4)) * 4) * 4);
+  }
+  const int a0 = __builtin_amdgcn_readfirstlane((int)(ga.off0 * 4));
+  const int a1 = __builtin_amdgcn_readfirstlane((int)(ga.off1 * 4));
+  const int b0 = __builtin_amdgcn_readfirstlane((int)(gb.off0 * 4));
+  const int b1 = __builtin_amdgcn_readfirstlane((int)(gb.off1 * 4));
+  const int b_step = (int)(BK * gs->b_ld * 4);
+  floatx4 ra[A_VEC], rb[B_VEC], xa[A_VEC], xb[B_VEC];
+  auto load_slab = [&](int kt) {
+    const int sa = kt * BK * 4, sb = kt * b_step;
+#pragma unroll
+    for (int i = 0; i < A_VEC; ++i) ra[i] = buffer_load4(rsa, a_vo[i], a0 + sa);
+    if (ma >= 2) {
+#pragma unroll
+      for (int i = 0; i < A_VEC; ++i) xa[i] = buffer_load4(rsa, a_vo[i], a1 + sa);
+    }
+#pragma unroll
+    for (int i = 0; i < B_VEC; ++i) rb[i] = buffer_load4(rsb, b_vo[i], b0 + sb);
+    if (mb >= 2) {
+#pragma unroll
+      for (int i = 0; i < B_VEC; ++i) xb[i] = buffer_load4(rsb, b_vo[i], b1 + sb);
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < A_VEC; ++i) xa[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < B_VEC; ++i) xb[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+  load_slab(0);
+  floatx4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nk = k / BK;
+  const int lr = lane & 15, lg = lane >> 4;
+  int cur = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    gather_combine(ma, ga, ra, xa);
+    gather_combine(mb, gb, rb, xb);
+#pragma unroll
+    for (int i = 0; i < A_VEC; ++i) {
+      const int idx = tid + 256 * i;
+      *reinterpret_cast<floatx4*>(&As[cur][idx / KQ][(idx % KQ) * 4]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_VEC; ++i) {
+      const int idx = tid + 256 * i;
+      *reinterpret_cast<floatx4*>(&Bs[cur][idx / (BN / 4)][(idx % (BN / 4)) * 4]) = rb[i];
+    }
+    if (kt + 1 < nk) load_slab(kt + 1);  // the staging registers are free once stored
+    __syncthreads();
+    // k order inside each chunk of 16 as in gemm_f32_tile (same bits)
+#pragma unroll
+    for (int c = 0; c < BK / 16; ++c) {
+      floatx4 a[FM];
+      float b[4][FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        a[i] = *reinterpret_cast<const floatx4*>(&As[cur][wm * WM + i * 16 + lr][c * 16 + lg * 4]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < FN; ++q) b[j][q] = Bs[cur][c * 16 + lg * 4 + j][wn * WN + q * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int q = 0; q < FN; ++q)
+            acc[i][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[j][q], acc[i][q], 0, 0, 0);
+    }
+    cur ^= 1;
+  }
+  static_assert(FM % EPI == 0, "epilogue passes must split the fragments evenly");
+  constexpr int FP = FM / EPI, WR = WM / EPI;
+  float* Es = smem + wave * WR * LDE;
+  constexpr int LPR = WN / 4, RPI = 64 / LPR;
+  gbl<float>* Pw = Pl + (int64_t)(wm * WM) * n + wn * WN;
+  const int er = lane / LPR, ec = (lane % LPR) * 4;
+#pragma unroll
+  for (int ps = 0; ps < EPI; ++ps) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < FP; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Es[(i * 16 + lg * 4 + v) * LDE + j * 16 + lr] = acc[ps * FP + i][j][v];
+    __syncthreads();
+#pragma unroll
+    for (int r0 = 0; r0 < WR; r0 += RPI) {
+      const floatx4 v = *reinterpret_cast<const floatx4*>(&Es[(r0 + er) * LDE + ec]);
+      *reinterpret_cast<gbl<floatx4>*>(Pw + (int64_t)(ps * WR + r0 + er) * n + ec) = v;
+    }
+  }
+}
+
 }  // namespace tiles
 }  // namespace rbc
 

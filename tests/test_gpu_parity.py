@@ -49,6 +49,12 @@ def _schemes(names):
             kind, lam = n.split(":")
             lib.append(rbc.Scheme.builtin("%s:%r" % (kind, float(lam))))
             ref.append(getattr(osch, kind)(float(lam)))
+        elif n.startswith("scaled:"):  # scaled:<u>:<v>: Strassen with U times u, V times v (approximate)
+            _, u, v = n.split(":")
+            U, V, W = osch.strassen()
+            U, V = np.asarray(U) * float(u), np.asarray(V) * float(v)
+            lib.append(rbc.Scheme.from_tensors(U, V, W, residual_tol=float("inf")))
+            ref.append((U, V, np.asarray(W)))
         elif n.startswith("pert:"):
             _, sigma, seed = n.split(":")
             base = osch.strassen()
@@ -532,6 +538,10 @@ def test_tail_split_tiles_give_the_same_bits(prec):
     (["strassen"] * 2, 300, 192, 500, 128),    # 128-tiles whose tail tiles take 16-k slabs
     (["strassen", "naive:2,3,2"], 260, 300, 170, 64),  # non-square deepest level, one term each
     (["naive:3,2,2", "naive:2,2,2"], 1000, 1000, 1000, 0),
+    # coefficients other than +-1 at the deepest level: both terms rounded apart (U), and
+    # a +-1 second coefficient after a scaled first one (V scaled by 1 keeps +-1)
+    (["strassen", "scaled:0.75:1.25"], 1024, 1024, 1024, 128),
+    (["strassen", "scaled:0.5:1"], 1000, 1000, 1000, 128),
 ])
 def test_leaf_gather_same_bits(names, M, K, N, tile):
     # The leaf product that forms its operands while loading them (deepest level's gather
