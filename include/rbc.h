@@ -187,7 +187,12 @@ rbc_status rbc_fold(rbc_scheme s, const int32_t* signs, const int32_t* perms, in
  * prod b1, prod b2, prod b3, rounded up to the leaf GEMM tile; A and B are
  * zero padded virtually (never copied).  leaf_tile = 0 picks the tile
  * automatically; otherwise it is the square tile edge (f32, bf16x3: 64 or
- * 128; f16s, fp8c: 32, 64, 96 or 128; f64: 16).  levels may be 0 (plain product by the leaf kernel). */
+ * 128; f16s, fp8c: 32, 64, 96 or 128; f64: 16).  levels may be 0 (plain product by the leaf kernel).
+ * leaf_tile = -1 (f32 and f64 only; RBC_EUNSUPPORTED otherwise) asks for exact blocks: the
+ * padding is only to a multiple of prod b1, prod b2, prod b3, so the recursion splits
+ * the matrices exactly as the unpadded problem (an N = 320 product with five Strassen
+ * levels has leaves of 10 x 10), and the leaves, of any size, run on a kernel that
+ * masks the edges of its 16 x 16 tiles (small leaves; no leaf gather). */
 rbc_status rbc_plan_create(int64_t M, int64_t K, int64_t N, int levels, const rbc_scheme* schemes,
                            rbc_prec prec, int leaf_tile, rbc_plan* out);
 rbc_status rbc_plan_get_info(rbc_plan p, rbc_plan_info* info);

@@ -92,6 +92,10 @@ struct Plan {
   int Q = 0;
   rbc_prec prec = RBC_PREC_F32;
   int tile_m = 0, tile_n = 0, tile_k = 0;
+  // Exact blocks (leaf_tile = -1): the recursion's blocks are those of the
+  // unpadded problem (padding only to a multiple of the block counts), and the
+  // leaves, of any size, run through the masked leaf kernels.
+  bool exact_blocks = false;
   std::vector<Scheme> levels;
   std::vector<LevelTables> tables;
   std::vector<Group> groups;

@@ -119,7 +119,68 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ S,
   for (int v = 0; v < 4; ++v) Pl[(int64_t)((lane >> 4) + 4 * v) * n + (lane & 15)] = acc[v];
 }
 
+// Leaves of any size (plans with exact blocks, where the recursion's blocks are
+// not padded to the tile): one wavefront per 16 x 16 output tile, operands read
+// straight from global memory, reads outside the leaf return zero and writes
+// outside it are dropped.  Small leaves only (latency bound).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_masked(const T* __restrict__ S, const T* __restrict__ Tm,
+                                                     T* __restrict__ P, int m, int n, int k, int tiles_n,
+                                                     int tiles_per_leaf, int64_t ntiles) {
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;  // whole wavefront
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int64_t leaf = tile / tiles_per_leaf;
+  const int t = (int)(tile - leaf * tiles_per_leaf);
+  const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
+  const int row = tm * 16 + lr, col = tn * 16 + lr;
+  const T* Sl = S + leaf * (int64_t)m * k + (int64_t)row * k;
+  const T* Tl = Tm + leaf * (int64_t)k * n + col;
+  typedef T Tx4 __attribute__((ext_vector_type(4)));
+  Tx4 acc = {T(0), T(0), T(0), T(0)};
+  for (int k0 = 0; k0 < k; k0 += 4) {
+    const int kk = k0 + lg;  // lane group lg carries k = k0 + lg
+    const T a = (row < m && kk < k) ? Sl[kk] : T(0);
+    const T b = (col < n && kk < k) ? Tl[(int64_t)kk * n] : T(0);
+    if constexpr (sizeof(T) == 8)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    else
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  // D layout: lane holds column lane & 15; rows lg + 4 v (f64), 4 lg + v (f32)
+  T* Pl = P + leaf * (int64_t)m * n;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = tm * 16 + (sizeof(T) == 8 ? lg + 4 * v : 4 * lg + v);
+    if (r < m && col < n) Pl[(int64_t)r * n + col] = acc[v];
+  }
+}
+
 }  // namespace
+
+template <typename T>
+static hipError_t launch_masked(const T* S, const T* Tm, T* P, int64_t m, int64_t n, int64_t k, int64_t batch,
+                                hipStream_t stream) {
+  if (batch == 0 || m == 0 || n == 0) return hipSuccess;
+  if (m > (1 << 30) || n > (1 << 30) || k > (1 << 30)) return hipErrorInvalidValue;
+  const int tiles_n = (int)((n + 15) / 16), tiles_per_leaf = (int)(((m + 15) / 16) * tiles_n);
+  const int64_t ntiles = batch * tiles_per_leaf;
+  const int64_t nblocks = (ntiles + 3) / 4;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gemm_masked<T>, dim3((unsigned)nblocks), dim3(256), 0, stream, S, Tm, P, (int)m, (int)n,
+                     (int)k, tiles_n, tiles_per_leaf, ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32_masked(const float* S, const float* T, float* P, int64_t m, int64_t n, int64_t k,
+                                  int64_t batch, hipStream_t stream) {
+  return launch_masked<float>(S, T, P, m, n, k, batch, stream);
+}
+
+hipError_t launch_gemm_f64_masked(const double* S, const double* T, double* P, int64_t m, int64_t n, int64_t k,
+                                  int64_t batch, hipStream_t stream) {
+  return launch_masked<double>(S, T, P, m, n, k, batch, stream);
+}
 
 hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, int64_t n, int64_t k,
                            int64_t batch, int tile, hipStream_t stream) {

@@ -97,6 +97,11 @@ hipError_t launch_gemm_f32_gathered(const LeafGather& g, float* P, int64_t m, in
                                     int64_t batch, int tile, hipStream_t stream);
 hipError_t launch_gemm_f64(const double* S, const double* T, double* P, int64_t m, int64_t n,
                            int64_t k, int64_t batch, hipStream_t stream);
+// Leaves of any size m x k by k x n (no tile padding), f32 or f64 (exact-block plans).
+hipError_t launch_gemm_f32_masked(const float* S, const float* T, float* P, int64_t m, int64_t n, int64_t k,
+                                  int64_t batch, hipStream_t stream);
+hipError_t launch_gemm_f64_masked(const double* S, const double* T, double* P, int64_t m, int64_t n, int64_t k,
+                                  int64_t batch, hipStream_t stream);
 // bf16x3: S and T hold hi planes followed (plane elements later) by lo planes.
 hipError_t launch_gemm_bf16x3(const uint16_t* S, const uint16_t* T, float* P, int64_t m, int64_t n,
                               int64_t k, int64_t batch, int tile, hipStream_t stream);

@@ -233,6 +233,7 @@ LeafLaunch build_leaf(const Plan& p, char* ws) {
   L.prec = p.prec;
   L.S = ws + p.off_S, L.T = ws + p.off_T, L.P = ws + p.off_P;
   L.m = p.mM, L.n = p.mN, L.k = p.mK, L.batch = p.n_leaves, L.tile = p.tile_m;
+  L.masked = p.exact_blocks;
   L.eS = L.eT = nullptr;
   if (p.prec == RBC_PREC_F16S || p.prec == RBC_PREC_FP8C) {
     L.eS = reinterpret_cast<const int32_t*>(ws + p.off_aux + kAuxExpOffset);
@@ -320,6 +321,15 @@ hipError_t launch(const GatherLaunch& a, const GatherLaunch& b, hipStream_t s) {
 }
 
 hipError_t launch(const LeafLaunch& l, hipStream_t s) {
+  if (l.masked) {
+    if (l.prec == RBC_PREC_F64)
+      return launch_gemm_f64_masked(static_cast<const double*>(l.S), static_cast<const double*>(l.T),
+                                    static_cast<double*>(l.P), l.m, l.n, l.k, l.batch, s);
+    if (l.prec == RBC_PREC_F32)
+      return launch_gemm_f32_masked(static_cast<const float*>(l.S), static_cast<const float*>(l.T),
+                                    static_cast<float*>(l.P), l.m, l.n, l.k, l.batch, s);
+    return hipErrorInvalidValue;
+  }
   switch (l.prec) {
     case RBC_PREC_F64:
       return launch_gemm_f64(static_cast<const double*>(l.S), static_cast<const double*>(l.T),

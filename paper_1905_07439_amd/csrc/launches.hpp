@@ -52,6 +52,7 @@ struct LeafLaunch {
   void* P;
   int64_t m, n, k, batch;
   int tile;
+  bool masked;  // leaves of any size (exact-block plans)
   const int32_t* eS;
   const int32_t* eT;
 };

@@ -184,7 +184,12 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   const int64_t lm = ceil_div(M, P1), lk = ceil_div(K, P2), ln = ceil_div(N, P3);
 
   // Leaf GEMM tile.
-  if (prec == RBC_PREC_F64) {
+  if (leaf_tile == -1) {  // exact blocks: leaves of any size, masked leaf kernels
+    if (prec != RBC_PREC_F64 && prec != RBC_PREC_F32)
+      return fail(RBC_EUNSUPPORTED, "exact blocks (leaf_tile -1) for f64 and f32 only");
+    p.exact_blocks = true;
+    p.tile_m = p.tile_n = p.tile_k = 1;
+  } else if (prec == RBC_PREC_F64) {
     if (leaf_tile == 0) leaf_tile = 16;
     if (leaf_tile != 16) return fail(RBC_EUNSUPPORTED, "f64 leaf tile must be 16");
     p.tile_m = p.tile_n = 16, p.tile_k = 4;
@@ -225,7 +230,7 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   const int prod_bytes = prec == RBC_PREC_F64 ? 8 : 4;
 
   p.groups = form_groups(p, p.Q);
-  p.leaf_gather_ok = prec == RBC_PREC_F32 && p.Q >= 2 && two_terms(levels[p.Q - 1]);
+  p.leaf_gather_ok = prec == RBC_PREC_F32 && !p.exact_blocks && p.Q >= 2 && two_terms(levels[p.Q - 1]);
   if (p.leaf_gather_ok) p.fgroups = form_groups(p, p.Q - 1);
 
   // Workspace: leaf operands, products, then the group-boundary buffers.

@@ -95,18 +95,17 @@ def test_error_distribution_matches_oracle(kind):
     # the errors of the oracle's F-hat^(Q) on the same draws (trial t = algorithm seed t),
     # for Q = 1..3 and the four modes.  The errors are ~1e-3 (algorithmic); a wrong draw,
     # mode or fold would move them far more than the 1e-12 allowed.
-    n = 64
+    # n = 80 as in the paper: exact blocks, so the oracle's own (unpadded) block structure
+    n = 80
     res = study.error_distribution(kind, n=n, qs=(1, 2, 3), trials=3, scheme="pert", prec="f64")
     A, B = study.matrices(kind, n, 1)
     AB = A @ B
     for q in (1, 2, 3):
-        plan = rbc.Plan(n, n, n, [rbc.Scheme.builtin("perturbed_strassen", 1e-3, 42)] * q, prec="f64")
-        dims = (plan.info["mM"], plan.info["mK"], plan.info["mN"])
         for m in study.MODES:
             errs = res["errors"]["Q%d/%s" % (q, m)]
             assert len(errs) == (1 if m == "none" else 3)
             for t, e in enumerate(errs):
-                C = recursion.rbc_seeded(A, B, _pert_levels(q), t, m, leaf_dims=dims)
+                C = recursion.rbc_seeded(A, B, _pert_levels(q), t, m)
                 e_or = recursion.rel_err(C, AB)
                 assert e_or > 1e-6 and abs(e - e_or) <= 1e-12, (kind, q, m, t, e, e_or)
     _say("error distribution %s matches the oracle; Q3 full %s" % (kind, res["errors"]["Q3/full"]))
@@ -116,18 +115,16 @@ def test_error_distribution_matches_oracle(kind):
 def test_error_of_average_matches_oracle(mode):
     # The harness's error-of-average curve (eq. error-of-average) against the oracle's average
     # of F-hat over the same seeds 0..k-1, at each checkpoint k.
-    n, K = 64, 8
+    n, K = 80, 8
     res = study.error_of_average("adversarial1", n=n, qs=(1, 2, 3), K=K, checkpoints=(1, 2, 5, 8), scheme="pert",
                                  prec="f64", mode=mode)
     A, B = study.matrices("adversarial1", n, 1)
     AB = A @ B
     for q in (1, 2, 3):
-        plan = rbc.Plan(n, n, n, [rbc.Scheme.builtin("perturbed_strassen", 1e-3, 42)] * q, prec="f64")
-        dims = (plan.info["mM"], plan.info["mK"], plan.info["mN"])
         acc = np.zeros((n, n))
         curve = dict(res["curves"]["Q%d" % q])
         for k in range(1, K + 1):
-            acc += recursion.rbc_seeded(A, B, _pert_levels(q), k - 1, mode, leaf_dims=dims)
+            acc += recursion.rbc_seeded(A, B, _pert_levels(q), k - 1, mode)
             if k in curve:
                 e_or = recursion.rel_err(acc / k, AB)
                 assert abs(curve[k] - e_or) <= 1e-12 * max(1.0, e_or / 1e-3), (q, k, curve[k], e_or)

@@ -98,6 +98,11 @@ GATHER_CASES = [
     (["apa322:0.0625", "strassen"], 150, 100, 90, "f32", 64),
     (["apa322:0.001", "apa322:0.01"], 90, 60, 50, "f64", 16),
     (["apa322:0.015", "apa223:0.015", "apa232:0.015"], 130, 100, 120, "f32", 64),
+    # exact blocks (leaf tile -1): the unpadded problem's block structure, leaves of any size
+    (["strassen"] * 3, 80, 80, 80, "f32", -1),
+    (["strassen"] * 2, 321, 130, 99, "f32", -1),
+    (["laderman", "strassen"], 100, 90, 110, "f64", -1),
+    (["pert:1e-3:42"] * 3, 80, 80, 80, "f64", -1),
 ]
 
 
@@ -141,6 +146,37 @@ def test_gather_and_scatter_bit_exact(case, mode):
         ref = recursion.combine(list(P), M, N, K, ref_s, dr, kappa_scale=ks, arith=arith,
                                 leaf_dims=(mM, mK, mN))
         np.testing.assert_array_equal(C.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("prec,names,N", [("f32", ["strassen"] * 5, 320), ("f64", ["strassen"] * 3, 80),
+                                          ("f32", ["laderman", "strassen"], 102), ("f64", ["strassen"] * 2, 77)])
+def test_exact_blocks_end_to_end(prec, names, N):
+    # Exact-block plans split the matrices as the unpadded problem does (N = 320 with five
+    # Strassen levels: leaves of 10 x 10) -- the oracle's default padding.  Integers are exact;
+    # f64 Gaussian products match the oracle's recursion to rounding.
+    _say("exact blocks", prec, names, N)
+    lib_s, ref_s = _schemes(names)
+    plan = rbc.Plan(N, N, N, lib_s, prec=prec, leaf_tile=-1)
+    P1 = int(np.prod([osch_dims(r)[0] for r in ref_s]))
+    assert plan.info["Mp"] == -(-N // P1) * P1 and plan.info["mM"] == -(-N // P1)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    ndt = np.float64 if prec == "f64" else np.float32
+    Ai = workloads.integers((N, N), 31).astype(ndt)
+    Bi = workloads.integers((N, N), 32).astype(ndt)
+    for seed, mode in [(0, "full"), (3, "signs"), (4, "none")]:
+        C = plan.matmul(torch.from_numpy(Ai).to(DEV), torch.from_numpy(Bi).to(DEV), seed=seed, mode=mode)
+        torch.cuda.synchronize()
+        assert np.array_equal(C.cpu().numpy(), (Ai.astype(np.float64) @ Bi.astype(np.float64)).astype(ndt))
+    if prec == "f64":
+        A = workloads.gaussian((N, N), 33)
+        B = workloads.gaussian((N, N), 34)
+        C = plan.matmul(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV), seed=7).cpu().numpy()
+        ref = recursion.rbc_seeded(A, B, ref_s, 7)
+        assert recursion.rel_err(C, ref) <= 1e-13
+
+
+def osch_dims(t):
+    return oten.dims(*t)
 
 
 @pytest.mark.parametrize("names,M,K,N", [(["strassen", "strassen"], 256, 192, 320),

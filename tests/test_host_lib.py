@@ -14,6 +14,7 @@ import pytest
 import paper_1905_07439_amd as rbc
 from paper_1905_07439_amd import _lib
 from oracle import draws as odraws
+from oracle import recursion
 from oracle import schemes as oschemes
 from oracle import tensors as otensors
 
@@ -177,6 +178,25 @@ def test_plan_geometry():
     # the plain product's one group copies A in and C out: its bytes are counted
     tz = z.traffic()
     assert tz["gather_A"] == 100 * 50 * 4 + 128 * 64 * 4 and tz["scatter"] == 128 * 64 * 4 + 100 * 30 * 4
+
+
+def test_exact_block_plans():
+    # leaf tile -1: padding only to a multiple of the block counts (the oracle's default
+    # padding), leaves of any size; f32 and f64 only
+    S = rbc.Scheme.builtin("strassen")
+    L = rbc.Scheme.builtin("laderman")
+    p = rbc.Plan(320, 320, 320, [S] * 5, prec="f32", leaf_tile=-1)
+    i = p.info
+    assert (i["Mp"], i["mM"], i["mK"], i["mN"], i["tile_m"]) == (320, 10, 10, 10, 1)
+    assert p.leaf_gather == (False, False)
+    q = rbc.Plan(100, 90, 110, [L, S], prec="f64", leaf_tile=-1)
+    assert (q.info["mM"], q.info["mK"], q.info["mN"]) == (17, 15, 19)
+    assert (q.info["Mp"], q.info["Kp"], q.info["Np"]) == (102, 90, 114)
+    assert (q.info["mM"], q.info["mK"], q.info["mN"]) == tuple(
+        d // b for d, b in zip(recursion.padded_dims(100, 90, 110, [oschemes.laderman(), oschemes.strassen()]), (6, 6, 6)))
+    for prec in ("bf16x3", "f16s", "fp8c"):
+        with pytest.raises(rbc.RbcError):
+            rbc.Plan(64, 64, 64, [S], prec=prec, leaf_tile=-1)
 
 
 def test_fusion_needs_parallel_work():
