@@ -14,6 +14,7 @@ from those parent blocks while loading them.  Prints one JSON line.
     python bench.py --workload batch512       # 512 products of mixed N in one persistent launch
     python bench.py --workload serve          # Poisson request stream, fp8 leaves, p50/p99 latency
     python bench.py --workload peaks          # measured ceilings: streaming copy, MFMA loops per dtype
+    python bench.py --workload leaves         # reduced-precision leaf products at the configurations' shapes
     python bench.py --copy-calibration BYTES  # plain copy of known size (counter scale)
 """
 
@@ -558,6 +559,57 @@ def serve_stream(args):
     print(json.dumps(out), flush=True)
 
 
+def leaves(args):
+    """The reduced-precision leaf products at the configurations' shapes, one product per
+    case timed stage by stage (HIP events): f16s Strassen Q = 2 at N = 4096 (49 leaves of
+    1024^3), bf16x3 rank-10 <3,2,2> APA (lambda = 1e-3) Q = 1 at N = 3072 (10 leaves of
+    1024 x 1536 x 1536, three bf16 products each), fp8c Strassen Q = 4 at N = 4096 (2401
+    leaves of 256^3, hi/lo e4m3 with one correction pass: three fp8 products each);
+    A, B ~ N(0,1) (seeds 3001/3002), mode full.  Per case: leaf kernel time, its rate against
+    the dtype's dense MFMA peak, and the leaf stage's algorithmic HBM bytes per second."""
+    import numpy as np
+    import torch
+
+    import paper_1905_07439_amd as rbc
+    import workloads
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    S = rbc.Scheme.builtin("strassen")
+    cases = [("f16s", 4096, [S] * 2, 1, 2500.0), ("bf16x3", 3072, [rbc.Scheme.builtin("apa322", 1e-3)], 3, 2500.0),
+             ("fp8c", 4096, [S] * 4, 3, 5000.0)]
+    rows = []
+    for prec, n, levels, passes, peak in cases:
+        A = torch.from_numpy(workloads.gaussian((n, n), 3001).astype(np.float32)).to(dev)
+        B = torch.from_numpy(workloads.gaussian((n, n), 3002).astype(np.float32)).to(dev)
+        plan = rbc.Plan(n, n, n, levels, prec=prec)
+        ws = plan.workspace(dev)
+        C = torch.empty((n, n), dtype=torch.float32, device=dev)
+        for i in range(args.warmup):
+            plan.matmul(A, B, C=C, seed=i, workspace=ws)
+        plan.set_timing(True)
+        for i in range(args.steps):
+            plan.matmul(A, B, C=C, seed=i, workspace=ws)
+        torch.cuda.synchronize()
+        stage_ms, calls = plan.timing_collect()
+        plan.set_timing(False)
+        info = plan.info
+        leaf_ms = stage_ms[2] / calls
+        flops = passes * info["n_leaves"] * 2.0 * info["mM"] * info["mK"] * info["mN"]
+        leaf_bytes = plan.traffic()["leaf"]
+        rows.append({"prec": prec, "n": n, "levels": len(levels), "leaf": [info["mM"], info["mK"], info["mN"]],
+                     "n_leaves": info["n_leaves"], "tile": info["tile_m"], "leaf_ms": round(leaf_ms, 4),
+                     "leaf_tflops": round(flops / leaf_ms / 1e9, 1), "mfma_peak_tflops": peak,
+                     "mfma_frac": round(flops / leaf_ms / 1e9 / peak, 3),
+                     "leaf_algorithmic_GBs": round(leaf_bytes / leaf_ms / 1e6, 1),
+                     "hbm_floor_ms": round(leaf_bytes / HBM_PEAK_GBS / 1e6, 4),
+                     "stage_ms": [round(x / calls, 4) for x in stage_ms[:4]]})
+        del plan, ws
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "reduced-precision leaf products at the configurations' shapes", "n_gpus": 1,
+                      "steps": args.steps, "rows": rows}), flush=True)
+
+
 def copy_calibration(nbytes):
     """A plain device copy of nbytes (for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
     import torch
@@ -577,7 +629,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="strassen4096",
-                    choices=["strassen4096", "approx3072", "batch512", "serve", "small64", "peaks"])
+                    choices=["strassen4096", "approx3072", "batch512", "serve", "small64", "peaks", "leaves"])
     ap.add_argument("--small-reps", type=int, default=1000)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--batch-count", type=int, default=512)
@@ -600,6 +652,8 @@ def main():
         return small64(args)
     if args.workload == "peaks":
         return peaks(args)
+    if args.workload == "leaves":
+        return leaves(args)
 
     import numpy as np
     import torch

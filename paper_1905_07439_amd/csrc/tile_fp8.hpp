@@ -130,8 +130,7 @@ __device__ __forceinline__ void gemm_fp8c_tile16(const uint8_t* __restrict__ S, 
       const int pl = idx / (BK * (BN / 16)), rem = idx % (BK * (BN / 16));
       *reinterpret_cast<u32x4*>(&Bs[cur][pl][rem / (BN / 16)][(rem % (BN / 16)) * 16]) = rb[i];
     }
-    __syncthreads();
-    if (kt + 1 < nk) {
+    if (kt + 1 < nk) {  // the next slab's loads before the barrier (staging registers are free)
       const int k1 = (kt + 1) * BK;
 #pragma unroll
       for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i] + k1);
@@ -139,6 +138,7 @@ __device__ __forceinline__ void gemm_fp8c_tile16(const uint8_t* __restrict__ S, 
       for (int i = 0; i < B_ITER; ++i)
         rb[i] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)k1 * n);
     }
+    __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < BK / 32; ++kk) {
       u32x2 ah[FM], al[FM], bh[FN], bl[FN];
@@ -251,8 +251,7 @@ __device__ __forceinline__ void gemm_fp8c_tile32(const uint8_t* __restrict__ S, 
       const int pl = idx / (BK * (BN / 16)), rem = idx % (BK * (BN / 16));
       *reinterpret_cast<u32x4*>(&Bs[cur][pl][rem / (BN / 16)][(rem % (BN / 16)) * 16]) = rb[i];
     }
-    __syncthreads();
-    if (kt + 1 < nk) {
+    if (kt + 1 < nk) {  // the next slab's loads before the barrier (staging registers are free)
       const int k1 = (kt + 1) * BK;
 #pragma unroll
       for (int i = 0; i < A_ITER; ++i) ra[i] = *reinterpret_cast<const gbl<const u32x4>*>(a_src[i] + k1);
@@ -260,6 +259,7 @@ __device__ __forceinline__ void gemm_fp8c_tile32(const uint8_t* __restrict__ S, 
       for (int i = 0; i < B_ITER; ++i)
         rb[i] = *reinterpret_cast<const gbl<const u32x4>*>(b_src[i] + (int64_t)k1 * n);
     }
+    __syncthreads();
     i32x8 ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
