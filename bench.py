@@ -628,6 +628,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--device-warmup-ms", type=float, default=500.0,
+                    help="untimed back-to-back products before the warm-up steps (clock ramp)")
     ap.add_argument("--workload", default="strassen4096",
                     choices=["strassen4096", "approx3072", "batch512", "serve", "small64", "peaks", "leaves"])
     ap.add_argument("--small-reps", type=int, default=1000)
@@ -674,6 +676,16 @@ def main():
     ws = plan.workspace(dev)
     stream = torch.cuda.current_stream()
 
+    # Device warm-up (untimed): the GPU's clocks take up to about a second of load to reach
+    # their steady state (the same leaf product measured 0.96 ms cold and 0.80 ms warm), so the
+    # product runs back to back for --device-warmup-ms before the W warm-up steps.
+    t_dw = time.perf_counter()
+    n_dw = 0
+    while (time.perf_counter() - t_dw) * 1e3 < args.device_warmup_ms:
+        for i in range(8):
+            plan.matmul(A, B, C=C, seed=i % 16, workspace=ws)
+        n_dw += 8
+        torch.cuda.synchronize()
     for i in range(args.warmup):
         plan.matmul(A, B, C=C, seed=i % 16, workspace=ws)
     torch.cuda.synchronize()
@@ -729,6 +741,7 @@ def main():
                                "A,B ~ U[-1,1] (seeds 2001/2002), algorithm seeds 0..15, mode full",
                    "n": N, "levels": LEVELS, "scheme": "strassen", "leaf": info["mM"], "prec": "f32",
                    "leaf_gather": plan.leaf_gather[0], "parallelism": "single GPU"},
+        "device_warmup": {"ms": args.device_warmup_ms, "products": n_dw},
         "rel_err_vs_fp64": rel_err,
         "stage_ms": {"gather_A": round(stage_ms[0] / calls, 4), "gather_B": round(stage_ms[1] / calls, 4),
                      "leaf": round(leaf_ms, 4), "scatter": round(stage_ms[3] / calls, 4)},
