@@ -58,6 +58,39 @@ __global__ __launch_bounds__(256) void k_gemm_lowp_split(const uint16_t* __restr
                                       4 * tiles_per_leaf, bid, smem);
 }
 
+// Large tiles BM x BN on NWM x NWN wavefronts with the partial last round as (BM/2) x
+// (BN/2) tiles on SWM x SWN wavefronts (LowpTileW; same bits as the 128-tiles).
+template <int KIND, int BM, int BN, int NWM, int NWN, int SWM, int SWN>
+__global__ __launch_bounds__(64 * NWM * NWN) void k_gemm_lowp_wide(
+    const uint16_t* __restrict__ S, const uint16_t* __restrict__ T, float* __restrict__ P, int m, int n, int k,
+    int64_t plane_s, int64_t plane_t, const int32_t* __restrict__ eS, const int32_t* __restrict__ eT, int tiles_n,
+    int tiles_per_leaf, int64_t n_big, int64_t n_small) {
+  static_assert(NWM * NWN == SWM * SWN, "one thread count for both tile sizes");
+  constexpr int SB = tiles::LowpTileW<KIND, BM, BN, NWM, NWN>::SMEM_HALVES;
+  constexpr int SH = tiles::LowpTileW<KIND, BM / 2, BN / 2, SWM, SWN>::SMEM_HALVES;
+  __shared__ __attribute__((aligned(16))) uint16_t smem[SB > SH ? SB : SH];
+  int64_t bid;
+  if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid))
+    tiles::gemm_lowp_tile_w<KIND, BM, BN, NWM, NWN>(S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n,
+                                                    tiles_per_leaf, bid, smem);
+  else
+    tiles::gemm_lowp_tile_w<KIND, BM / 2, BN / 2, SWM, SWN>(S, T, P, m, n, k, plane_s, plane_t, eS, eT,
+                                                            2 * tiles_n, 4 * tiles_per_leaf, bid, smem);
+}
+
+template <int KIND, int BM, int BN, int NWM, int NWN, int SWM, int SWN>
+void launch_wide(hipStream_t stream, const uint16_t* S, const uint16_t* T, float* P, int64_t m, int64_t n, int64_t k,
+                 int64_t batch, const int32_t* eS, const int32_t* eT) {
+  const int tiles_n = (int)(n / BN), tiles_per_leaf = (int)((m / BM) * tiles_n);
+  const int64_t nblocks = batch * tiles_per_leaf;
+  const int64_t plane_s = batch * m * k, plane_t = batch * k * n;
+  const void* kern = (const void*)k_gemm_lowp_wide<KIND, BM, BN, NWM, NWN, SWM, SWN>;
+  const TailSplit sp = tail_split(nblocks, resident_blocks(kern, 64 * NWM * NWN));
+  hipLaunchKernelGGL((k_gemm_lowp_wide<KIND, BM, BN, NWM, NWN, SWM, SWN>), dim3((unsigned)(sp.n_big + sp.n_small)),
+                     dim3(64 * NWM * NWN), 0, stream, S, T, P, (int)m, (int)n, (int)k, plane_s, plane_t, eS, eT,
+                     tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
+}
+
 template <int KIND, int BM>
 void launch_split(int64_t nblocks, hipStream_t stream, const uint16_t* S, const uint16_t* T, float* P, int64_t m,
                   int64_t n, int64_t k, int64_t plane_s, int64_t plane_t, const int32_t* eS, const int32_t* eT,
@@ -80,7 +113,18 @@ hipError_t launch_lowp(const uint16_t* S, const uint16_t* T, float* P, int64_t m
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   const int64_t plane_s = batch * m * k, plane_t = batch * k * n;
   const dim3 grid((unsigned)nblocks), block(256);
-  if (tile == 128)
+  // 128-tile plans whose leaves allow it run on the larger tiles (same bits)
+  bool wide = false;
+  if constexpr (KIND == tiles::LOWP_F16S) {
+    if ((wide = tile == 128 && m % 256 == 0 && n % 256 == 0))
+      launch_wide<KIND, 256, 256, 4, 4, 4, 4>(stream, S, T, P, m, n, k, batch, eS, eT);
+  } else {
+    if ((wide = tile == 128 && n % 256 == 0))
+      launch_wide<KIND, 128, 256, 4, 2, 2, 4>(stream, S, T, P, m, n, k, batch, eS, eT);
+  }
+  if (wide)
+    ;
+  else if (tile == 128)
     launch_split<KIND, 128>(nblocks, stream, S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf);
   else if (tile == 64)
     launch_split<KIND, 64>(nblocks, stream, S, T, P, m, n, k, plane_s, plane_t, eS, eT, tiles_n, tiles_per_leaf);
