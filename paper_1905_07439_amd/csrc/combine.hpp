@@ -28,9 +28,6 @@
 #ifndef RBC_NT_LOADS
 #define RBC_NT_LOADS 1
 #endif
-#ifndef RBC_NT_STORES
-#define RBC_NT_STORES 1
-#endif
 #ifndef RBC_LEVEL_BARRIER
 #define RBC_LEVEL_BARRIER 0
 #endif
@@ -168,11 +165,11 @@ __device__ __forceinline__ VecT<T, V> vload(const gbl<const T>* p) {
 
 template <typename T, int V>
 __device__ __forceinline__ void vstore(gbl<T>* p, VecT<T, V> v) {
-#if RBC_NT_STORES
-  __builtin_nontemporal_store(v, reinterpret_cast<gbl<VecT<T, V>>*>(p));
-#else
   *reinterpret_cast<gbl<VecT<T, V>>*>(p) = v;
-#endif
+}
+template <typename T, int V>
+__device__ __forceinline__ void vstore_nt(gbl<T>* p, VecT<T, V> v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<gbl<VecT<T, V>>*>(p));
 }
 
 template <typename T, int OUTF, int V>
@@ -181,10 +178,12 @@ struct GatherEmit {
   int64_t dst_batch, plane, off;
   const int32_t* exps;  // f16s: LDS copy of the exponents of outputs exp_base, exp_base + 1, ...
   int64_t exp_base;
+  bool nt;              // streaming stores (GatherParams::nt_store)
   __device__ __forceinline__ void operator()(int64_t idx, VecT<T, V> v) const {
     if constexpr (OUTF == OUT_SAME) {
-      // streaming store: the leaf operands are read once, by the next kernel
-      vstore<T, V>(global_ptr(static_cast<T*>(dst)) + idx * dst_batch + off, v);
+      gbl<T>* d = global_ptr(static_cast<T*>(dst)) + idx * dst_batch + off;
+      if (nt) vstore_nt<T, V>(d, v);
+      else vstore<T, V>(d, v);
     } else if constexpr (OUTF == OUT_FP8X2) {
       // scaled split: y = 2^e v, hi = rn_e4m3(y), lo = rn_e4m3(16 (y - hi)) (y - hi is exact);
       // the conversions are the hardware's OCP e4m3 round-to-nearest-even ones
@@ -351,7 +350,7 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct,
     }
   }
   const int64_t n_out = R ? ipow(R, NL) : p.lev[0].R;
-  GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, exps, in * n_out};
+  GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, exps, in * n_out, p.nt_store != 0};
   gather_level<T, V, NL, BR, BC, R, gather_staged<T, OUTF, NL, R>(), gather_rolled<OUTF>(), 0>(v, p.lev, ct, in, e);
 }
 

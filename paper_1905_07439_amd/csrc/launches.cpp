@@ -204,6 +204,7 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     gp.dst = ws + (which == 0 ? g.off_a_bot : g.off_b_bot);
     gp.dst_batch = gp.rows_bot * gp.cols_bot;
     gp.n_in = g.n_in;
+    gp.nt_store = gi + 1 < groups.size() ? 1 : 0;
     const bool bf16_out = last && p.prec == RBC_PREC_BF16X3;
     const bool f16_out = last && p.prec == RBC_PREC_F16S;
     const bool fp8_out = last && p.prec == RBC_PREC_FP8C;
