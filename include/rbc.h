@@ -232,6 +232,25 @@ rbc_status rbc_plan_set_leaf_gather(rbc_plan p, int on);
  * gather to its default; the results are the same either way. */
 rbc_status rbc_plan_set_fusion(rbc_plan p, int fuse_max);
 rbc_status rbc_plan_get_leaf_gather(rbc_plan p, int* on, int* available);
+/* Leaf scatter (eq. recursive-random-formula, the W side of the deepest level).
+ * With the leaf gather on, rbc_matmul can also fold the deepest level's scatter
+ * into the leaf product's launch: the workgroup that stores the last of a
+ * parent's R leaf tiles over a 64 x 64 region combines that region of the R
+ * products through the deepest level's folded W (in order over r, one rounding
+ * per multiply and add, zero coefficients skipped) into the parent's product
+ * block, and the scatter passes then start one level up.  C is the same to the
+ * bit.  The plan qualifies with the leaf gather (leaf sides multiples of 64);
+ * its workspace then holds the parents' product blocks and one int32 counter
+ * per parent and 64 x 64 region as well (rbc_plan_get_info's ws_bytes).  Each
+ * leaf tile then ends with an agent-scope release (an L2 write-back on gfx950),
+ * which with the combinations costs more than the scatter pass it saves, so it
+ * is off by default; RBC_LEAF_SCATTER=1 in the environment turns it on for
+ * every new plan that takes the leaf gather.
+ * set: on != 0 fails with RBC_EUNSUPPORTED unless the plan qualifies and its
+ * leaf gather is on; turning the leaf gather off turns it off.  get: whether it
+ * is on and whether the plan qualifies (either pointer may be NULL). */
+rbc_status rbc_plan_set_leaf_scatter(rbc_plan p, int on);
+rbc_status rbc_plan_get_leaf_scatter(rbc_plan p, int* on, int* available);
 void rbc_plan_destroy(rbc_plan p);
 
 /* ---- products ------------------------------------------------------------ */

@@ -314,6 +314,16 @@ class Plan:
     def set_leaf_gather(self, on=True):
         check(lib().rbc_plan_set_leaf_gather(self._h, int(bool(on))))
 
+    @property
+    def leaf_scatter(self):
+        """(on, available): whether matmul folds the deepest level's scatter into the leaf product."""
+        on, av = ctypes.c_int(), ctypes.c_int()
+        check(lib().rbc_plan_get_leaf_scatter(self._h, ctypes.byref(on), ctypes.byref(av)))
+        return bool(on.value), bool(av.value)
+
+    def set_leaf_scatter(self, on=True):
+        check(lib().rbc_plan_set_leaf_scatter(self._h, int(bool(on))))
+
     # ---- timing -------------------------------------------------------------
     def set_timing(self, on=True):
         check(lib().rbc_plan_set_timing(self._h, int(bool(on))))

@@ -105,6 +105,8 @@ SIGNATURES = {
     "rbc_peak_copy": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "rbc_peak_mfma": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, c_vp, c_dbl_p, c_vp]),
     "rbc_plan_get_leaf_gather": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "rbc_plan_set_leaf_scatter": (ctypes.c_int, [c_vp, ctypes.c_int]),
+    "rbc_plan_get_leaf_scatter": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "rbc_plan_timing_collect": (ctypes.c_int, [c_vp, c_dbl_p, ctypes.POINTER(c_i64)]),
     "rbc_batch_create": (ctypes.c_int, [ctypes.POINTER(BatchOptions), ctypes.POINTER(c_vp)]),
     "rbc_batch_add": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_i64, ctypes.c_uint64,

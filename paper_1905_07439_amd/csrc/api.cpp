@@ -185,10 +185,12 @@ rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
     bytes[0] += rdA * e + n_out * g.a_rows_bot * g.a_cols_bot * wo;
     bytes[1] += rdB * e + n_out * g.b_rows_bot * g.b_cols_bot * wo;
   }
-  const size_t ng = p.groups.size();
+  const bool ls = p.leaf_gather && p.leaf_scatter;
+  const std::vector<Group>& sg = ls ? p.fgroups : p.groups;
+  const size_t ng = sg.size();
   for (size_t gi = 0; gi < ng; ++gi) {
-    const Group& g = p.groups[gi];
-    const bool last = gi + 1 == ng;
+    const Group& g = sg[gi];
+    const bool last = gi + 1 == ng && !ls;
     const double n_out = (double)g.n_in * g.Rg;
     // scatter: every bottom block once, the writable part of every top block once
     const double rp = last ? e_prod : e_mid;
@@ -204,6 +206,8 @@ rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
     const double n_par = (double)g.n_in * g.Rg;
     bytes[2] = n_par * ((double)g.a_rows_bot * g.a_cols_bot + (double)g.b_rows_bot * g.b_cols_bot) * e +
                (double)p.n_leaves * p.mM * p.mN * e_prod;
+    // leaf scatter: the products read back once, the parents' product blocks written once
+    if (ls) bytes[2] += (double)p.n_leaves * p.mM * p.mN * e_prod + n_par * (double)g.c_rows_bot * g.c_cols_bot * e_mid;
   }
   return RBC_OK;
 }
@@ -276,16 +280,16 @@ rbc_status run_gathers(Ctx& c, const void* A, int64_t lda, const void* B, int64_
   return RBC_OK;
 }
 
-rbc_status run_leaf(Ctx& c, bool leaf_gather = false) {
-  hipError_t e = leaf_gather ? launch(build_leaf_gather(c.p, c.dr, c.ws), c.stream)
+rbc_status run_leaf(Ctx& c, bool leaf_gather = false, bool leaf_scatter = false, bool kappa_scale = false) {
+  hipError_t e = leaf_gather ? launch(build_leaf_gather(c.p, c.dr, c.ws, leaf_scatter, kappa_scale), c.stream)
                              : launch(build_leaf(c.p, c.ws), c.stream);
   if (e != hipSuccess) return fail(RBC_EHIP, "leaf launch: %s", hipGetErrorString(e));
   return RBC_OK;
 }
 
-rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc) {
+rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc, bool leaf_scatter = false) {
   std::vector<ScatterLaunch> sl;
-  build_scatter(c.p, c.dr, kappa_scale, C, ldc, c.ws, sl);
+  build_scatter(c.p, c.dr, kappa_scale, C, ldc, c.ws, sl, leaf_scatter);
   for (const ScatterLaunch& l : sl) {
     hipError_t e = launch(l, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "scatter launch: %s", hipGetErrorString(e));
@@ -328,9 +332,10 @@ rbc_status rbc::matmul_impl(Plan& p, const void* A, int64_t lda, const void* B, 
     return st;
   }
   if ((st = record(p, c.stream, 2)) != RBC_OK) return st;
-  if ((st = run_leaf(c, lg)) != RBC_OK) return st;
+  const bool ls = lg && p.leaf_scatter;
+  if ((st = run_leaf(c, lg, ls, kappa_scale != 0)) != RBC_OK) return st;
   if ((st = record(p, c.stream, 3)) != RBC_OK) return st;
-  if ((st = run_scatter(c, kappa_scale != 0, C, ldc)) != RBC_OK) return st;
+  if ((st = run_scatter(c, kappa_scale != 0, C, ldc, ls)) != RBC_OK) return st;
   if ((st = record(p, c.stream, 4)) != RBC_OK) return st;
   if (p.timing) ++p.recorded;
   return RBC_OK;
@@ -561,6 +566,22 @@ rbc_status rbc_plan_set_leaf_gather(rbc_plan h, int on) {
   if (on && !h->p.leaf_gather_ok)
     return fail(RBC_EUNSUPPORTED, "leaf gather needs f32, two or more levels and at most two terms per product");
   h->p.leaf_gather = on != 0;
+  if (!on) h->p.leaf_scatter = false;
+  return RBC_OK;
+}
+
+rbc_status rbc_plan_set_leaf_scatter(rbc_plan h, int on) {
+  if (!h) return fail(RBC_EINVAL, "null plan");
+  if (on && !(h->p.leaf_scatter_ok && h->p.leaf_gather))
+    return fail(RBC_EUNSUPPORTED, "leaf scatter needs the leaf gather on");
+  h->p.leaf_scatter = on != 0;
+  return RBC_OK;
+}
+
+rbc_status rbc_plan_get_leaf_scatter(rbc_plan h, int* on, int* available) {
+  if (!h) return fail(RBC_EINVAL, "null plan");
+  if (on) *on = h->p.leaf_scatter ? 1 : 0;
+  if (available) *available = h->p.leaf_scatter_ok ? 1 : 0;
   return RBC_OK;
 }
 

@@ -118,6 +118,13 @@ struct Plan {
   bool leaf_gather_ok = false;   // the plan qualifies
   bool leaf_gather = false;      // rbc_matmul takes that path
   std::vector<Group> fgroups;
+  // Leaf scatter (with the leaf gather): the leaf product also combines the
+  // deepest level's products into the parents' product blocks (off_pc), and
+  // the scatter passes run over fgroups.  Counters at off_cnt, n_cnt of them.
+  bool leaf_scatter_ok = false;
+  bool leaf_scatter = false;
+  size_t off_pc = 0, off_cnt = 0;
+  int64_t n_cnt = 0;
 
   // device state, created on first use (see device.cpp)
   int device = -1;

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include "tile_f32.hpp"
+#include "leaf_scatter.hpp"
 #include "occupancy.hpp"
 
 namespace rbc {
@@ -56,33 +57,59 @@ __global__ __launch_bounds__(256, 3) void k_gemm_f32_128(const float* __restrict
 
 // The same tiles with the operands gathered while they are loaded (LeafGather).
 // BUF: 128-tiles through buffer loads (gemm_f32_gathered_tile; parents under 2 GiB).
-template <bool BUF>
-__global__ __launch_bounds__(256, 3) void k_gemm_f32_128_gathered(const LeafGather g, float* __restrict__ P, int m,
-                                                                  int n, int k, int tiles_n, int tiles_per_leaf,
-                                                                  int64_t n_big, int64_t n_small) {
+// SCAT: the deepest level's scatter follows each tile (LeafScatter).
+template <bool BUF, bool SCAT>
+__global__ __launch_bounds__(256, 3) void k_gemm_f32_128_gathered(const LeafGather g, const LeafScatter ls,
+                                                                  float* __restrict__ P, int m, int n, int k,
+                                                                  int tiles_n, int tiles_per_leaf, int64_t n_big,
+                                                                  int64_t n_small) {
   __shared__ __attribute__((aligned(16))) float smem[kSmem128 > kSmem64 ? kSmem128 : kSmem64];
+  __shared__ int32_t flags[4];
   int64_t bid;
   if (tiles::split_tail(blockIdx.x, n_big, n_small, tiles_n, tiles_per_leaf, &bid)) {
     if constexpr (BUF)
       tiles::gemm_f32_gathered_tile<128, 128, 16, 4>(&g, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem);
     else
       tiles::gemm_f32_tile<128, 128, 16, 4, true>(g.A, g.B, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem, &g);
+    if constexpr (SCAT) {
+      const int64_t leaf = bid / tiles_per_leaf;
+      const int t = (int)(bid - leaf * tiles_per_leaf);
+      tiles::leaf_scatter_tile<128, 128>(ls, P, m, n, g.R, leaf, t / tiles_n, t % tiles_n, flags);
+    }
+    return;
   }
-  else if (k % 32 == 0)
+  if (k % 32 == 0)
     tiles::gemm_f32_tile<64, 64, 32, 2, true>(g.A, g.B, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem,
                                               &g);
   else
     tiles::gemm_f32_tile<64, 64, 16, 2, true>(g.A, g.B, P, m, n, k, 2 * tiles_n, 4 * tiles_per_leaf, bid, smem,
                                               &g);
+  if constexpr (SCAT) {
+    const int64_t leaf = bid / (4 * tiles_per_leaf);
+    const int t = (int)(bid - leaf * 4 * tiles_per_leaf);
+    tiles::leaf_scatter_tile<64, 64>(ls, P, m, n, g.R, leaf, t / (2 * tiles_n), t % (2 * tiles_n), flags);
+  }
 }
 
-template <int BK, int MINB>
-__global__ __launch_bounds__(256, MINB) void k_gemm_f32_64_gathered(const LeafGather g, float* __restrict__ P, int m,
-                                                                    int n, int k, int tiles_n, int tiles_per_leaf,
+template <int BK, int MINB, bool SCAT>
+__global__ __launch_bounds__(256, MINB) void k_gemm_f32_64_gathered(const LeafGather g, const LeafScatter ls,
+                                                                    float* __restrict__ P, int m, int n, int k,
+                                                                    int tiles_n, int tiles_per_leaf,
                                                                     int64_t nblocks) {
   __shared__ __attribute__((aligned(16))) float smem[F32Tile<64, 64, BK, 2>::SMEM];
-  tiles::gemm_f32_tile<64, 64, BK, 2, true>(g.A, g.B, P, m, n, k, tiles_n, tiles_per_leaf,
-                                            tiles::xcd_remap(blockIdx.x, nblocks), smem, &g);
+  __shared__ int32_t flags[1];
+  const int64_t bid = tiles::xcd_remap(blockIdx.x, nblocks);
+  tiles::gemm_f32_tile<64, 64, BK, 2, true>(g.A, g.B, P, m, n, k, tiles_n, tiles_per_leaf, bid, smem, &g);
+  if constexpr (SCAT) {
+    const int64_t leaf = bid / tiles_per_leaf;
+    const int t = (int)(bid - leaf * tiles_per_leaf);
+    tiles::leaf_scatter_tile<64, 64>(ls, P, m, n, g.R, leaf, t / tiles_n, t % tiles_n, flags);
+  }
+}
+
+// Zero n words (the leaf scatter's counters, before its launch).
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
 }
 
 template <int BM, int BN, int BK, int MINB, int EPI>
@@ -204,33 +231,48 @@ hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, 
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_f32_gathered(const LeafGather& g, float* P, int64_t m, int64_t n, int64_t k,
-                                    int64_t batch, int tile, hipStream_t stream) {
-  if (batch == 0 || m == 0 || n == 0) return hipSuccess;
-  if (m % tile || n % tile || k % 16 || (tile != 64 && tile != 128)) return hipErrorInvalidValue;
-  if (!g.A || !g.B || !g.la.tab || !g.lb.tab || g.R < 1 || batch % g.R) return hipErrorInvalidValue;
+template <bool SCAT>
+static hipError_t launch_gathered(const LeafGather& g, const LeafScatter& ls, float* P, int64_t m, int64_t n,
+                                  int64_t k, int tile, int64_t nblocks, hipStream_t stream) {
   const int tiles_n = (int)(n / tile), tiles_per_leaf = (int)((m / tile) * tiles_n);
-  const int64_t nblocks = batch * tiles_per_leaf;
-  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 block(256);
   if (tile == 128) {
     // buffer loads address a parent with 32-bit byte offsets
     const bool buf = g.a_batch < (int64_t(1) << 29) && g.b_batch < (int64_t(1) << 29);
-    const void* kern = buf ? (const void*)k_gemm_f32_128_gathered<true> : (const void*)k_gemm_f32_128_gathered<false>;
+    const void* kern = buf ? (const void*)k_gemm_f32_128_gathered<true, SCAT>
+                           : (const void*)k_gemm_f32_128_gathered<false, SCAT>;
     const TailSplit sp = tail_split(nblocks, resident_blocks(kern, 256));
     if (buf)
-      hipLaunchKernelGGL(k_gemm_f32_128_gathered<true>, dim3((unsigned)(sp.n_big + sp.n_small)), block, 0, stream, g,
-                         P, (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
+      hipLaunchKernelGGL((k_gemm_f32_128_gathered<true, SCAT>), dim3((unsigned)(sp.n_big + sp.n_small)), block, 0,
+                         stream, g, ls, P, (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
     else
-      hipLaunchKernelGGL(k_gemm_f32_128_gathered<false>, dim3((unsigned)(sp.n_big + sp.n_small)), block, 0, stream,
-                         g, P, (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
+      hipLaunchKernelGGL((k_gemm_f32_128_gathered<false, SCAT>), dim3((unsigned)(sp.n_big + sp.n_small)), block, 0,
+                         stream, g, ls, P, (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, sp.n_big, sp.n_small);
   } else if (k % 32 == 0)
-    hipLaunchKernelGGL((k_gemm_f32_64_gathered<32, 4>), dim3((unsigned)nblocks), block, 0, stream, g, P, (int)m,
-                       (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
+    hipLaunchKernelGGL((k_gemm_f32_64_gathered<32, 4, SCAT>), dim3((unsigned)nblocks), block, 0, stream, g, ls, P,
+                       (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
   else
-    hipLaunchKernelGGL((k_gemm_f32_64_gathered<16, 4>), dim3((unsigned)nblocks), block, 0, stream, g, P, (int)m,
-                       (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
+    hipLaunchKernelGGL((k_gemm_f32_64_gathered<16, 4, SCAT>), dim3((unsigned)nblocks), block, 0, stream, g, ls, P,
+                       (int)m, (int)n, (int)k, tiles_n, tiles_per_leaf, nblocks);
   return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32_gathered(const LeafGather& g, float* P, int64_t m, int64_t n, int64_t k,
+                                    int64_t batch, int tile, hipStream_t stream, const LeafScatter* ls) {
+  if (batch == 0 || m == 0 || n == 0) return hipSuccess;
+  if (m % tile || n % tile || k % 16 || (tile != 64 && tile != 128)) return hipErrorInvalidValue;
+  if (!g.A || !g.B || !g.la.tab || !g.lb.tab || g.R < 1 || batch % g.R) return hipErrorInvalidValue;
+  const int64_t nblocks = batch * (m / tile) * (n / tile);
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (!ls) return launch_gathered<false>(g, LeafScatter{}, P, m, n, k, tile, nblocks, stream);
+  if (!ls->out || !ls->cnt || !ls->lw.tab || ls->br < 1 || ls->bc < 1 || ls->br > kMaxB || ls->bc > kMaxB)
+    return hipErrorInvalidValue;
+  const int64_t n_cnt = batch / g.R * (m / 64) * (n / 64);
+  const int64_t zb = (n_cnt + 255) / 256;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)(zb < 1024 ? zb : 1024)), dim3(256), 0, stream, ls->cnt, n_cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gathered<true>(g, *ls, P, m, n, k, tile, nblocks, stream);
 }
 
 hipError_t launch_gemm_f64(const double* S, const double* T, double* P, int64_t m, int64_t n,

@@ -83,6 +83,23 @@ struct LeafGather {
   int32_t bra, bca, brb, bcb, R;
 };
 
+// The deepest level's scatter folded into the same launch (leaf scatter): the
+// R leaf products of a parent (leaves parent * R + r) are combined through the
+// deepest level's folded W into the parent's product block, sub-block (k, l)
+// = the sum over r, in order, of the folded coefficient times P_r (one
+// rounding per multiply and per add, products with a zero coefficient
+// skipped), as that level's scatter would.  A per-parent counter for every
+// 64 x 64 region of a leaf counts the leaf tiles stored there; the workgroup
+// whose tile brings a region's count to R combines that region.
+struct LeafScatter {
+  float* out;                // parents' product blocks: out_batch elements apart, row stride out_ld
+  int32_t* cnt;              // (m / 64) (n / 64) counters per parent, zero before the launch
+  int64_t out_batch, out_ld;
+  int64_t row_blk, col_blk;  // element offset of sub-block (1, 0) and of (0, 1) in an out block
+  SideLevel lw;              // the deepest level's C side (f32 table)
+  int32_t br, bc;            // sub-blocks of an out block (b1 x b3)
+};
+
 // Element-type codes for launchers.
 enum Elt { ELT_F32 = 0, ELT_F64 = 1 };
 
@@ -101,9 +118,12 @@ hipError_t launch_scatter(Elt tp, Elt ta, Elt to, int vec, int nl, int br, int b
 // each row-major and contiguous, consecutive leaves back to back.
 hipError_t launch_gemm_f32(const float* S, const float* T, float* P, int64_t m, int64_t n, int64_t k,
                            int64_t batch, int tile, hipStream_t stream);
-// P (batch leaves of m x n) from operands gathered on the fly (LeafGather).
+// P (batch leaves of m x n) from operands gathered on the fly (LeafGather);
+// with ls, also the parents' product blocks (LeafScatter; its counters are
+// cleared by this call, on the stream, before the product).
 hipError_t launch_gemm_f32_gathered(const LeafGather& g, float* P, int64_t m, int64_t n, int64_t k,
-                                    int64_t batch, int tile, hipStream_t stream);
+                                    int64_t batch, int tile, hipStream_t stream,
+                                    const LeafScatter* ls = nullptr);
 hipError_t launch_gemm_f64(const double* S, const double* T, double* P, int64_t m, int64_t n,
                            int64_t k, int64_t batch, hipStream_t stream);
 // Leaves of any size m x k by k x n (no tile padding), f32 or f64 (exact-block plans).

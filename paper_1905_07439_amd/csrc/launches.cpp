@@ -243,9 +243,11 @@ LeafLaunch build_leaf(const Plan& p, char* ws) {
   return L;
 }
 
-LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws) {
+LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws, bool leaf_scatter,
+                                   bool kappa_scale) {
   LeafGatherLaunch L;
   std::memset(&L.g, 0, sizeof L.g);
+  std::memset(&L.ls, 0, sizeof L.ls);
   const Group& up = p.fgroups.back();
   const Scheme& s = p.levels[p.Q - 1];
   LeafGather& g = L.g;
@@ -260,16 +262,27 @@ LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws) {
   g.bra = s.b1, g.bca = s.b2, g.brb = s.b2, g.bcb = s.b3, g.R = s.R;
   L.P = reinterpret_cast<float*>(ws + p.off_P);
   L.m = p.mM, L.n = p.mN, L.k = p.mK, L.batch = p.n_leaves, L.tile = p.tile_m;
+  L.scatter = leaf_scatter;
+  if (leaf_scatter) {
+    LeafScatter& ls = L.ls;
+    ls.out = reinterpret_cast<float*>(ws + p.off_pc);
+    ls.cnt = reinterpret_cast<int32_t*>(ws + p.off_cnt);
+    ls.out_ld = up.c_cols_bot, ls.out_batch = up.c_rows_bot * up.c_cols_bot;
+    ls.row_blk = p.mM * ls.out_ld, ls.col_blk = p.mN;
+    fill_side(p, dr, p.Q - 1, SIDE_C, false, kappa_scale, ls.lw);
+    ls.br = s.b1, ls.bc = s.b3;
+  }
   return L;
 }
 
 void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, int64_t ldc, char* ws,
-                   std::vector<ScatterLaunch>& out) {
+                   std::vector<ScatterLaunch>& out, bool leaf_scatter) {
   out.clear();
   const bool f64_tabs = p.prec == RBC_PREC_F64 || p.prec == RBC_PREC_BF16X3;
-  for (size_t gi = p.groups.size(); gi-- > 0;) {
-    const Group& g = p.groups[gi];
-    const bool last = gi + 1 == p.groups.size();
+  const std::vector<Group>& groups = leaf_scatter ? p.fgroups : p.groups;
+  for (size_t gi = groups.size(); gi-- > 0;) {
+    const Group& g = groups[gi];
+    const bool last = gi + 1 == groups.size() && !leaf_scatter;
     ScatterLaunch L;
     ScatterParams& sp = L.p;
     std::memset(&sp, 0, sizeof sp);
@@ -279,7 +292,7 @@ void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, in
     if (gi == 0) {
       sp.dst = C, sp.ld_dst = ldc, sp.dst_batch = 0, sp.dst_rows = p.M, sp.dst_cols = p.N;
     } else {
-      const Group& up = p.groups[gi - 1];
+      const Group& up = groups[gi - 1];
       sp.dst = ws + up.off_c_bot;
       sp.ld_dst = g.c_cols_top, sp.dst_batch = g.c_rows_top * g.c_cols_top;
       sp.dst_rows = g.c_rows_top, sp.dst_cols = g.c_cols_top;
@@ -352,7 +365,7 @@ hipError_t launch(const LeafLaunch& l, hipStream_t s) {
 }
 
 hipError_t launch(const LeafGatherLaunch& l, hipStream_t s) {
-  return launch_gemm_f32_gathered(l.g, l.P, l.m, l.n, l.k, l.batch, l.tile, s);
+  return launch_gemm_f32_gathered(l.g, l.P, l.m, l.n, l.k, l.batch, l.tile, s, l.scatter ? &l.ls : nullptr);
 }
 
 hipError_t launch(const ScatterLaunch& l, hipStream_t s) {

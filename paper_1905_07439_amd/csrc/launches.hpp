@@ -62,6 +62,8 @@ struct LeafGatherLaunch {  // f32 leaf products with the deepest level gathered 
   float* P;
   int64_t m, n, k, batch;
   int tile;
+  bool scatter;              // and the deepest level's scatter after each tile (ls)
+  LeafScatter ls;
 };
 
 struct ScatterLaunch {
@@ -76,11 +78,14 @@ struct ScatterLaunch {
 void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int64_t ldx, char* ws,
                   std::vector<ScaleLaunch>& scale, std::vector<GatherLaunch>& out, bool leaf_gather = false);
 LeafLaunch build_leaf(const Plan& p, char* ws);
-// Requires p.leaf_gather_ok.
-LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws);
-// In execution order (deepest group first).
+// Requires p.leaf_gather_ok; leaf_scatter (requires p.leaf_scatter_ok): the
+// launch also writes the parents' product blocks (kappa_scale as for the scatter).
+LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws, bool leaf_scatter = false,
+                                   bool kappa_scale = false);
+// In execution order (deepest group first).  leaf_scatter: the passes of levels
+// [0, Q - 1) (Plan::fgroups), from the parents' product blocks.
 void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, int64_t ldc, char* ws,
-                   std::vector<ScatterLaunch>& out);
+                   std::vector<ScatterLaunch>& out, bool leaf_scatter = false);
 
 hipError_t launch(const ScaleLaunch& l, hipStream_t s);
 hipError_t launch(const ScaleLaunch& a, const ScaleLaunch& b, hipStream_t s);  // both in one launch

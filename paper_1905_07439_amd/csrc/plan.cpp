@@ -135,6 +135,17 @@ static int leaf_gather_env() {
   return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : -1;
 }
 
+// RBC_LEAF_SCATTER=1 turns the leaf scatter on for every new plan that takes
+// the leaf gather; unset or 0, it is off (it costs more than it saves: f32
+// Strassen F-hat^(3) at N = 4096, leaf 0.78 -> 1.10 ms against a scatter
+// 0.117 -> 0.058 ms; of the 0.32 ms, about 0.14 ms are the release fences'
+// L2 write-backs, one per leaf tile, and 0.18 ms the combinations, whose
+// loads the waiting tile slots cannot hide).
+static int leaf_scatter_env() {
+  const char* e = std::getenv("RBC_LEAF_SCATTER");
+  return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : -1;
+}
+
 // f32 bytes the gathers of A and B move over `gs` (each top block read once,
 // each bottom block written once).
 static double gather_bytes(const Plan& p, const std::vector<Group>& gs) {
@@ -264,8 +275,24 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     if (last && bb <= p.bytes_T) g.off_b_bot = p.off_T;
     else g.off_b_bot = off, off = align256(off + bb);
   }
+  // Leaf scatter: the parents' product blocks, fgroups' intermediate product
+  // blocks, and the counters.
+  p.leaf_scatter_ok = p.leaf_gather_ok && p.mM % 64 == 0 && p.mN % 64 == 0;
+  if (p.leaf_scatter_ok) {
+    for (size_t gi = 0; gi < p.fgroups.size(); ++gi) {
+      Group& g = p.fgroups[gi];
+      const size_t nb = (size_t)g.n_in * g.Rg;
+      g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * 4);
+    }
+    const Group& g = p.fgroups.back();
+    p.off_pc = g.off_c_bot;
+    p.n_cnt = (int64_t)g.n_in * g.Rg * (p.mM / 64) * (p.mN / 64);
+    p.off_cnt = off, off = align256(off + (size_t)p.n_cnt * 4);
+  }
   const int env = leaf_gather_env();
   p.leaf_gather = p.leaf_gather_ok && (env < 0 ? leaf_gather_pays(p) : env == 1);
+  const int senv = leaf_scatter_env();
+  p.leaf_scatter = p.leaf_gather && p.leaf_scatter_ok && senv == 1;
   if (prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) {
     p.off_aux = off;
     p.bytes_aux = kAuxExpOffset + 2 * (size_t)p.n_leaves * 4;
