@@ -7,7 +7,11 @@ is one full pass of the hot path: draws + fold for every level, gather of A
 and B, the batched leaf GEMM, and the scatter into C, with A and B resident
 in HBM.  With the plan's leaf gather on (the default at this size) the
 gathers stop one level above the leaves and the leaf GEMM forms its operands
-from those parent blocks while loading them.  Prints one JSON line.
+from those parent blocks while loading them.  Prints one JSON line; besides
+the headline it carries, each measured outside the timed steps, the f64 N = 64
+latency case, one rank-10 APA row on bf16 hi+lo leaves at N = 3072, and
+compact rows of the 512-product batch (f16 leaves) and of the served request
+stream (fp8 leaves, 0.5 s of arrivals).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --workload approx3072     # approximate scheme, bf16 hi+lo leaves
@@ -332,6 +336,10 @@ def batch_levels(n):
 
 
 def batch512(args):
+    print(json.dumps(batch512_line(args)), flush=True)
+
+
+def batch512_line(args):
     """512 independent products, N_i = 96 k_i with k_i uniform on {2..24} (size seed 4000),
     Laderman then Strassen to leaves of 64..128, f16 leaves with per-leaf power-of-two scales,
     all in one persistent launch replayed from a HIP graph.  A_i, B_i are N(0,1) times one
@@ -466,10 +474,14 @@ def batch512(args):
                      "unit": "GB/s", "frac": round(traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None, "algorithmic_bytes": traffic},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def serve_stream(args):
+    print(json.dumps(serve_line(args)), flush=True)
+
+
+def serve_line(args):
     """Requests C = A B arriving as a Poisson process at 2000 per second (seed 5000) for
     --serve-seconds, N log-uniform in [128, 4096] (multiples of 32), scheme uniform over
     Strassen, Laderman and the approximate (perturbed Strassen, lambda = 1e-3) scheme, one
@@ -556,7 +568,35 @@ def serve_stream(args):
         "runs": out_rows,
         "capacity_all_arrived_at_0": capacity,
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def _compact_rows(args):
+    """The batched and the served configurations' headline figures, for the default line
+    (each in a few seconds; a failure is reported in its row instead of ending the line)."""
+    rows = {}
+    try:
+        b = batch512_line(argparse.Namespace(batch_count=512, batch_budget_gb=args.batch_budget_gb, steps=3,
+                                             warmup=1))
+        rows["batch512_f16s"] = {
+            "ms_per_batch": b["ms_per_step"], "tflops": b["value"], "steps": 3,
+            "rel_err_vs_fp64": b["rel_err_vs_fp64"], "levels_mode": b["levels_mode"], "same_gpu": b["same_gpu"],
+            "hbm_frac_algorithmic": b["roofline"]["frac"], "workload": b["config"]["workload"]}
+    except Exception as e:  # noqa: BLE001 -- reported, not fatal for the headline
+        rows["batch512_f16s"] = {"error": repr(e)}
+    try:
+        v = serve_line(argparse.Namespace(serve_seconds=0.5))
+        runs = v["runs"]
+        rows["serve_fp8c"] = {
+            "seconds_of_arrivals": 0.5, "p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"], "tflops": v["value"],
+            "rel_err_vs_fp64": runs["fp8c_direct"]["rel_err_vs_fp64"],
+            "f32_recursive_same_stream": {"p50_ms": round(runs["f32_direct"]["latency_ms"]["p50"], 3),
+                                          "p99_ms": round(runs["f32_direct"]["latency_ms"]["p99"], 3),
+                                          "tflops": round(runs["f32_direct"]["effective_tflops"], 3)},
+            "capacity_all_arrived_at_0": v["capacity_all_arrived_at_0"], "workload": v["config"]["workload"]}
+    except Exception as e:  # noqa: BLE001
+        rows["serve_fp8c"] = {"error": repr(e)}
+    return rows
 
 
 def leaves(args):
@@ -637,6 +677,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-budget-gb", type=int, default=24)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="the headline workload alone (no other configurations' rows): for profiler runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this library has no multi-GPU path (requested --gpus %d)"
@@ -751,8 +793,10 @@ def main():
         "roofline": roofline,
     }
     # the other configurations' headline figures, cheap enough for the default line
-    out["small64_f64_n64_q2"] = small64_stats(1000, 20)
-    out["apa322_n3072_q1_bf16x3"] = apa3072_row(max(5, args.steps // 2), 3)
+    if not args.headline_only:
+        out["small64_f64_n64_q2"] = small64_stats(1000, 20)
+        out["apa322_n3072_q1_bf16x3"] = apa3072_row(max(5, args.steps // 2), 3)
+        out.update(_compact_rows(args))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A64, B64)
     print(json.dumps(out), flush=True)

@@ -239,9 +239,10 @@ rbc_status rbc_plan_get_leaf_gather(rbc_plan p, int* on, int* available);
  * products through the deepest level's folded W (in order over r, one rounding
  * per multiply and add, zero coefficients skipped) into the parent's product
  * block, and the scatter passes then start one level up.  C is the same to the
- * bit.  The plan qualifies with the leaf gather (leaf sides multiples of 64);
- * its workspace then holds the parents' product blocks and one int32 counter
- * per parent and 64 x 64 region as well (rbc_plan_get_info's ws_bytes).  Each
+ * bit.  The plan qualifies with the leaf gather (leaf sides multiples of 64).
+ * Turning it on the first time appends to the plan's workspace the parents'
+ * product blocks and one int32 counter per parent and 64 x 64 region (query
+ * rbc_plan_get_info's ws_bytes again; it stays that size).  Each
  * leaf tile then ends with an agent-scope release (an L2 write-back on gfx950),
  * which with the combinations costs more than the scatter pass it saves, so it
  * is off by default; RBC_LEAF_SCATTER=1 in the environment turns it on for

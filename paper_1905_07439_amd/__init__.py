@@ -322,7 +322,13 @@ class Plan:
         return bool(on.value), bool(av.value)
 
     def set_leaf_scatter(self, on=True):
+        """Turning it on the first time enlarges the workspace (a cached one is dropped)."""
         check(lib().rbc_plan_set_leaf_scatter(self._h, int(bool(on))))
+        inf = PlanInfo()
+        check(lib().rbc_plan_get_info(self._h, ctypes.byref(inf)))
+        if inf.as_dict()["workspace_bytes"] != self.info["workspace_bytes"]:
+            self.info = inf.as_dict()
+            self._ws = None
 
     # ---- timing -------------------------------------------------------------
     def set_timing(self, on=True):

@@ -574,6 +574,7 @@ rbc_status rbc_plan_set_leaf_scatter(rbc_plan h, int on) {
   if (!h) return fail(RBC_EINVAL, "null plan");
   if (on && !(h->p.leaf_scatter_ok && h->p.leaf_gather))
     return fail(RBC_EUNSUPPORTED, "leaf scatter needs the leaf gather on");
+  if (on) layout_leaf_scatter(h->p);
   h->p.leaf_scatter = on != 0;
   return RBC_OK;
 }

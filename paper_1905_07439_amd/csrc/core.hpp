@@ -121,6 +121,7 @@ struct Plan {
   // Leaf scatter (with the leaf gather): the leaf product also combines the
   // deepest level's products into the parents' product blocks (off_pc), and
   // the scatter passes run over fgroups.  Counters at off_cnt, n_cnt of them.
+  // Those regions are laid out (off_cnt != 0) when it is first turned on.
   bool leaf_scatter_ok = false;
   bool leaf_scatter = false;
   size_t off_pc = 0, off_cnt = 0;
@@ -135,6 +136,9 @@ struct Plan {
   std::vector<void*> events;     // hipEvent_t, 5 per recorded call
   int64_t recorded = 0;
 };
+
+// The leaf scatter's workspace regions (appended to the plan's workspace on first use).
+void layout_leaf_scatter(Plan& p);
 
 // Is a fused group of `nl` levels of shape <b1,b2,b3> with R products compiled?
 bool fused_supported(int b1, int b2, int b3, int R, int nl);

@@ -171,6 +171,21 @@ static bool leaf_gather_pays(const Plan& p) {
   return saved_us > 0.09 * flops / 125e6;
 }
 
+void layout_leaf_scatter(Plan& p) {
+  if (!p.leaf_scatter_ok || p.off_cnt) return;
+  size_t off = align256(p.ws_bytes);
+  for (size_t gi = 0; gi < p.fgroups.size(); ++gi) {
+    Group& g = p.fgroups[gi];
+    const size_t nb = (size_t)g.n_in * g.Rg;
+    g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * 4);
+  }
+  const Group& g = p.fgroups.back();
+  p.off_pc = g.off_c_bot;
+  p.n_cnt = (int64_t)g.n_in * g.Rg * (p.mM / 64) * (p.mN / 64);
+  p.off_cnt = off, off = align256(off + (size_t)p.n_cnt * 4);
+  p.ws_bytes = off;
+}
+
 rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>& levels,
                      rbc_prec prec, int leaf_tile, Plan& out, bool fuse_max) {
   if (M < 1 || K < 1 || N < 1) return fail(RBC_EINVAL, "empty product %lldx%lldx%lld", (long long)M,
@@ -275,24 +290,10 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     if (last && bb <= p.bytes_T) g.off_b_bot = p.off_T;
     else g.off_b_bot = off, off = align256(off + bb);
   }
-  // Leaf scatter: the parents' product blocks, fgroups' intermediate product
-  // blocks, and the counters.
   p.leaf_scatter_ok = p.leaf_gather_ok && p.mM % 64 == 0 && p.mN % 64 == 0;
-  if (p.leaf_scatter_ok) {
-    for (size_t gi = 0; gi < p.fgroups.size(); ++gi) {
-      Group& g = p.fgroups[gi];
-      const size_t nb = (size_t)g.n_in * g.Rg;
-      g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * 4);
-    }
-    const Group& g = p.fgroups.back();
-    p.off_pc = g.off_c_bot;
-    p.n_cnt = (int64_t)g.n_in * g.Rg * (p.mM / 64) * (p.mN / 64);
-    p.off_cnt = off, off = align256(off + (size_t)p.n_cnt * 4);
-  }
   const int env = leaf_gather_env();
   p.leaf_gather = p.leaf_gather_ok && (env < 0 ? leaf_gather_pays(p) : env == 1);
-  const int senv = leaf_scatter_env();
-  p.leaf_scatter = p.leaf_gather && p.leaf_scatter_ok && senv == 1;
+  p.leaf_scatter = p.leaf_gather && p.leaf_scatter_ok && leaf_scatter_env() == 1;
   if (prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) {
     p.off_aux = off;
     p.bytes_aux = kAuxExpOffset + 2 * (size_t)p.n_leaves * 4;
@@ -315,6 +316,7 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     }
   }
   p.ws_bytes = std::max<size_t>(off, 256);
+  if (p.leaf_scatter) layout_leaf_scatter(p);
 
   // Host tables per level: U, V, W and (1 - kappa)^-1 W, in f64 and f32.
   for (const Scheme& s : levels) {

@@ -71,6 +71,10 @@ def test_leaf_scatter_same_bits(names, M, K, N, tile):
     g.manual_seed(M + 3 * K + 7 * N)
     A = torch.randn(M, K, device=DEV, generator=g)
     B = torch.randn(K, N, device=DEV, generator=g)
+    before = plan.workspace_bytes
+    plan.set_leaf_gather(True)
+    plan.set_leaf_scatter(True)  # lays out its regions: the workspace grows once
+    assert plan.workspace_bytes > before
     ws = plan.workspace(DEV)
     for seed, mode, ks in [(0, "full", True), (5, "full", False), (1, "signs", True), (3, "none", False),
                            (2, "perms", True)]:
