@@ -229,7 +229,8 @@ rbc_status rbc_plan_set_leaf_gather(rbc_plan p, int on);
  * them alone.  fuse_max = 1 fuses wherever the shapes allow (for batches: many
  * products share the GPU, and fewer, larger tasks pay).  Changing it re-lays
  * out the workspace (query rbc_plan_get_info again) and resets the leaf
- * gather to its default; the results are the same either way. */
+ * gather and the leaf scatter to their defaults; the results are the same either
+ * way. */
 rbc_status rbc_plan_set_fusion(rbc_plan p, int fuse_max);
 rbc_status rbc_plan_get_leaf_gather(rbc_plan p, int* on, int* available);
 /* Leaf scatter (eq. recursive-random-formula, the W side of the deepest level).
