@@ -95,7 +95,7 @@ typedef struct {
   int64_t mM, mK, mN;       /* leaf block: S is mM x mK, T is mK x mN */
   int64_t n_leaves;         /* prod_d R_d */
   int32_t levels;           /* Q */
-  int32_t n_groups;         /* fused level groups */
+  int32_t n_groups;         /* fused level groups of the gathers (and of the batch engine's scatters) */
   int32_t prec;             /* rbc_prec */
   int32_t tile_m, tile_n, tile_k;  /* leaf GEMM tile */
   size_t workspace_bytes;   /* minimum workspace for rbc_matmul */
@@ -104,6 +104,8 @@ typedef struct {
   size_t off_aux, bytes_aux;       /* RBC_PREC_F16S, RBC_PREC_FP8C: partial maxima of |A| and of
                                       |B| (1024 f32 each, scratch), then at off_aux + 8192 the
                                       per-leaf exponents of S and of T (n_leaves int32 each) */
+  int32_t n_scatter_groups; /* scatter passes of rbc_matmul and rbc_stage_scatter: up to three
+                               2x2x2, rank-7 levels share one where the pass has enough work */
 } rbc_plan_info;
 
 const char* rbc_status_str(rbc_status s);

@@ -26,7 +26,8 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t),
                 ("off_S", ctypes.c_size_t), ("off_T", ctypes.c_size_t), ("off_P", ctypes.c_size_t),
                 ("bytes_S", ctypes.c_size_t), ("bytes_T", ctypes.c_size_t), ("bytes_P", ctypes.c_size_t),
-                ("off_aux", ctypes.c_size_t), ("bytes_aux", ctypes.c_size_t)]
+                ("off_aux", ctypes.c_size_t), ("bytes_aux", ctypes.c_size_t),
+                ("n_scatter_groups", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -160,6 +160,7 @@ rbc_status rbc_plan_get_info(rbc_plan h, rbc_plan_info* info) {
   info->off_S = p.off_S, info->off_T = p.off_T, info->off_P = p.off_P;
   info->bytes_S = p.bytes_S, info->bytes_T = p.bytes_T, info->bytes_P = p.bytes_P;
   info->off_aux = p.off_aux, info->bytes_aux = p.bytes_aux;
+  info->n_scatter_groups = (int32_t)p.sgroups.size();
   return RBC_OK;
 }
 
@@ -186,7 +187,7 @@ rbc_status rbc_plan_traffic(rbc_plan h, double bytes[4]) {
     bytes[1] += rdB * e + n_out * g.b_rows_bot * g.b_cols_bot * wo;
   }
   const bool ls = p.leaf_gather && p.leaf_scatter;
-  const std::vector<Group>& sg = ls ? p.fgroups : p.groups;
+  const std::vector<Group>& sg = ls ? p.fgroups : p.sgroups;
   const size_t ng = sg.size();
   for (size_t gi = 0; gi < ng; ++gi) {
     const Group& g = sg[gi];
@@ -289,7 +290,7 @@ rbc_status run_leaf(Ctx& c, bool leaf_gather = false, bool leaf_scatter = false,
 
 rbc_status run_scatter(Ctx& c, bool kappa_scale, void* C, int64_t ldc, bool leaf_scatter = false) {
   std::vector<ScatterLaunch> sl;
-  build_scatter(c.p, c.dr, kappa_scale, C, ldc, c.ws, sl, leaf_scatter);
+  build_scatter(c.p, c.dr, kappa_scale, C, ldc, c.ws, sl, leaf_scatter ? c.p.fgroups : c.p.sgroups, leaf_scatter);
   for (const ScatterLaunch& l : sl) {
     hipError_t e = launch(l, c.stream);
     if (e != hipSuccess) return fail(RBC_EHIP, "scatter launch: %s", hipGetErrorString(e));

@@ -204,7 +204,7 @@ struct Builder {
     for (GatherLaunch& l : gB) l.p.scale_partial = nullptr;
     const LeafLaunch lf = build_leaf(p, item_ws);
     std::vector<ScatterLaunch> sc;  // deepest group first
-    build_scatter(p, dr, it.kappa_scale != 0, it.C, it.ldc, item_ws, sc);
+    build_scatter(p, dr, it.kappa_scale != 0, it.C, it.ldc, item_ws, sc, p.groups);
     const int ng = (int)p.groups.size();
 
     // counters of this item

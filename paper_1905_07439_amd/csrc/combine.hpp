@@ -19,9 +19,12 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "devptr.hpp"
 #include "scale.hpp"
 #include "kernels.hpp"
+#include "occupancy.hpp"
 
 #pragma clang fp contract(off)
 
@@ -109,11 +112,11 @@ constexpr int coef_entries() {
 
 // Every thread of the workgroup calls this; it ends with a barrier when it
 // stages anything.
-template <typename T, int NS, int BR, int BC, int R>
+template <typename T, int NS, int BR, int BC, int R, int NT = 256>
 __device__ __forceinline__ void stage_coefs(const SideLevel* lev, T* lds) {
   constexpr int BB = BR * BC, RM = R ? R : kMaxR;
   if constexpr (NS > 0) {
-    for (int i = threadIdx.x; i < NS * BB * RM; i += 256) {
+    for (int i = threadIdx.x; i < NS * BB * RM; i += NT) {
       const int lt = i / (BB * RM), rem = i - lt * (BB * RM), kl = rem / RM, r = rem - kl * RM;
       const SideLevel& L = lev[lt];
       const int RR = R ? R : L.R;
@@ -433,12 +436,40 @@ __device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t 
   }
 }
 
+// Output sub-block s of a scatter group (digits base BR * BC, the deepest
+// level's least significant) at bottom position (y, x) of top block dst.
+template <typename TA, typename TO, int V, int NL, int BR, int BC>
+__device__ __forceinline__ void scatter_store(const ScatterParams& p, gbl<TO>* dst, int64_t y, int64_t x, int s,
+                                              const VecT<TA, V>& v) {
+  constexpr int BB = BR * BC;
+  int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
+  int rem = s;
+#pragma unroll
+  for (int t = 0; t < NL; ++t) {
+    const int d = rem % BB;
+    rem /= BB;
+    row += (d / BC) * hs;
+    col += (d % BC) * ws;
+    hs *= BR;
+    ws *= BC;
+  }
+  VecT<TO, V> w;
+#pragma unroll
+  for (int e = 0; e < V; ++e) w[e] = (TO)v[e];
+  if (row < p.dst_rows && col + V <= p.dst_cols) {
+    *reinterpret_cast<gbl<VecT<TO, V>>*>(dst + row * p.ld_dst + col) = w;  // aligned: checked by the host
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+      if (row < p.dst_rows && col + e < p.dst_cols) dst[row * p.ld_dst + col + e] = w[e];
+  }
+}
+
 // One workgroup's share of a scatter: 256 threads x V positions (block bx)
 // of top block o.
 template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
 __device__ __forceinline__ void scatter_block(const ScatterParams& p, const TA* ct, int64_t bx, int64_t o) {
-  constexpr int BB = BR * BC;
-  constexpr int NOUT = ipow(BB, NL);
+  constexpr int NOUT = ipow(BR * BC, NL);
   const int64_t npos = p.rows_bot * p.cols_bot;
   const int64_t pos = (bx * 256 + threadIdx.x) * V;
   if (pos >= npos) return;
@@ -448,29 +479,7 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, const TA* 
   scatter_level<TP, TA, V, NL, BR, BC, R, scatter_staged<TA, NL, R>(), 0>(src, p.src_batch, pos, p.lev, ct, o, out);
   gbl<TO>* dst = global_ptr(static_cast<TO*>(p.dst)) + o * p.dst_batch;
 #pragma unroll
-  for (int s = 0; s < NOUT; ++s) {
-    int64_t row = y, col = x, hs = p.rows_bot, ws = p.cols_bot;
-    int rem = s;
-#pragma unroll
-    for (int t = 0; t < NL; ++t) {
-      const int d = rem % BB;
-      rem /= BB;
-      row += (d / BC) * hs;
-      col += (d % BC) * ws;
-      hs *= BR;
-      ws *= BC;
-    }
-    VecT<TO, V> w;
-#pragma unroll
-    for (int e = 0; e < V; ++e) w[e] = (TO)out[s][e];
-    if (row < p.dst_rows && col + V <= p.dst_cols) {
-      *reinterpret_cast<gbl<VecT<TO, V>>*>(dst + row * p.ld_dst + col) = w;  // aligned: checked by the host
-    } else {
-#pragma unroll
-      for (int e = 0; e < V; ++e)
-        if (row < p.dst_rows && col + e < p.dst_cols) dst[row * p.ld_dst + col + e] = w[e];
-    }
-  }
+  for (int s = 0; s < NOUT; ++s) scatter_store<TA, TO, V, NL, BR, BC>(p, dst, y, x, s, out[s]);
 }
 
 template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
@@ -479,6 +488,226 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
   stage_scatter_coefs<TA, NL, BR, BC, R>(p.lev, ct);
   for (int64_t o = blockIdx.y; o < p.n_out; o += gridDim.y)
     scatter_block<TP, TA, TO, V, NL, BR, BC, R>(p, ct, blockIdx.x, o);
+}
+
+// Scatters over levels whose W table has Strassen's zero pattern
+// (SideLevel::w_strassen).  Output block ij of such a level reads table block
+// b = (pr[k] * 2 + pc[l]) for (k, l) = (ij / 2, ij % 2); with the level's row
+// and column permutations fixed (pr[0] = PR0, pc[0] = PC0) b is a compile-time
+// function of ij, and so are the products that feed it (kStrassenWNz[b]), so
+// the zero terms are never formed.  The first term stands alone and the rest
+// are added in ascending r, as in scatter_level.
+template <int PR0, int PC0>
+__host__ __device__ constexpr int sw_block(int ij) {
+  return (((ij >> 1) ^ PR0) << 1) | ((ij & 1) ^ PC0);
+}
+
+// The folded coefficient of output block ij, product r of a Strassen-shaped
+// level: staged in LDS (level LT < NS) or the table entry by a scalar load,
+// uniform either way.
+template <typename TA, int NS, int LT>
+__device__ __forceinline__ TA coef_u(const SideLevel* lev, const TA* ct, int ij, int r) {
+  if constexpr (LT < NS)
+    return ct[(LT * 4 + ij) * 7 + r];
+  else
+    return coef<TA, 2, true>(lev[LT], ij / 2, ij % 2, r, 7);
+}
+
+// The two lower levels of a three-level group for top product prefix idx,
+// the deepest level with Strassen's pattern: out[ij1 * 4 + ij2] = level-1
+// block ij1, sub-block ij2, the same roundings as scatter_level<.., 1>.  The
+// next level-1 product's seven loads are issued before the current one is
+// combined.  Level 1 skips a zero coefficient by a (uniform) branch, its sums
+// starting at -0 so that the first term's sum is that term, sign of zero
+// included; a sum that took no term is set to +0 at the end.
+template <typename TP, typename TA, int V, int NS, int PR0, int PC0>
+__device__ __forceinline__ void scatter3_lower_sw(const gbl<const TP>* src, int64_t src_batch, int64_t off,
+                                                  const SideLevel* lev, const TA* ct, int64_t idx,
+                                                  VecT<TA, V>* out) {
+  TA c2[4][4];
+#pragma unroll
+  for (int ij2 = 0; ij2 < 4; ++ij2) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int b = sw_block<PR0, PC0>(ij2);
+      c2[ij2][n] = n < kStrassenWNzCount[b] ? coef_u<TA, NS, 2>(lev, ct, ij2, kStrassenWNz[b][n]) : TA(0);
+    }
+  }
+  bool any1[4] = {false, false, false, false};
+#pragma unroll
+  for (int j = 0; j < 16; ++j) out[j] = VecT<TA, V>(TA(-0.0));
+  const gbl<const TP>* base = src + idx * 49 * src_batch + off;
+  VecT<TA, V> x[7];
+#pragma unroll
+  for (int r2 = 0; r2 < 7; ++r2) {
+    const VecT<TP, V> v = vload<TP, V>(base + r2 * src_batch);
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[r2][e] = (TA)v[e];
+  }
+#pragma unroll 1
+  for (int r1 = 0; r1 < 7; ++r1) {
+    VecT<TP, V> xn[7];
+    if (r1 + 1 < 7) {
+#pragma unroll
+      for (int r2 = 0; r2 < 7; ++r2) xn[r2] = vload<TP, V>(base + ((r1 + 1) * 7 + r2) * src_batch);
+    }
+    VecT<TA, V> p2[4];
+#pragma unroll
+    for (int ij2 = 0; ij2 < 4; ++ij2) {
+      const int b = sw_block<PR0, PC0>(ij2);
+      p2[ij2] = c2[ij2][0] * x[kStrassenWNz[b][0]];
+#pragma unroll
+      for (int n = 1; n < 4; ++n)
+        if (n < kStrassenWNzCount[b]) p2[ij2] = p2[ij2] + c2[ij2][n] * x[kStrassenWNz[b][n]];
+    }
+#pragma unroll
+    for (int ij1 = 0; ij1 < 4; ++ij1) {
+      const TA c = coef_u<TA, NS, 1>(lev, ct, ij1, r1);
+      if (c != TA(0)) {
+        __asm__ volatile("");  // a uniform branch, not four selects per term
+#pragma unroll
+        for (int ij2 = 0; ij2 < 4; ++ij2) out[ij1 * 4 + ij2] = out[ij1 * 4 + ij2] + c * p2[ij2];
+        any1[ij1] = true;
+      }
+    }
+#pragma unroll
+    for (int r2 = 0; r2 < 7; ++r2)
+#pragma unroll
+      for (int e = 0; e < V; ++e) x[r2][e] = (TA)xn[r2][e];
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (!any1[j / 4]) out[j] = VecT<TA, V>(TA(0));
+}
+
+// The top level of a three-level group with Strassen's pattern for the 8
+// output sub-blocks j0 .. j0 + 7 of top block ij (uniform): acc[q] = the sum
+// over the nonzero products r of c_r m[r][j0 + q], first term alone, r
+// ascending.  The table block, and with it the products, is chosen by a
+// uniform branch.
+template <typename TA, int V, int NS>
+__device__ __forceinline__ void scatter3_top_sw(const SideLevel* lev, const TA* ct, int ij, int j0,
+                                                const VecT<TA, V>* m, int lane, VecT<TA, V>* acc) {
+  auto body = [&](auto bconst) {
+    constexpr int b = decltype(bconst)::value;
+    TA c[4];
+#pragma unroll
+    for (int n = 0; n < kStrassenWNzCount[b]; ++n) c[n] = coef_u<TA, NS, 0>(lev, ct, ij, kStrassenWNz[b][n]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      acc[q] = c[0] * m[(kStrassenWNz[b][0] * 16 + j0 + q) * 64 + lane];
+#pragma unroll
+      for (int n = 1; n < kStrassenWNzCount[b]; ++n)
+        acc[q] = acc[q] + c[n] * m[(kStrassenWNz[b][n] * 16 + j0 + q) * 64 + lane];
+    }
+  };
+  const int b = __builtin_amdgcn_readfirstlane(lev[0].pr[ij >> 1] * 2 + lev[0].pc[ij & 1]);
+  if (b == 0)
+    body(std::integral_constant<int, 0>());
+  else if (b == 1)
+    body(std::integral_constant<int, 1>());
+  else if (b == 2)
+    body(std::integral_constant<int, 2>());
+  else
+    body(std::integral_constant<int, 3>());
+}
+
+// Three fused levels of 2 x 2 blocks and 7 products each.  A task is one top
+// block and 64 V positions of the bottom block; a persistent workgroup of 512
+// threads walks its tasks in a two-stage pipeline with two LDS buffers.  In
+// step t every wavefront w first combines the top level of task t - 1 for its
+// 8 output sub-blocks 8 w .. 8 w + 7 (top block w / 2, so the coefficients are
+// uniform) over ascending r and stores them; then wavefront w < 7 forms, for
+// task t and the top level's product w, the 16 sub-block values of the two
+// lower levels (scatter_level: the walk and order of one thread of k_scatter)
+// and leaves them in LDS.  One barrier per step.  Every output is the same
+// sequence of roundings as in k_scatter, so the bits are the same.  Measured
+// on the f32 scatter of N = 4096, Q = 3 (one box): two passes (k_scatter over
+// levels [1, 3), then level 0) 143 us; one thread holding all 64 outputs of a
+// position, about 100 values in registers, 124-132 us; this kernel with the
+// general walk 122-131 us, with only loads in the walk 80 us (the walk's
+// selects and multiplies bound it, not the memory), and with the walks
+// specialized to Strassen's pattern 94 us.
+template <typename TP, typename TA, typename TO, int V>
+__global__ __launch_bounds__(512) void k_scatter3(ScatterParams p) {
+  constexpr int NL = 3, BR = 2, BC = 2, R = 7, SUB = 16;
+  constexpr int NS = scatter_staged<TA, NL, R>();
+  __shared__ TA ct[scatter_coef_entries<TA, NL, BR, BC, R>()];
+  __shared__ VecT<TA, V> mid[2][R * SUB * 64];
+  stage_coefs<TA, NS, BR, BC, R, 512>(p.lev, ct);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ij = w >> 1, j0 = (w & 1) * 8;
+  const int64_t npos = p.rows_bot * p.cols_bot;
+  const int64_t nblk = (npos + 64 * V - 1) / (64 * V);
+  const int64_t ntask = nblk * p.n_out;
+  const int64_t mine = blockIdx.x < ntask ? (ntask - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const gbl<const TP>* src = global_ptr(static_cast<const TP*>(p.src));
+  // Strassen's pattern in the top level's table; in the deepest level's, the
+  // case (pr[0], pc[0]) of its specialized walk (-1: the general walk)
+  const bool sw0 = p.lev[0].w_strassen != 0;
+  const int sw2 = p.lev[2].w_strassen ? p.lev[2].pr[0] * 2 + p.lev[2].pc[0] : -1;
+  for (int64_t t = 0; t <= mine; ++t) {
+    if (t > 0) {
+      const int64_t task = blockIdx.x + (t - 1) * gridDim.x;
+      const int64_t o = task / nblk, pos = ((task - o * nblk) * 64 + lane) * V;
+      const VecT<TA, V>* m = mid[(t - 1) & 1];
+      VecT<TA, V> acc[8];
+      if (sw0) {
+        scatter3_top_sw<TA, V, NS>(p.lev, ct, ij, j0, m, lane, acc);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = VecT<TA, V>(TA(0));
+        bool first = true;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          TA c;
+          if constexpr (NS > 0)
+            c = ct[ij * R + r];
+          else
+            c = coef<TA, BC, true>(p.lev[0], ij / BC, ij % BC, r, R);
+          const bool nz = c != TA(0);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const VecT<TA, V> tv = c * m[(r * SUB + j0 + q) * 64 + lane];
+            const VecT<TA, V> sum = first ? tv : acc[q] + tv;
+            acc[q] = nz ? sum : acc[q];
+          }
+          first = first && !nz;
+        }
+      }
+      if (pos < npos) {
+        const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
+        gbl<TO>* dst = global_ptr(static_cast<TO*>(p.dst)) + o * p.dst_batch;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) scatter_store<TA, TO, V, NL, BR, BC>(p, dst, y, x, ij * SUB + j0 + q, acc[q]);
+      }
+    }
+    if (w < R && t < mine) {
+      const int64_t task = blockIdx.x + t * gridDim.x;
+      const int64_t o = task / nblk, pos = ((task - o * nblk) * 64 + lane) * V;
+      VecT<TA, V> sub[SUB];
+      if (pos < npos) {
+        const gbl<const TP>* s0 = src;
+        const int64_t pr = o * R + w;
+        if (sw2 == 0)
+          scatter3_lower_sw<TP, TA, V, NS, 0, 0>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+        else if (sw2 == 1)
+          scatter3_lower_sw<TP, TA, V, NS, 0, 1>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+        else if (sw2 == 2)
+          scatter3_lower_sw<TP, TA, V, NS, 1, 0>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+        else if (sw2 == 3)
+          scatter3_lower_sw<TP, TA, V, NS, 1, 1>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+        else
+          scatter_level<TP, TA, V, NL, BR, BC, R, NS, 1>(src, p.src_batch, pos, p.lev, ct, pr, sub);
+      } else {
+#pragma unroll
+        for (int j = 0; j < SUB; ++j) sub[j] = VecT<TA, V>(TA(0));
+      }
+#pragma unroll
+      for (int j = 0; j < SUB; ++j) mid[t & 1][(w * SUB + j) * 64 + lane] = sub[j];
+    }
+    __syncthreads();
+  }
 }
 
 inline dim3 grid_for(int64_t npos, int64_t nbatch) {
@@ -500,8 +729,19 @@ hipError_t run_gather(const GatherPair& pp, hipStream_t s) {
 
 template <typename TP, typename TA, typename TO, int V, int NL, int BR, int BC, int R>
 hipError_t run_scatter(const ScatterParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((k_scatter<TP, TA, TO, V, NL, BR, BC, R>),
-                     grid_for(p.rows_bot * p.cols_bot / V, p.n_out), dim3(256), 0, s, p);
+  if constexpr (NL == 3 && BR == 2 && BC == 2 && R == 7) {
+    // one position per thread whatever the alignment allows: with two, the
+    // walk's registers and the doubled LDS buffers leave one workgroup per CU
+    constexpr int VV = 1;
+    const int64_t ntask = (p.rows_bot * p.cols_bot / VV + 63) / 64 * p.n_out;
+    void (*kfn)(ScatterParams) = k_scatter3<TP, TA, TO, VV>;
+    const int64_t slots = resident_blocks(reinterpret_cast<const void*>(kfn), 512);
+    const int64_t g = slots > 0 && slots < ntask ? slots : ntask;
+    hipLaunchKernelGGL(kfn, dim3((unsigned)g), dim3(512), 0, s, p);
+  } else {
+    hipLaunchKernelGGL((k_scatter<TP, TA, TO, V, NL, BR, BC, R>),
+                       grid_for(p.rows_bot * p.cols_bot / V, p.n_out), dim3(256), 0, s, p);
+  }
   return hipGetLastError();
 }
 

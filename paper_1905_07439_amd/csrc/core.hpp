@@ -56,9 +56,16 @@ struct SideLevel {
   int8_t pr[kMaxB], pc[kMaxB];
   int8_t sr[kMaxB], sc[kMaxB];
   int32_t R;
-  int32_t pad_;
+  int32_t w_strassen;  // C side: the table's nonzero entries are those of kStrassenWNz
   const void* tab;  // device table of this side (f64 or f32, see Plan)
 };
+
+// Nonzero products of each 2 x 2 output block (11, 12, 21, 22) in Strassen's W,
+// the form of Golub & Van Loan: C11 = P1 + P4 - P5 + P7, C12 = P3 + P5,
+// C21 = P2 + P4, C22 = P1 - P2 + P3 + P6 (0-based, padded with -1).  Scatters
+// over tables with exactly this pattern skip the zero terms at compile time.
+constexpr int kStrassenWNz[4][4] = {{0, 3, 4, 6}, {2, 4, -1, -1}, {1, 3, -1, -1}, {0, 1, 2, 5}};
+constexpr int kStrassenWNzCount[4] = {4, 2, 2, 4};
 
 // Consecutive levels that one kernel pass fuses.  All levels of a group share
 // the block shape <b1, b2, b3>.  "top" blocks enter the group from above (the
@@ -114,6 +121,12 @@ struct Plan {
   // fgroups then gather levels [0, Q - 1) (the last one's bottom blocks, the
   // parents of the leaves, at off_S and off_T when they fit there); the stage
   // calls and the batch engine keep the separate gather of every level.
+  // Scatter passes of rbc_matmul and the stage calls: as `groups`, but up to
+  // three Strassen-shaped levels per pass (k_scatter3, one pass where two
+  // would write and re-read the blocks between them).  The gathers and the
+  // batch engine keep `groups`.  Boundary buffers are those of `groups` where
+  // a boundary coincides, else unused ones of `groups` or new ones.
+  std::vector<Group> sgroups;
   bool fuse_max = false;         // fuse levels regardless of the pass's parallel work
   bool leaf_gather_ok = false;   // the plan qualifies
   bool leaf_gather = false;      // rbc_matmul takes that path

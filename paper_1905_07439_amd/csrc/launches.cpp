@@ -123,6 +123,20 @@ void fill_side(const Plan& p, const Draws& dr, int level, Side side, bool f64, b
   for (int j = 0; j < nc; ++j) L.pc[j] = (int8_t)pc[j], L.sc[j] = (int8_t)sc[j];
   L.R = s.R;
   L.tab = table(p, level, kind, f64);
+  if (side == SIDE_C && s.b1 == 2 && s.b3 == 2 && s.R == 7) {
+    // the table the kernels read, in their precision
+    const LevelTables& t = p.tables[level];
+    bool same = true;
+    for (int b = 0; b < 4 && same; ++b)
+      for (int r = 0; r < 7 && same; ++r) {
+        bool listed = false;
+        for (int n = 0; n < kStrassenWNzCount[b]; ++n) listed = listed || kStrassenWNz[b][n] == r;
+        const size_t i = (size_t)b * 7 + r;
+        const double v = f64 ? (kappa_scale ? t.Wk[i] : t.W[i]) : (double)(kappa_scale ? t.Wkf[i] : t.Wf[i]);
+        same = (v != 0.0) == listed;
+      }
+    L.w_strassen = same ? 1 : 0;
+  }
 }
 
 }  // namespace
@@ -276,13 +290,12 @@ LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws, boo
 }
 
 void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, int64_t ldc, char* ws,
-                   std::vector<ScatterLaunch>& out, bool leaf_scatter) {
+                   std::vector<ScatterLaunch>& out, const std::vector<Group>& groups, bool from_parents) {
   out.clear();
   const bool f64_tabs = p.prec == RBC_PREC_F64 || p.prec == RBC_PREC_BF16X3;
-  const std::vector<Group>& groups = leaf_scatter ? p.fgroups : p.groups;
   for (size_t gi = groups.size(); gi-- > 0;) {
     const Group& g = groups[gi];
-    const bool last = gi + 1 == groups.size() && !leaf_scatter;
+    const bool last = gi + 1 == groups.size() && !from_parents;
     ScatterLaunch L;
     ScatterParams& sp = L.p;
     std::memset(&sp, 0, sizeof sp);

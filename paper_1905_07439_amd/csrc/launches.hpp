@@ -82,10 +82,12 @@ LeafLaunch build_leaf(const Plan& p, char* ws);
 // launch also writes the parents' product blocks (kappa_scale as for the scatter).
 LeafGatherLaunch build_leaf_gather(const Plan& p, const Draws& dr, char* ws, bool leaf_scatter = false,
                                    bool kappa_scale = false);
-// In execution order (deepest group first).  leaf_scatter: the passes of levels
-// [0, Q - 1) (Plan::fgroups), from the parents' product blocks.
+// In execution order (deepest group first), over `groups`: Plan::groups (the
+// batch engine), Plan::sgroups (rbc_matmul, the stage calls) or, with
+// from_parents (leaf scatter), Plan::fgroups: the passes of levels [0, Q - 1)
+// from the parents' product blocks.
 void build_scatter(const Plan& p, const Draws& dr, bool kappa_scale, void* C, int64_t ldc, char* ws,
-                   std::vector<ScatterLaunch>& out, bool leaf_scatter = false);
+                   std::vector<ScatterLaunch>& out, const std::vector<Group>& groups, bool from_parents = false);
 
 hipError_t launch(const ScaleLaunch& l, hipStream_t s);
 hipError_t launch(const ScaleLaunch& a, const ScaleLaunch& b, hipStream_t s);  // both in one launch

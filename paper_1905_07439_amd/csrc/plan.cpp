@@ -29,15 +29,18 @@ bool fused_supported(int b1, int b2, int b3, int R, int nl) {
   return (nl == 2 || nl == 3) && strassen_shape;
 }
 
-// Most levels one pass fuses.  Three fused levels need about 100 values in
-// registers per thread, which costs occupancy; two keep every kernel under
-// 80 VGPRs.  Override with the environment variable RBC_MAX_FUSED_LEVELS.
-static int max_fused_levels() {
+// Most levels one pass fuses.  Three fused levels in one thread need about
+// 100 values in registers, which costs occupancy: gathers take two.  Scatters
+// take three (scatter = true): k_scatter3 spreads the top level over the
+// wavefronts of its workgroup.  The environment variable RBC_MAX_FUSED_LEVELS
+// overrides both.
+static int max_fused_levels(bool scatter = false) {
   const char* e = std::getenv("RBC_MAX_FUSED_LEVELS");
   if (e && *e) {
     const int v = std::atoi(e);
     if (v >= 1 && v <= 3) return v;
   }
+  if (scatter) return 3;
   return 2;
 }
 
@@ -69,10 +72,9 @@ static bool enough_work(const Plan& p, int d, int g_d1) {
   return n_in * (a > b ? a : b) >= 262144.0;
 }
 
-static std::vector<Group> form_groups(const Plan& p, int d_end) {
+static std::vector<Group> form_groups(const Plan& p, int d_end, int max_nl) {
   const std::vector<Scheme>& levels = p.levels;
   std::vector<Group> gs;
-  const int max_nl = max_fused_levels();
   for (int d = d_end - 1; d >= 0; --d) {
     const Scheme& s = levels[d];
     if (!gs.empty()) {
@@ -255,9 +257,10 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
   const int leaf_op_bytes = prec == RBC_PREC_F64 ? 8 : ((prec == RBC_PREC_F16S || prec == RBC_PREC_FP8C) ? 2 : 4);
   const int prod_bytes = prec == RBC_PREC_F64 ? 8 : 4;
 
-  p.groups = form_groups(p, p.Q);
+  p.groups = form_groups(p, p.Q, max_fused_levels());
+  p.sgroups = form_groups(p, p.Q, max_fused_levels(true));
   p.leaf_gather_ok = prec == RBC_PREC_F32 && !p.exact_blocks && p.Q >= 2 && two_terms(levels[p.Q - 1]);
-  if (p.leaf_gather_ok) p.fgroups = form_groups(p, p.Q - 1);
+  if (p.leaf_gather_ok) p.fgroups = form_groups(p, p.Q - 1, max_fused_levels());
 
   // Workspace: leaf operands, products, then the group-boundary buffers.
   size_t off = 0;
@@ -277,6 +280,35 @@ rbc_status make_plan(int64_t M, int64_t K, int64_t N, const std::vector<Scheme>&
     g.off_a_bot = off, off = align256(off + nb * g.a_rows_bot * g.a_cols_bot * p.comb_bytes);
     g.off_b_bot = off, off = align256(off + nb * g.b_rows_bot * g.b_cols_bot * p.comb_bytes);
     g.off_c_bot = off, off = align256(off + nb * g.c_rows_bot * g.c_cols_bot * p.recomb_bytes);
+  }
+  // Scatter groups: a boundary that `groups` also has shares its buffer; any
+  // other takes a buffer of `groups` that no scatter group uses, if one is
+  // large enough, else a new one.
+  {
+    std::vector<bool> used(p.groups.size(), false);
+    for (size_t gi = 0; gi + 1 < p.sgroups.size(); ++gi)
+      for (size_t h = 0; h + 1 < p.groups.size(); ++h)
+        if (p.groups[h].d1 == p.sgroups[gi].d1) used[h] = true;
+    for (size_t gi = 0; gi < p.sgroups.size(); ++gi) {
+      Group& g = p.sgroups[gi];
+      g.off_a_bot = g.off_b_bot = 0;  // gathers never run over these groups
+      if (gi + 1 == p.sgroups.size()) {
+        g.off_c_bot = p.off_P;
+        continue;
+      }
+      const size_t need = (size_t)g.n_in * g.Rg * g.c_rows_bot * g.c_cols_bot * p.recomb_bytes;
+      bool placed = false;
+      for (size_t h = 0; h + 1 < p.groups.size() && !placed; ++h) {
+        const Group& o = p.groups[h];
+        if (o.d1 == g.d1) g.off_c_bot = o.off_c_bot, placed = true;
+      }
+      for (size_t h = 0; h + 1 < p.groups.size() && !placed; ++h) {
+        const Group& o = p.groups[h];
+        if (!used[h] && (size_t)o.n_in * o.Rg * o.c_rows_bot * o.c_cols_bot * p.recomb_bytes >= need)
+          g.off_c_bot = o.off_c_bot, used[h] = true, placed = true;
+      }
+      if (!placed) g.off_c_bot = off, off = align256(off + need);
+    }
   }
   // Leaf gather: the leaves' parents go where the leaf operands would be when
   // they fit (the two paths never run at once on one workspace).

@@ -212,6 +212,29 @@ def test_fusion_needs_parallel_work():
         assert rbc.Plan(n, n, n, [S] * q, prec=prec).info["n_groups"] == groups, (prec, n, q)
 
 
+def test_scatter_passes_take_three_levels():
+    # Scatters fuse up to three Strassen-shaped levels per pass under the same
+    # parallel-work rule; the gathers (and the batch engine) keep two.
+    if os.environ.get("RBC_MAX_FUSED_LEVELS"):
+        pytest.skip("the environment fixes the fusion depth")
+    S = rbc.Scheme.builtin("strassen")
+    cases = [("f32", 4096, 3, 2, 1), ("f64", 4096, 3, 2, 1), ("f32", 4096, 4, 2, 2), ("f32", 2048, 3, 2, 2),
+             ("f32", 1024, 3, 3, 3), ("f32", 8192, 3, 2, 1), ("fp8c", 4096, 4, 2, 2), ("f32", 4096, 2, 1, 1)]
+    for prec, n, q, groups, sgroups in cases:
+        i = rbc.Plan(n, n, n, [S] * q, prec=prec).info
+        assert (i["n_groups"], i["n_scatter_groups"]) == (groups, sgroups), (prec, n, q)
+    L = rbc.Scheme.builtin("laderman")
+    i = rbc.Plan(4096, 4096, 4096, [L, S, S, S], prec="f32").info
+    assert i["n_scatter_groups"] == 2
+    # the workspace does not grow: boundary buffers are shared with the gathers' groups
+    os.environ["RBC_MAX_FUSED_LEVELS"] = "2"
+    try:
+        two = rbc.Plan(4096, 4096, 4096, [S] * 4, prec="f32").info
+    finally:
+        del os.environ["RBC_MAX_FUSED_LEVELS"]
+    assert rbc.Plan(4096, 4096, 4096, [S] * 4, prec="f32").info["workspace_bytes"] == two["workspace_bytes"]
+
+
 def test_fusion_max_option():
     if os.environ.get("RBC_MAX_FUSED_LEVELS"):
         pytest.skip("the environment fixes the fusion depth")
