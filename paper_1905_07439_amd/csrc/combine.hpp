@@ -436,6 +436,120 @@ __device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t 
   }
 }
 
+// Scatters over levels whose W table has Strassen's zero pattern
+// (SideLevel::w_strassen).  Output block ij of such a level reads table block
+// b = (pr[k] * 2 + pc[l]) for (k, l) = (ij / 2, ij % 2); with the level's row
+// and column permutations fixed (pr[0] = PR0, pc[0] = PC0) b is a compile-time
+// function of ij, and so are the products that feed it (kStrassenWNz[b]), so
+// the zero terms are never formed.  The first term stands alone and the rest
+// are added in ascending r, as in scatter_level.
+template <int PR0, int PC0>
+__host__ __device__ constexpr int sw_block(int ij) {
+  return (((ij >> 1) ^ PR0) << 1) | ((ij & 1) ^ PC0);
+}
+
+// The folded coefficient of output block ij, product r of a Strassen-shaped
+// level: staged in LDS (level LT < NS) or the table entry by a scalar load,
+// uniform either way.
+template <typename TA, int NS, int LT>
+__device__ __forceinline__ TA coef_u(const SideLevel* lev, const TA* ct, int ij, int r) {
+  if constexpr (LT < NS)
+    return ct[(LT * 4 + ij) * 7 + r];
+  else
+    return coef<TA, 2, true>(lev[LT], ij / 2, ij % 2, r, 7);
+}
+
+// Levels LO and LO + 1 of a scatter group (the latter its deepest, with
+// Strassen's pattern) for prefix idx at level LO: out[ij1 * 4 + ij2] = block
+// ij1 of level LO, sub-block ij2, the same roundings as scatter_level<.., LO>.
+// The next level-LO product's seven loads are issued before the current one
+// is combined.  Level LO skips a zero coefficient by a (uniform) branch, its
+// sums starting at -0 so that the first term's sum is that term, sign of zero
+// included; a sum that took no term is set to +0 at the end.
+template <typename TP, typename TA, int V, int NS, int LO, int PR0, int PC0>
+__device__ __forceinline__ void scatter2_sw(const gbl<const TP>* src, int64_t src_batch, int64_t off,
+                                            const SideLevel* lev, const TA* ct, int64_t idx, VecT<TA, V>* out) {
+  TA c2[4][4];
+#pragma unroll
+  for (int ij2 = 0; ij2 < 4; ++ij2) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int b = sw_block<PR0, PC0>(ij2);
+      c2[ij2][n] = n < kStrassenWNzCount[b] ? coef_u<TA, NS, LO + 1>(lev, ct, ij2, kStrassenWNz[b][n]) : TA(0);
+    }
+  }
+  bool any1[4] = {false, false, false, false};
+#pragma unroll
+  for (int j = 0; j < 16; ++j) out[j] = VecT<TA, V>(TA(-0.0));
+  const gbl<const TP>* base = src + idx * 49 * src_batch + off;
+  VecT<TA, V> x[7];
+#pragma unroll
+  for (int r2 = 0; r2 < 7; ++r2) {
+    const VecT<TP, V> v = vload<TP, V>(base + r2 * src_batch);
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[r2][e] = (TA)v[e];
+  }
+#pragma unroll 1
+  for (int r1 = 0; r1 < 7; ++r1) {
+    VecT<TP, V> xn[7];
+    if (r1 + 1 < 7) {
+#pragma unroll
+      for (int r2 = 0; r2 < 7; ++r2) xn[r2] = vload<TP, V>(base + ((r1 + 1) * 7 + r2) * src_batch);
+    }
+    VecT<TA, V> p2[4];
+#pragma unroll
+    for (int ij2 = 0; ij2 < 4; ++ij2) {
+      const int b = sw_block<PR0, PC0>(ij2);
+      p2[ij2] = c2[ij2][0] * x[kStrassenWNz[b][0]];
+#pragma unroll
+      for (int n = 1; n < 4; ++n)
+        if (n < kStrassenWNzCount[b]) p2[ij2] = p2[ij2] + c2[ij2][n] * x[kStrassenWNz[b][n]];
+    }
+#pragma unroll
+    for (int ij1 = 0; ij1 < 4; ++ij1) {
+      const TA c = coef_u<TA, NS, LO>(lev, ct, ij1, r1);
+      if (c != TA(0)) {
+        __asm__ volatile("");  // a uniform branch, not four selects per term
+#pragma unroll
+        for (int ij2 = 0; ij2 < 4; ++ij2) out[ij1 * 4 + ij2] = out[ij1 * 4 + ij2] + c * p2[ij2];
+        any1[ij1] = true;
+      }
+    }
+#pragma unroll
+    for (int r2 = 0; r2 < 7; ++r2)
+#pragma unroll
+      for (int e = 0; e < V; ++e) x[r2][e] = (TA)xn[r2][e];
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (!any1[j / 4]) out[j] = VecT<TA, V>(TA(0));
+}
+
+// The deepest level alone, with Strassen's pattern: out[ij] = block ij for
+// prefix idx, the products that feed it known at compile time (PR0, PC0 as
+// above), first term alone, r ascending.
+template <typename TP, typename TA, int V, int NS, int PR0, int PC0>
+__device__ __forceinline__ void scatter1_sw(const gbl<const TP>* src, int64_t src_batch, int64_t off,
+                                            const SideLevel* lev, const TA* ct, int64_t idx, VecT<TA, V>* out) {
+  const gbl<const TP>* base = src + idx * 7 * src_batch + off;
+  VecT<TA, V> x[7];
+#pragma unroll
+  for (int r = 0; r < 7; ++r) {
+    const VecT<TP, V> v = vload<TP, V>(base + r * src_batch);
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[r][e] = (TA)v[e];
+  }
+#pragma unroll
+  for (int ij = 0; ij < 4; ++ij) {
+    const int b = sw_block<PR0, PC0>(ij);
+    out[ij] = coef_u<TA, NS, 0>(lev, ct, ij, kStrassenWNz[b][0]) * x[kStrassenWNz[b][0]];
+#pragma unroll
+    for (int n = 1; n < 4; ++n)
+      if (n < kStrassenWNzCount[b])
+        out[ij] = out[ij] + coef_u<TA, NS, 0>(lev, ct, ij, kStrassenWNz[b][n]) * x[kStrassenWNz[b][n]];
+  }
+}
+
 // Output sub-block s of a scatter group (digits base BR * BC, the deepest
 // level's least significant) at bottom position (y, x) of top block dst.
 template <typename TA, typename TO, int V, int NL, int BR, int BC>
@@ -476,7 +590,38 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, const TA* 
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;
   const gbl<const TP>* src = global_ptr(static_cast<const TP*>(p.src));
   VecT<TA, V> out[NOUT];
-  scatter_level<TP, TA, V, NL, BR, BC, R, scatter_staged<TA, NL, R>(), 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+  constexpr int NS = scatter_staged<TA, NL, R>();
+  // Strassen's pattern in the deepest level's table: its case (pr[0], pc[0])
+  int sw = -1;
+  if constexpr (BR == 2 && BC == 2 && R == 7 && (NL == 1 || NL == 2)) {
+    const SideLevel& D = p.lev[NL - 1];
+    if (D.w_strassen) sw = D.pr[0] * 2 + D.pc[0];
+  }
+  if constexpr (BR == 2 && BC == 2 && R == 7 && NL == 2) {
+    if (sw == 0)
+      scatter2_sw<TP, TA, V, NS, 0, 0, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else if (sw == 1)
+      scatter2_sw<TP, TA, V, NS, 0, 0, 1>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else if (sw == 2)
+      scatter2_sw<TP, TA, V, NS, 0, 1, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else if (sw == 3)
+      scatter2_sw<TP, TA, V, NS, 0, 1, 1>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else
+      scatter_level<TP, TA, V, NL, BR, BC, R, NS, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+  } else if constexpr (BR == 2 && BC == 2 && R == 7 && NL == 1) {
+    if (sw == 0)
+      scatter1_sw<TP, TA, V, NS, 0, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else if (sw == 1)
+      scatter1_sw<TP, TA, V, NS, 0, 1>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else if (sw == 2)
+      scatter1_sw<TP, TA, V, NS, 1, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else if (sw == 3)
+      scatter1_sw<TP, TA, V, NS, 1, 1>(src, p.src_batch, pos, p.lev, ct, o, out);
+    else
+      scatter_level<TP, TA, V, NL, BR, BC, R, NS, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+  } else {
+    scatter_level<TP, TA, V, NL, BR, BC, R, NS, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
+  }
   gbl<TO>* dst = global_ptr(static_cast<TO*>(p.dst)) + o * p.dst_batch;
 #pragma unroll
   for (int s = 0; s < NOUT; ++s) scatter_store<TA, TO, V, NL, BR, BC>(p, dst, y, x, s, out[s]);
@@ -488,96 +633,6 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterParams p) {
   stage_scatter_coefs<TA, NL, BR, BC, R>(p.lev, ct);
   for (int64_t o = blockIdx.y; o < p.n_out; o += gridDim.y)
     scatter_block<TP, TA, TO, V, NL, BR, BC, R>(p, ct, blockIdx.x, o);
-}
-
-// Scatters over levels whose W table has Strassen's zero pattern
-// (SideLevel::w_strassen).  Output block ij of such a level reads table block
-// b = (pr[k] * 2 + pc[l]) for (k, l) = (ij / 2, ij % 2); with the level's row
-// and column permutations fixed (pr[0] = PR0, pc[0] = PC0) b is a compile-time
-// function of ij, and so are the products that feed it (kStrassenWNz[b]), so
-// the zero terms are never formed.  The first term stands alone and the rest
-// are added in ascending r, as in scatter_level.
-template <int PR0, int PC0>
-__host__ __device__ constexpr int sw_block(int ij) {
-  return (((ij >> 1) ^ PR0) << 1) | ((ij & 1) ^ PC0);
-}
-
-// The folded coefficient of output block ij, product r of a Strassen-shaped
-// level: staged in LDS (level LT < NS) or the table entry by a scalar load,
-// uniform either way.
-template <typename TA, int NS, int LT>
-__device__ __forceinline__ TA coef_u(const SideLevel* lev, const TA* ct, int ij, int r) {
-  if constexpr (LT < NS)
-    return ct[(LT * 4 + ij) * 7 + r];
-  else
-    return coef<TA, 2, true>(lev[LT], ij / 2, ij % 2, r, 7);
-}
-
-// The two lower levels of a three-level group for top product prefix idx,
-// the deepest level with Strassen's pattern: out[ij1 * 4 + ij2] = level-1
-// block ij1, sub-block ij2, the same roundings as scatter_level<.., 1>.  The
-// next level-1 product's seven loads are issued before the current one is
-// combined.  Level 1 skips a zero coefficient by a (uniform) branch, its sums
-// starting at -0 so that the first term's sum is that term, sign of zero
-// included; a sum that took no term is set to +0 at the end.
-template <typename TP, typename TA, int V, int NS, int PR0, int PC0>
-__device__ __forceinline__ void scatter3_lower_sw(const gbl<const TP>* src, int64_t src_batch, int64_t off,
-                                                  const SideLevel* lev, const TA* ct, int64_t idx,
-                                                  VecT<TA, V>* out) {
-  TA c2[4][4];
-#pragma unroll
-  for (int ij2 = 0; ij2 < 4; ++ij2) {
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const int b = sw_block<PR0, PC0>(ij2);
-      c2[ij2][n] = n < kStrassenWNzCount[b] ? coef_u<TA, NS, 2>(lev, ct, ij2, kStrassenWNz[b][n]) : TA(0);
-    }
-  }
-  bool any1[4] = {false, false, false, false};
-#pragma unroll
-  for (int j = 0; j < 16; ++j) out[j] = VecT<TA, V>(TA(-0.0));
-  const gbl<const TP>* base = src + idx * 49 * src_batch + off;
-  VecT<TA, V> x[7];
-#pragma unroll
-  for (int r2 = 0; r2 < 7; ++r2) {
-    const VecT<TP, V> v = vload<TP, V>(base + r2 * src_batch);
-#pragma unroll
-    for (int e = 0; e < V; ++e) x[r2][e] = (TA)v[e];
-  }
-#pragma unroll 1
-  for (int r1 = 0; r1 < 7; ++r1) {
-    VecT<TP, V> xn[7];
-    if (r1 + 1 < 7) {
-#pragma unroll
-      for (int r2 = 0; r2 < 7; ++r2) xn[r2] = vload<TP, V>(base + ((r1 + 1) * 7 + r2) * src_batch);
-    }
-    VecT<TA, V> p2[4];
-#pragma unroll
-    for (int ij2 = 0; ij2 < 4; ++ij2) {
-      const int b = sw_block<PR0, PC0>(ij2);
-      p2[ij2] = c2[ij2][0] * x[kStrassenWNz[b][0]];
-#pragma unroll
-      for (int n = 1; n < 4; ++n)
-        if (n < kStrassenWNzCount[b]) p2[ij2] = p2[ij2] + c2[ij2][n] * x[kStrassenWNz[b][n]];
-    }
-#pragma unroll
-    for (int ij1 = 0; ij1 < 4; ++ij1) {
-      const TA c = coef_u<TA, NS, 1>(lev, ct, ij1, r1);
-      if (c != TA(0)) {
-        __asm__ volatile("");  // a uniform branch, not four selects per term
-#pragma unroll
-        for (int ij2 = 0; ij2 < 4; ++ij2) out[ij1 * 4 + ij2] = out[ij1 * 4 + ij2] + c * p2[ij2];
-        any1[ij1] = true;
-      }
-    }
-#pragma unroll
-    for (int r2 = 0; r2 < 7; ++r2)
-#pragma unroll
-      for (int e = 0; e < V; ++e) x[r2][e] = (TA)xn[r2][e];
-  }
-#pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (!any1[j / 4]) out[j] = VecT<TA, V>(TA(0));
 }
 
 // The top level of a three-level group with Strassen's pattern for the 8
@@ -690,13 +745,13 @@ __global__ __launch_bounds__(512) void k_scatter3(ScatterParams p) {
         const gbl<const TP>* s0 = src;
         const int64_t pr = o * R + w;
         if (sw2 == 0)
-          scatter3_lower_sw<TP, TA, V, NS, 0, 0>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+          scatter2_sw<TP, TA, V, NS, 1, 0, 0>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
         else if (sw2 == 1)
-          scatter3_lower_sw<TP, TA, V, NS, 0, 1>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+          scatter2_sw<TP, TA, V, NS, 1, 0, 1>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
         else if (sw2 == 2)
-          scatter3_lower_sw<TP, TA, V, NS, 1, 0>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+          scatter2_sw<TP, TA, V, NS, 1, 1, 0>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
         else if (sw2 == 3)
-          scatter3_lower_sw<TP, TA, V, NS, 1, 1>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
+          scatter2_sw<TP, TA, V, NS, 1, 1, 1>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
         else
           scatter_level<TP, TA, V, NL, BR, BC, R, NS, 1>(src, p.src_batch, pos, p.lev, ct, pr, sub);
       } else {
