@@ -280,6 +280,49 @@ __device__ __forceinline__ void gather_level(const VecT<T, V>* v, const SideLeve
   }
 }
 
+// Gathers over levels whose U (A side, KIND 0) or V (B side, KIND 1) table has
+// Strassen's pattern (SideLevel::strassen).  Every product then sums at most two
+// blocks, and the sum of two terms does not depend on their order (IEEE
+// addition commutes, signed zeros included), so the walk can take the blocks in
+// table-block order: the thread loads the source sub-block (k, l) that table
+// block b = (pr[k], pc[l]) reads into slot b (b a digit per level), and the
+// blocks that feed each product are known at compile time.  v: NSRC values,
+// table block b of level LT at (b * SUB) + j.  The roundings are those of
+// gather_level (fl(c x), then one addition).
+template <typename T, int V, int NL, int NS, int KIND, int LT, typename Emit>
+__device__ __forceinline__ void gather_level_sw(const VecT<T, V>* v, const SideLevel* lev, const T* ct,
+                                                const int8_t (*kof)[4], const int8_t (*lof)[4], int64_t idx,
+                                                const Emit& emit) {
+  if constexpr (LT == NL) {
+    emit(idx, v[0]);
+  } else {
+    constexpr int SUB = ipow(4, NL - LT - 1);
+    const SideLevel& L = lev[LT];
+#pragma unroll
+    for (int r = 0; r < 7; ++r) {
+      const int b1 = KIND == 0 ? kStrassenUNz[r][0] : kStrassenVNz[r][0];
+      const int b2 = KIND == 0 ? kStrassenUNz[r][1] : kStrassenVNz[r][1];
+      auto c_of = [&](int b) -> T {
+        const int k = kof[LT][b], l = lof[LT][b];
+        if constexpr (LT < NS)
+          return ct[(LT * 4 + k * 2 + l) * 7 + r];
+        else
+          return coef<T, 2, true>(L, k, l, r, 7);
+      };
+      const T c1 = c_of(b1);
+      VecT<T, V> acc[SUB];
+#pragma unroll
+      for (int j = 0; j < SUB; ++j) acc[j] = c1 * v[b1 * SUB + j];
+      if (b2 >= 0) {
+        const T c2 = c_of(b2);
+#pragma unroll
+        for (int j = 0; j < SUB; ++j) acc[j] = acc[j] + c2 * v[b2 * SUB + j];
+      }
+      gather_level_sw<T, V, NL, NS, KIND, LT + 1>(acc, lev, ct, kof, lof, idx * 7 + r, emit);
+    }
+  }
+}
+
 // Outputs of one top block in a gather group (R == 0: the level's own count,
 // at most kMaxR for a single level).
 template <int NL, int R>
@@ -316,11 +359,24 @@ __device__ __forceinline__ void load_exponents(const GatherParams& p, int64_t in
   __syncthreads();
 }
 
+// Whether gather_block takes the walk specialized to Strassen's pattern where
+// the tables allow it (gather_level_sw).  It saves arithmetic but holds more
+// registers: f32 gathers of four positions per thread, bound by HBM already,
+// ran 10% slower with it (N = 4096, Q = 3: 49 -> 54 us a side), and the batch
+// engine's persistent kernel, whose registers are the union of every task,
+// spilled (it passes false).  Reduced-precision outputs gained: fp8c N = 4096,
+// Q = 4 212 -> 170 us a side, f16s Q = 2 61 -> 54 us, bf16x3 N = 3072 79 -> 71 us;
+// f64 81 -> 73 us; f32 with one position per thread (N = 1000) 17 -> 14 us.
+template <typename T, int OUTF, int V>
+constexpr bool gather_sw_default() {
+  return !(OUTF == OUT_SAME && sizeof(T) == 4 && V == 4);
+}
+
 // One workgroup's share of a gather: 256 threads x V positions (block bx of
 // the position range) of top block `in`.  Used by k_gather and by the batch
-// engine's persistent kernel.  exps: for f16s outputs, top block `in`'s
-// exponents in LDS (load_exponents).
-template <typename T, int OUTF, int V, int NL, int BR, int BC, int R>
+// engine's kernels.  exps: for f16s outputs, top block `in`'s exponents in LDS
+// (load_exponents).  SW: see gather_sw_default.
+template <typename T, int OUTF, int V, int NL, int BR, int BC, int R, bool SW = gather_sw_default<T, OUTF, V>()>
 __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct, int64_t bx, int64_t in,
                                              const int32_t* exps) {
   constexpr int BB = BR * BC;
@@ -330,6 +386,22 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct,
   if (pos >= npos) return;
   const int64_t y = pos / p.cols_bot, x = pos - y * p.cols_bot;  // cols_bot % V == 0
   const gbl<const T>* src = global_ptr(static_cast<const T*>(p.src)) + in * p.src_batch;
+  // Strassen's pattern at every level of a group of one or two levels: slot s
+  // holds the source sub-block that table block s (digit per level) reads
+  bool sw = false;
+  int8_t kof[kMaxGroupLevels][4] = {}, lof[kMaxGroupLevels][4] = {};
+  if constexpr (SW && BR == 2 && BC == 2 && R == 7 && NL <= 2 && NL >= 1) {
+    sw = true;
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      sw = sw && p.lev[t].strassen != 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        kof[t][b] = p.lev[t].pr[0] == (b >> 1) ? 0 : 1;
+        lof[t][b] = p.lev[t].pc[0] == (b & 1) ? 0 : 1;
+      }
+    }
+  }
   VecT<T, V> v[NSRC];
 #pragma unroll
   for (int s = 0; s < NSRC; ++s) {
@@ -339,8 +411,10 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct,
     for (int t = 0; t < NL; ++t) {  // least significant digit = deepest level
       const int d = rem % BB;
       rem /= BB;
-      row += (d / BC) * hs;
-      col += (d % BC) * ws;
+      const int lt = NL - 1 - t;
+      const int kr = sw ? kof[lt][d] : d / BC, lc = sw ? lof[lt][d] : d % BC;
+      row += kr * hs;
+      col += lc * ws;
       hs *= BR;
       ws *= BC;
     }
@@ -354,7 +428,17 @@ __device__ __forceinline__ void gather_block(const GatherParams& p, const T* ct,
   }
   const int64_t n_out = R ? ipow(R, NL) : p.lev[0].R;
   GatherEmit<T, OUTF, V> e{p.dst, p.dst_batch, p.plane, pos, exps, in * n_out, p.nt_store != 0};
-  gather_level<T, V, NL, BR, BC, R, gather_staged<T, OUTF, NL, R>(), gather_rolled<OUTF>(), 0>(v, p.lev, ct, in, e);
+  constexpr int NS = gather_staged<T, OUTF, NL, R>();
+  if constexpr (SW && BR == 2 && BC == 2 && R == 7 && NL <= 2 && NL >= 1) {
+    if (sw) {
+      if (p.side == 0)
+        gather_level_sw<T, V, NL, NS, 0, 0>(v, p.lev, ct, kof, lof, in, e);
+      else
+        gather_level_sw<T, V, NL, NS, 1, 0>(v, p.lev, ct, kof, lof, in, e);
+      return;
+    }
+  }
+  gather_level<T, V, NL, BR, BC, R, NS, gather_rolled<OUTF>(), 0>(v, p.lev, ct, in, e);
 }
 
 // One side's share of a gather launch.
@@ -437,7 +521,7 @@ __device__ __forceinline__ void scatter_level(const gbl<const TP>* src, int64_t 
 }
 
 // Scatters over levels whose W table has Strassen's zero pattern
-// (SideLevel::w_strassen).  Output block ij of such a level reads table block
+// (SideLevel::strassen).  Output block ij of such a level reads table block
 // b = (pr[k] * 2 + pc[l]) for (k, l) = (ij / 2, ij % 2); with the level's row
 // and column permutations fixed (pr[0] = PR0, pc[0] = PC0) b is a compile-time
 // function of ij, and so are the products that feed it (kStrassenWNz[b]), so
@@ -595,7 +679,7 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, const TA* 
   int sw = -1;
   if constexpr (BR == 2 && BC == 2 && R == 7 && (NL == 1 || NL == 2)) {
     const SideLevel& D = p.lev[NL - 1];
-    if (D.w_strassen) sw = D.pr[0] * 2 + D.pc[0];
+    if (D.strassen) sw = D.pr[0] * 2 + D.pc[0];
   }
   if constexpr (BR == 2 && BC == 2 && R == 7 && NL == 2) {
     if (sw == 0)
@@ -699,8 +783,8 @@ __global__ __launch_bounds__(512) void k_scatter3(ScatterParams p) {
   const gbl<const TP>* src = global_ptr(static_cast<const TP*>(p.src));
   // Strassen's pattern in the top level's table; in the deepest level's, the
   // case (pr[0], pc[0]) of its specialized walk (-1: the general walk)
-  const bool sw0 = p.lev[0].w_strassen != 0;
-  const int sw2 = p.lev[2].w_strassen ? p.lev[2].pr[0] * 2 + p.lev[2].pc[0] : -1;
+  const bool sw0 = p.lev[0].strassen != 0;
+  const int sw2 = p.lev[2].strassen ? p.lev[2].pr[0] * 2 + p.lev[2].pc[0] : -1;
   for (int64_t t = 0; t <= mine; ++t) {
     if (t > 0) {
       const int64_t task = blockIdx.x + (t - 1) * gridDim.x;

@@ -56,7 +56,7 @@ struct SideLevel {
   int8_t pr[kMaxB], pc[kMaxB];
   int8_t sr[kMaxB], sc[kMaxB];
   int32_t R;
-  int32_t w_strassen;  // C side: the table's nonzero entries are those of kStrassenWNz
+  int32_t strassen;  // the table's nonzero entries are Strassen's: kStrassenUNz (A side), kStrassenVNz (B), kStrassenWNz (C)
   const void* tab;  // device table of this side (f64 or f32, see Plan)
 };
 
@@ -66,6 +66,12 @@ struct SideLevel {
 // over tables with exactly this pattern skip the zero terms at compile time.
 constexpr int kStrassenWNz[4][4] = {{0, 3, 4, 6}, {2, 4, -1, -1}, {1, 3, -1, -1}, {0, 1, 2, 5}};
 constexpr int kStrassenWNzCount[4] = {4, 2, 2, 4};
+// Nonzero blocks (11, 12, 21, 22) of each product in the same form's U and V:
+// P1 = (A11 + A22)(B11 + B22), P2 = (A21 + A22) B11, P3 = A11 (B12 - B22),
+// P4 = A22 (B21 - B11), P5 = (A11 + A12) B22, P6 = (A21 - A11)(B11 + B12),
+// P7 = (A12 - A22)(B21 + B22); at most two, padded with -1.
+constexpr int kStrassenUNz[7][2] = {{0, 3}, {2, 3}, {0, -1}, {3, -1}, {0, 1}, {0, 2}, {1, 3}};
+constexpr int kStrassenVNz[7][2] = {{0, 3}, {0, -1}, {1, 3}, {0, 2}, {3, -1}, {0, 1}, {2, 3}};
 
 // Consecutive levels that one kernel pass fuses.  All levels of a group share
 // the block shape <b1, b2, b3>.  "top" blocks enter the group from above (the

@@ -44,6 +44,7 @@ struct GatherParams {
   // fp8c at Q = 4, whose first group feeds the second, was 1.4% slower with
   // ordinary stores there.
   int32_t nt_store;
+  int32_t side;        // 0: A (U tables), 1: B (V tables)
   SideLevel lev[kMaxGroupLevels];
 };
 

@@ -123,19 +123,27 @@ void fill_side(const Plan& p, const Draws& dr, int level, Side side, bool f64, b
   for (int j = 0; j < nc; ++j) L.pc[j] = (int8_t)pc[j], L.sc[j] = (int8_t)sc[j];
   L.R = s.R;
   L.tab = table(p, level, kind, f64);
-  if (side == SIDE_C && s.b1 == 2 && s.b3 == 2 && s.R == 7) {
-    // the table the kernels read, in their precision
+  if (s.b1 == 2 && s.b2 == 2 && s.b3 == 2 && s.R == 7) {
+    // the table the kernels read, in their precision, against Strassen's pattern
     const LevelTables& t = p.tables[level];
     bool same = true;
     for (int b = 0; b < 4 && same; ++b)
       for (int r = 0; r < 7 && same; ++r) {
         bool listed = false;
-        for (int n = 0; n < kStrassenWNzCount[b]; ++n) listed = listed || kStrassenWNz[b][n] == r;
+        if (side == SIDE_C) {
+          for (int n = 0; n < kStrassenWNzCount[b]; ++n) listed = listed || kStrassenWNz[b][n] == r;
+        } else {
+          const int* nz = side == SIDE_A ? kStrassenUNz[r] : kStrassenVNz[r];
+          listed = nz[0] == b || nz[1] == b;
+        }
         const size_t i = (size_t)b * 7 + r;
-        const double v = f64 ? (kappa_scale ? t.Wk[i] : t.W[i]) : (double)(kappa_scale ? t.Wkf[i] : t.Wf[i]);
+        double v;
+        if (side == SIDE_A) v = f64 ? t.U[i] : (double)t.Uf[i];
+        else if (side == SIDE_B) v = f64 ? t.V[i] : (double)t.Vf[i];
+        else v = f64 ? (kappa_scale ? t.Wk[i] : t.W[i]) : (double)(kappa_scale ? t.Wkf[i] : t.Wf[i]);
         same = (v != 0.0) == listed;
       }
-    L.w_strassen = same ? 1 : 0;
+    L.strassen = same ? 1 : 0;
   }
 }
 
@@ -219,6 +227,7 @@ void build_gather(const Plan& p, const Draws& dr, int which, const void* X, int6
     gp.dst_batch = gp.rows_bot * gp.cols_bot;
     gp.n_in = g.n_in;
     gp.nt_store = gi + 1 < groups.size() ? 1 : 0;
+    gp.side = which;
     const bool bf16_out = last && p.prec == RBC_PREC_BF16X3;
     const bool f16_out = last && p.prec == RBC_PREC_F16S;
     const bool fp8_out = last && p.prec == RBC_PREC_FP8C;
