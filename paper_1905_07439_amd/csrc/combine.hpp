@@ -362,11 +362,11 @@ __device__ __forceinline__ void load_exponents(const GatherParams& p, int64_t in
 // Whether gather_block takes the walk specialized to Strassen's pattern where
 // the tables allow it (gather_level_sw).  It saves arithmetic but holds more
 // registers: f32 gathers of four positions per thread, bound by HBM already,
-// ran 10% slower with it (N = 4096, Q = 3: 49 -> 54 us a side), and the batch
-// engine's persistent kernel, whose registers are the union of every task,
-// spilled (it passes false).  Reduced-precision outputs gained: fp8c N = 4096,
-// Q = 4 212 -> 170 us a side, f16s Q = 2 61 -> 54 us, bf16x3 N = 3072 79 -> 71 us;
-// f64 81 -> 73 us; f32 with one position per thread (N = 1000) 17 -> 14 us.
+// ran 10% slower with it (N = 4096, Q = 3: 49 -> 54 us a side).  Reduced-
+// precision outputs gained: fp8c N = 4096, Q = 4 212 -> 170 us a side, f16s
+// Q = 2 61 -> 54 us, bf16x3 N = 3072 79 -> 71 us; f64 81 -> 73 us; f32 with
+// one position per thread (N = 1000) 17 -> 14 us.  The batch engine's
+// persistent kernel chooses for itself (it takes the walk everywhere).
 template <typename T, int OUTF, int V>
 constexpr bool gather_sw_default() {
   return !(OUTF == OUT_SAME && sizeof(T) == 4 && V == 4);
