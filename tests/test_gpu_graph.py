@@ -27,6 +27,7 @@ def setup_module(module):
 
 CASES = [
     ("f32", ["strassen"] * 3, 2048),     # the leaf gather is on at this size
+    ("f32", ["strassen"] * 3, 4096),     # and the scatter is one pass over the three levels (k_scatter3)
     ("f32", ["laderman", "strassen"], 600),
     ("f64", ["strassen"] * 2, 64),
     ("f16s", ["strassen"] * 2, 1024),
