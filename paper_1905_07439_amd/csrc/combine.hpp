@@ -609,6 +609,72 @@ __device__ __forceinline__ void scatter2_sw(const gbl<const TP>* src, int64_t sr
     if (!any1[j / 4]) out[j] = VecT<TA, V>(TA(0));
 }
 
+// scatter2_sw with level LO's table of Strassen's pattern as well, its case
+// (pr[0], pc[0]) = (QR, QC) fixed: the products that feed each block of level
+// LO are known at compile time too (kStrassenWNz[sw_block<QR, QC>(ij1)]), so
+// the level-LO loop is unrolled and neither level forms a zero term or tests
+// a coefficient.  Every output has at least two terms; the first stands alone.
+template <typename TP, typename TA, int V, int NS, int LO, int PR0, int PC0, int QR, int QC>
+__device__ __forceinline__ void scatter2_sww(const gbl<const TP>* src, int64_t src_batch, int64_t off,
+                                             const SideLevel* lev, const TA* ct, int64_t idx, VecT<TA, V>* out) {
+  TA c2[4][4], c1[4][4];
+#pragma unroll
+  for (int ij = 0; ij < 4; ++ij) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int b2 = sw_block<PR0, PC0>(ij), b1 = sw_block<QR, QC>(ij);
+      c2[ij][n] = n < kStrassenWNzCount[b2] ? coef_u<TA, NS, LO + 1>(lev, ct, ij, kStrassenWNz[b2][n]) : TA(0);
+      c1[ij][n] = n < kStrassenWNzCount[b1] ? coef_u<TA, NS, LO>(lev, ct, ij, kStrassenWNz[b1][n]) : TA(0);
+    }
+  }
+  const gbl<const TP>* base = src + idx * 49 * src_batch + off;
+#pragma unroll
+  for (int r1 = 0; r1 < 7; ++r1) {
+    VecT<TA, V> x[7];
+#pragma unroll
+    for (int r2 = 0; r2 < 7; ++r2) {
+      const VecT<TP, V> v = vload<TP, V>(base + (r1 * 7 + r2) * src_batch);
+#pragma unroll
+      for (int e = 0; e < V; ++e) x[r2][e] = (TA)v[e];
+    }
+    VecT<TA, V> p2[4];
+#pragma unroll
+    for (int ij2 = 0; ij2 < 4; ++ij2) {
+      const int b = sw_block<PR0, PC0>(ij2);
+      p2[ij2] = c2[ij2][0] * x[kStrassenWNz[b][0]];
+#pragma unroll
+      for (int n = 1; n < 4; ++n)
+        if (n < kStrassenWNzCount[b]) p2[ij2] = p2[ij2] + c2[ij2][n] * x[kStrassenWNz[b][n]];
+    }
+#pragma unroll
+    for (int ij1 = 0; ij1 < 4; ++ij1) {
+      const int b = sw_block<QR, QC>(ij1);
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        if (n < kStrassenWNzCount[b] && kStrassenWNz[b][n] == r1) {
+#pragma unroll
+          for (int ij2 = 0; ij2 < 4; ++ij2) {
+            const VecT<TA, V> t = c1[ij1][n] * p2[ij2];
+            out[ij1 * 4 + ij2] = n == 0 ? t : out[ij1 * 4 + ij2] + t;
+          }
+        }
+    }
+  }
+}
+
+// Calls f with std::integral_constant<int, c> for a permutation case c in 0..3.
+template <typename F>
+__device__ __forceinline__ void sw_case(int c, F&& f) {
+  if (c == 0)
+    f(std::integral_constant<int, 0>());
+  else if (c == 1)
+    f(std::integral_constant<int, 1>());
+  else if (c == 2)
+    f(std::integral_constant<int, 2>());
+  else
+    f(std::integral_constant<int, 3>());
+}
+
 // The deepest level alone, with Strassen's pattern: out[ij] = block ij for
 // prefix idx, the products that feed it known at compile time (PR0, PC0 as
 // above), first term alone, r ascending.
@@ -682,7 +748,17 @@ __device__ __forceinline__ void scatter_block(const ScatterParams& p, const TA* 
     if (D.strassen) sw = D.pr[0] * 2 + D.pc[0];
   }
   if constexpr (BR == 2 && BC == 2 && R == 7 && NL == 2) {
-    if (sw == 0)
+    const int sw0 = p.lev[0].strassen ? p.lev[0].pr[0] * 2 + p.lev[0].pc[0] : -1;
+    if (sw >= 0 && sw0 >= 0)
+      sw_case(sw, [&](auto k1) {
+        constexpr int c1 = decltype(k1)::value;
+        sw_case(sw0, [&](auto k0) {
+          constexpr int c0 = decltype(k0)::value;
+          scatter2_sww<TP, TA, V, NS, 0, (c1 >> 1), (c1 & 1), (c0 >> 1), (c0 & 1)>(src, p.src_batch, pos, p.lev, ct,
+                                                                                   o, out);
+        });
+      });
+    else if (sw == 0)
       scatter2_sw<TP, TA, V, NS, 0, 0, 0>(src, p.src_batch, pos, p.lev, ct, o, out);
     else if (sw == 1)
       scatter2_sw<TP, TA, V, NS, 0, 0, 1>(src, p.src_batch, pos, p.lev, ct, o, out);
@@ -784,6 +860,7 @@ __global__ __launch_bounds__(512) void k_scatter3(ScatterParams p) {
   // Strassen's pattern in the top level's table; in the deepest level's, the
   // case (pr[0], pc[0]) of its specialized walk (-1: the general walk)
   const bool sw0 = p.lev[0].strassen != 0;
+  const int sw1 = p.lev[1].strassen ? p.lev[1].pr[0] * 2 + p.lev[1].pc[0] : -1;
   const int sw2 = p.lev[2].strassen ? p.lev[2].pr[0] * 2 + p.lev[2].pc[0] : -1;
   for (int64_t t = 0; t <= mine; ++t) {
     if (t > 0) {
@@ -828,7 +905,16 @@ __global__ __launch_bounds__(512) void k_scatter3(ScatterParams p) {
       if (pos < npos) {
         const gbl<const TP>* s0 = src;
         const int64_t pr = o * R + w;
-        if (sw2 == 0)
+        if (sw2 >= 0 && sw1 >= 0) {
+          sw_case(sw2, [&](auto k2) {
+            constexpr int c2 = decltype(k2)::value;
+            sw_case(sw1, [&](auto k1) {
+              constexpr int c1 = decltype(k1)::value;
+              scatter2_sww<TP, TA, V, NS, 1, (c2 >> 1), (c2 & 1), (c1 >> 1), (c1 & 1)>(s0, p.src_batch, pos, p.lev,
+                                                                                      ct, pr, sub);
+            });
+          });
+        } else if (sw2 == 0)
           scatter2_sw<TP, TA, V, NS, 1, 0, 0>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
         else if (sw2 == 1)
           scatter2_sw<TP, TA, V, NS, 1, 0, 1>(s0, p.src_batch, pos, p.lev, ct, pr, sub);
