@@ -841,8 +841,9 @@ __device__ __forceinline__ void scatter3_top_sw(const SideLevel* lev, const TA* 
 // levels [1, 3), then level 0) 143 us; one thread holding all 64 outputs of a
 // position, about 100 values in registers, 124-132 us; this kernel with the
 // general walk 122-131 us, with only loads in the walk 80 us (the walk's
-// selects and multiplies bound it, not the memory), and with the walks
-// specialized to Strassen's pattern 94 us.
+// selects and multiplies bound it, not the memory), with the deepest level's
+// walk specialized to Strassen's pattern 94 us, and with the middle level's as
+// well (scatter2_sww) 83 us.
 template <typename TP, typename TA, typename TO, int V>
 __global__ __launch_bounds__(512) void k_scatter3(ScatterParams p) {
   constexpr int NL = 3, BR = 2, BC = 2, R = 7, SUB = 16;
