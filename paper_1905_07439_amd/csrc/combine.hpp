@@ -834,8 +834,8 @@ __device__ __forceinline__ void scatter3_top_sw(const SideLevel* lev, const TA* 
 // 8 output sub-blocks 8 w .. 8 w + 7 (top block w / 2, so the coefficients are
 // uniform) over ascending r and stores them; then wavefront w < 7 forms, for
 // task t and the top level's product w, the 16 sub-block values of the two
-// lower levels (scatter_level: the walk and order of one thread of k_scatter)
-// and leaves them in LDS.  One barrier per step.  Every output is the same
+// lower levels (the walk and order of one thread of k_scatter, specialized
+// where the tables have Strassen's pattern) and leaves them in LDS.  One barrier per step.  Every output is the same
 // sequence of roundings as in k_scatter, so the bits are the same.  Measured
 // on the f32 scatter of N = 4096, Q = 3 (one box): two passes (k_scatter over
 // levels [1, 3), then level 0) 143 us; one thread holding all 64 outputs of a
@@ -858,8 +858,8 @@ __global__ __launch_bounds__(512) void k_scatter3(ScatterParams p) {
   const int64_t ntask = nblk * p.n_out;
   const int64_t mine = blockIdx.x < ntask ? (ntask - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const gbl<const TP>* src = global_ptr(static_cast<const TP*>(p.src));
-  // Strassen's pattern in the top level's table; in the deepest level's, the
-  // case (pr[0], pc[0]) of its specialized walk (-1: the general walk)
+  // Strassen's pattern in the top level's table; in the middle and deepest
+  // levels', the case (pr[0], pc[0]) of their specialized walks (-1: none)
   const bool sw0 = p.lev[0].strassen != 0;
   const int sw1 = p.lev[1].strassen ? p.lev[1].pr[0] * 2 + p.lev[1].pc[0] : -1;
   const int sw2 = p.lev[2].strassen ? p.lev[2].pr[0] * 2 + p.lev[2].pc[0] : -1;
