@@ -62,7 +62,8 @@ static bool same_shape(const Scheme& a, const Scheme& b) {
 // Q = 2: 977 vs 1054 us; Q = 3 at N = 2048: 203 vs 231 us).  RBC_MAX_FUSED_LEVELS set
 // in the environment overrides the rule.
 static bool enough_work(const Plan& p, int d, int g_d1) {
-  if (p.fuse_max || std::getenv("RBC_MAX_FUSED_LEVELS")) return true;
+  const char* env = std::getenv("RBC_MAX_FUSED_LEVELS");
+  if (p.fuse_max || (env && *env)) return true;
   double n_in = 1, a = (double)p.mM * p.mK, b = (double)p.mK * p.mN;
   for (int e = 0; e < d; ++e) n_in *= p.levels[e].R;
   for (int e = g_d1; e < p.Q; ++e) {
