@@ -117,7 +117,7 @@ hipError_t launch_lowp(const uint16_t* S, const uint16_t* T, float* P, int64_t m
   bool wide = false;
   if constexpr (KIND == tiles::LOWP_F16S) {
     if ((wide = tile == 128 && m % 256 == 0 && n % 256 == 0))
-      launch_wide<KIND, 256, 256, 4, 4, 4, 4>(stream, S, T, P, m, n, k, batch, eS, eT);
+      launch_wide<KIND, 256, 256, 2, 4, 2, 4>(stream, S, T, P, m, n, k, batch, eS, eT);
   } else {
     if ((wide = tile == 128 && n % 256 == 0))
       launch_wide<KIND, 128, 256, 4, 2, 2, 4>(stream, S, T, P, m, n, k, batch, eS, eT);

@@ -194,7 +194,10 @@ __device__ __forceinline__ void gemm_lowp_tile(const uint16_t* __restrict__ S,
 // so the same bits; larger tiles read fewer operand bytes per flop from L2 (49 f16s
 // leaves of 1024^3: 128 x 128 on 4 wavefronts 181 us, 256 x 128 on 8 162 us, 256 x 256
 // on 16 154 us; bf16x3, 10 leaves of 1024 x 1536^2: 128 x 256 on 8 wavefronts 173 us
-// against 177 us).
+// against 177 us).  Larger wavefront blocks read fewer LDS bytes per flop but gain
+// little: f16s 256 x 256 on 2 x 4 wavefronts (128 x 64 each, 188 VGPRs) 149.7 us
+// against 153.0 on 4 x 4, 128 x 128 each 165 us (spills); bf16x3 on 64 x 128 or
+// 128 x 64 per wavefront (one wavefront per SIMD) 219-227 us against 185.
 template <int KIND, int BM, int BN, int NWM, int NWN>
 struct LowpTileW {
   static constexpr int NP = KIND == LOWP_BF16X3 ? 2 : 1, BK = 32, LDK = BK + 8, LDB = BN + 16;
