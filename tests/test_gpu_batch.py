@@ -5,7 +5,8 @@ by Plan.matmul (the stand-alone path, itself checked against the oracle in
 test_gpu_parity): the batch runs the same arithmetic in the same order.
 Exact schemes on small integers must also give the exact product, which
 checks the batch against the plain definition independently of the
-stand-alone path.
+stand-alone path, and the reduced-precision products stay within the stated
+multiple of the oracle's emulation error.
 """
 
 import sys
@@ -16,6 +17,9 @@ import torch
 
 import paper_1905_07439_amd as rbc
 import workloads
+from oracle import precision, recursion
+
+from test_gpu_parity import _level_draws, _schemes as _oracle_schemes
 
 pytestmark = pytest.mark.gpu
 
@@ -106,6 +110,52 @@ def test_batch_equals_alone_bitwise(prec, specs, engine):
         _say("  n=%d seed=%d mode=%s" % (A.shape[0], seed, mode))
         assert torch.isfinite(C).all()
         assert torch.equal(C, R), (A.shape[0], seed, mode, (C - R).abs().max().item())
+
+
+def _emulation(prec, A, B, ref_s, dr, dims, kappa_scale):
+    """The oracle's emulation of one reduced-precision product: f32 combinations, the
+    per-leaf power-of-two scales, f16 leaves (f16s) or e4m3 hi + lo leaves with one
+    correction product (fp8c) multiplied exactly, then the f32 recombination."""
+    M, N, K = A.shape[0], B.shape[1], A.shape[1]
+    ops = recursion.leaf_operands(A, B, ref_s, dr, kappa_scale=kappa_scale, arith="f32", leaf_dims=dims)
+    gA, gB = precision.path_norms(ref_s, "A"), precision.path_norms(ref_s, "B")
+    mA, mB = float(np.max(np.abs(A))), float(np.max(np.abs(B)))
+    prods = []
+    for l, (S, T) in enumerate(ops):
+        if prec == "f16s":
+            eA, eB = precision.leaf_exponent(mA, gA[l]), precision.leaf_exponent(mB, gB[l])
+            S16 = np.ldexp(S, eA).astype(np.float16).astype(np.float64)
+            T16 = np.ldexp(T, eB).astype(np.float16).astype(np.float64)
+            prods.append(np.ldexp(S16 @ T16, -(eA + eB)).astype(np.float32))
+        else:
+            eA = precision.leaf_exponent(mA, gA[l], target=448.0)
+            eB = precision.leaf_exponent(mB, gB[l], target=448.0)
+            sh, sl = precision.split_e4m3_scaled(np.ldexp(S.astype(np.float64), eA))
+            th, tl = precision.split_e4m3_scaled(np.ldexp(T.astype(np.float64), eB))
+            prods.append(np.ldexp(sh @ th + (sh @ tl + sl @ th) / 16.0, -(eA + eB)).astype(np.float32))
+    return recursion.combine(prods, M, N, K, ref_s, dr, kappa_scale=kappa_scale, arith="f32", leaf_dims=dims)
+
+
+@pytest.mark.parametrize("prec,specs", [("f16s", F16S_SPECS[:3]), ("fp8c", FP8C_SPECS[:4])])
+def test_batch_errors_within_emulation(prec, specs):
+    # The stated gates of the batched (f16 leaves) and served (e4m3 leaves) configurations:
+    # each product's relative Frobenius error against A B at most 4x that of the oracle's
+    # emulation of the same precision, on the same draws, for inputs of the batched
+    # configuration's recipe (N(0,1) times 10^U(-3,3) per matrix).
+    b, items = _build(prec, specs, "gauss")
+    b.prepare()
+    b.launch()
+    b.check()
+    for (plan, A, B, seed, mode, C), (names, n) in zip(items, specs):
+        _, ref_s = _oracle_schemes(list(names))
+        _, _, dr = _level_draws(plan, ref_s, seed, mode)
+        info = plan.info
+        An, Bn = A.cpu().numpy(), B.cpu().numpy()
+        emu = _emulation(prec, An, Bn, ref_s, dr, (info["mM"], info["mK"], info["mN"]), mode != "none")
+        AB = An.astype(np.float64) @ Bn.astype(np.float64)
+        e, e_emu = recursion.rel_err(C.cpu().numpy(), AB), recursion.rel_err(emu, AB)
+        _say("  %s n=%d %s seed=%d mode=%s: rel err %.3g, emulation %.3g" % (prec, n, names, seed, mode, e, e_emu))
+        assert e <= 4 * e_emu, (n, names, seed, mode, e, e_emu)
 
 
 def test_batch_f32_integers_exact():
