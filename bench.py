@@ -232,7 +232,9 @@ def small64_stats(reps, warmup):
     """The small case: plain randomized Strassen in f64, N = 64, two levels (49 leaves of 16^3),
     A, B ~ N(0,1) (seeds 1001/1002) and integers in [-4, 4] (seed 1003 for A, 1004 for B),
     algorithm seed 0, mode full.  Launch-latency bound: per-call latency (HIP events around
-    each call) over `reps` calls, p50 and p99 in microseconds."""
+    each call) over `reps` calls, p50 and p99 in microseconds, beside the device's own time per
+    product (a captured graph of 20 products replayed; the eager call is bound by the host's
+    kernel-launch cost)."""
     import numpy as np
     import torch
 
@@ -264,8 +266,31 @@ def small64_stats(reps, warmup):
     err = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
     Ci = plan.matmul(Ai, Bi, seed=0, workspace=ws)
     exact = bool(torch.equal(Ci, Ai @ Bi))
+    # The device's own time per product: 20 products captured in a graph and replayed,
+    # so that no host issue time separates the launches (the eager call is host-bound).
+    C_eager = C.clone()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs):
+        for _ in range(20):
+            plan.matmul(A, B, C=C, seed=0, workspace=ws, stream=gs)
+    C.zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    replay_same = bool(torch.equal(C, C_eager))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(50):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    replay_same = replay_same and bool(torch.equal(C, C_eager))
+    device_us = e0.elapsed_time(e1) * 1e3 / (50 * 20)
     return {"p50_us": round(p50, 2), "p99_us": round(float(np.percentile(lat, 99)), 2),
             "min_us": round(float(lat.min()), 2), "reps": reps,
+            "device_us_per_product_graph": round(device_us, 2), "graph_replay_bitwise_equal": replay_same,
             "tflops_at_p50": round(2.0 * n ** 3 / (p50 * 1e-6) / 1e12, 6),
             "rel_err_vs_fp64": err, "integers_exact": exact}
 
@@ -279,7 +304,9 @@ def small64(args):
            "config": {"workload": "randomized Strassen, f64, N=64, 2 levels (49 leaves of 16^3), N(0,1) and "
                                   "integers in [-4,4], algorithm seed 0, mode full", "n": 64, "levels": 2,
                       "parallelism": "single GPU"},
-           "latency_us": {"p50": st["p50_us"], "p99": st["p99_us"], "min": st["min_us"]},
+           "latency_us": {"p50": st["p50_us"], "p99": st["p99_us"], "min": st["min_us"],
+                          "device_per_product_graph": st["device_us_per_product_graph"]},
+           "graph_replay_bitwise_equal": st["graph_replay_bitwise_equal"],
            "rel_err_vs_fp64": st["rel_err_vs_fp64"], "integers_exact": st["integers_exact"]}
     print(json.dumps(out), flush=True)
 
